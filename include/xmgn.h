@@ -1,0 +1,216 @@
+/*
+ * xmgn.h -- C ABI of the MI355X (gfx950) X-MeshGraphNet processor library.
+ *
+ * The library builds multi-scale kNN graphs from point clouds, splits them
+ * into partitions with an L-hop halo, and runs the MeshGraphNet
+ * encoder / processor / decoder forward and its hand-written adjoint over a
+ * batch of partitions on one GPU, with gradients aggregated over partitions.
+ *
+ * Conventions (every call):
+ *  - Return XMGN_OK (0) or a negative XMGN_ERR_* code; xmgn_last_error()
+ *    then describes the failure.  No C++ exception crosses this boundary.
+ *  - "dev" pointers are HIP device memory, "host" pointers host memory.  All
+ *    arrays are dense and row-major.  The caller owns every buffer it passes;
+ *    the library never frees or keeps a caller pointer beyond the call.
+ *  - Handles (xmgn_ctx, xmgn_graph, xmgn_partset) are owned by the library and
+ *    released with the matching *_destroy call.
+ *  - Device work is enqueued asynchronously on the given stream (a
+ *    hipStream_t; NULL = the null stream).  Only xmgn_build_knn synchronises
+ *    (it needs the edge count).  Arguments are validated on the host before
+ *    any device work, so invalid input never reaches a kernel.
+ *  - Node and edge indices are int32: n < 2^31 and E < 2^31 per graph/batch.
+ *  - Results are deterministic: no floating-point atomics are used, and the
+ *    same inputs on the same device give bitwise identical outputs.
+ */
+#ifndef XMGN_H
+#define XMGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t xmgn_status;
+#define XMGN_OK 0
+#define XMGN_ERR_INVALID (-1)     /* bad argument or inconsistent sizes */
+#define XMGN_ERR_OOM (-2)         /* device or host allocation failed */
+#define XMGN_ERR_HIP (-3)         /* a HIP runtime call failed */
+#define XMGN_ERR_CAPACITY (-4)    /* a caller buffer is too small */
+#define XMGN_ERR_UNSUPPORTED (-5) /* hidden width / device not supported */
+#define XMGN_ERR_STATE (-6)       /* call order violated (e.g. backward first) */
+
+typedef void* xmgn_stream; /* hipStream_t */
+
+typedef struct xmgn_ctx xmgn_ctx;         /* device context: workspace, tape */
+typedef struct xmgn_graph xmgn_graph;     /* receiver-sorted CSR graph */
+typedef struct xmgn_partset xmgn_partset; /* partitions with halos */
+
+/* Message of the last failing call on this thread (never NULL). */
+const char* xmgn_last_error(void);
+/* Library version string. */
+const char* xmgn_version(void);
+
+/*
+ * Model description.  Architecture (MeshGraphNet, Sec. II; X-MeshGraphNet
+ * Sec. III.D):
+ *   node encoder  node_in -> H -> H -> H, then LayerNorm
+ *   edge encoder  edge_in -> H -> H -> H, then LayerNorm; the edge input is
+ *                 [x_s - x_r, |x_s - x_r|] (Sec. II.E) normalised by a
+ *                 caller-given affine
+ *   n_layers processor layers (Eq. 1-4): per edge k = (s -> r)
+ *       v_k = LN(W2e act(W1e [h_r; h_s; e_k] + b1e) + b2e),  e'_k = e_k + v_k
+ *       m_r = sum of v_k over the in-edges of r (aggregate 0) or of e'_k
+ *             (aggregate 1), added in ascending sender order
+ *       h'_r = h_r + LN(W2n act(W1n [h_r; m_r] + b1n) + b2n)
+ *   decoder H -> H -> H -> out_dim, no LayerNorm.
+ *   LN(u) = gamma (u - mean) / sqrt(var + ln_eps) + beta, biased variance.
+ */
+typedef struct {
+  int32_t hidden;     /* H: 128 or 256 */
+  int32_t n_layers;   /* processor layers L >= 1 */
+  int32_t node_in;    /* node input width, 1..8 (6 = position + normal) */
+  int32_t edge_in;    /* must be 4 */
+  int32_t out_dim;    /* decoder outputs, 1..16 */
+  int32_t activation; /* 0 = ReLU, 1 = SiLU */
+  int32_t precision;  /* 0 = plain FP32 (FP32 storage, FP32 MFMA),
+                         1 = BF16 storage and MFMA operands, FP32 accumulate,
+                             FP32 LayerNorm statistics, segment sums and
+                             gradient accumulation */
+  int32_t aggregate;  /* 0 = sum of messages v, 1 = sum of updated edges e' */
+  float ln_eps;       /* LayerNorm epsilon, e.g. 1e-5 */
+} xmgn_model_desc;
+
+/*
+ * Parameter blob: FP32, flat, in this order, every W stored [out][in]:
+ *   block 0 node encoder: W1[H][node_in] b1[H] W2[H][H] b2[H] W3[H][H] b3[H] gamma[H] beta[H]
+ *   block 1 edge encoder: W1[H][edge_in] b1 W2 b2 W3 b3 gamma beta (as above)
+ *   per layer l = 0..L-1:
+ *     block 2 edge MLP:   W1[H][3H] b1[H] W2[H][H] b2[H] gamma[H] beta[H]
+ *     block 3 node MLP:   W1[H][2H] b1[H] W2[H][H] b2[H] gamma[H] beta[H]
+ *   block 4 decoder:      W1[H][H] b1[H] W2[H][H] b2[H] W3[out][H] b3[out]
+ * xmgn_param_count gives the total; xmgn_param_offset the start of tensor
+ * `tensor` (0-based, in the order above) of `block` (layer ignored for
+ * blocks 0, 1, 4).
+ */
+xmgn_status xmgn_param_count(const xmgn_model_desc* desc, int64_t* count);
+xmgn_status xmgn_param_offset(const xmgn_model_desc* desc, int32_t block, int32_t layer,
+                              int32_t tensor, int64_t* offset);
+
+/* Context on HIP device `device` (must be gfx950). */
+xmgn_status xmgn_ctx_create(int32_t device, xmgn_ctx** out);
+void xmgn_ctx_destroy(xmgn_ctx* ctx);
+
+/* Tile configuration of the processor kernels (rows per tile 32 or 64,
+ * 0 = library default) and the persistent grid size in workgroups
+ * (0 = library default).  Changing it invalidates cached batch plans. */
+xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int32_t node_rows,
+                               int32_t grid);
+
+/*
+ * 1. Multi-scale kNN graph (Sec. III.B, III.C).
+ * pos: dev float32 [n][3].  Level l is the prefix [0, level_end[l]) of the
+ * points (level_end: host int32 [n_levels], strictly increasing, last == n).
+ * Every point of level l receives an edge from each of its k_intra nearest
+ * other points of level l, and (l >= 1) from each of its k_cross nearest
+ * points of level l-1.  Distances are squared Euclidean in FP64 from the
+ * FP32 coordinates, summed x, y, z in that order without fused
+ * multiply-add; equal distances rank the lower index first; the point itself
+ * is excluded by index.  Repeated (receiver, sender) pairs are kept once and
+ * each receiver's senders are sorted ascending.  Requires k_intra <
+ * level_end[0], k_cross < level_end[0], k_intra <= 16, k_cross <= 16.
+ * Synchronises `stream` once.  The graph keeps a device and a host copy.
+ */
+xmgn_status xmgn_build_knn(xmgn_ctx* ctx, const float* pos, int32_t n, const int32_t* level_end,
+                           int32_t n_levels, int32_t k_intra, int32_t k_cross, xmgn_graph** out,
+                           xmgn_stream stream);
+/* Graph from a host CSR (row_ptr int32 [n+1], col int32 [E] senders,
+ * each segment strictly ascending).  Host-only; no device memory. */
+xmgn_status xmgn_graph_from_csr(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                                xmgn_graph** out);
+xmgn_status xmgn_graph_info(const xmgn_graph* g, int32_t* n_nodes, int64_t* n_edges);
+/* Copy the CSR to host arrays row_ptr [n+1] and col [E]. */
+xmgn_status xmgn_graph_export(const xmgn_graph* g, int32_t* row_ptr, int32_t* col);
+void xmgn_graph_destroy(xmgn_graph* g);
+
+/*
+ * 2. Partitions with an L-hop halo (Sec. III.A), host-side.
+ * pos: host float32 [n][3]; part_sizes: host int32 [n_parts], positive, sum n.
+ * Recursive coordinate bisection: parts [a, b) split at m = a + (b-a)/2
+ * along the axis of largest bounding-box extent (x, y, z on ties), nodes
+ * ordered by (coordinate, id), the first sum(part_sizes[a:m]) go left.
+ * The halo of a part is every node within halo_hops in-edge hops of it
+ * (breadth-first over senders).  Local node order: inner nodes by id, then
+ * halo nodes by (hop, id).  Local edges: all in-edges of local nodes with hop
+ * < halo_hops, each segment in ascending global sender id.  With halo_hops
+ * >= n_layers the inner outputs equal the full-graph outputs.
+ */
+xmgn_status xmgn_partition_halo(const xmgn_graph* g, const float* pos, int32_t n_parts,
+                                const int32_t* part_sizes, int32_t halo_hops,
+                                xmgn_partset** out);
+/* Partitions given by an explicit inner-node list per part (host int32
+ * arrays concatenated in `inner`, counts in `n_inner`), each extended by a
+ * halo_hops halo.  Parts may overlap (e.g. in-cones of sampled nodes). */
+xmgn_status xmgn_partition_explicit(const xmgn_graph* g, int32_t n_parts, const int32_t* n_inner,
+                                    const int32_t* inner, int32_t halo_hops, xmgn_partset** out);
+xmgn_status xmgn_partset_count(const xmgn_partset* ps, int32_t* n_parts, int32_t* n_global);
+xmgn_status xmgn_partset_info(const xmgn_partset* ps, int32_t part, int32_t* n_inner,
+                              int32_t* n_halo, int64_t* n_edges);
+/* Host outputs of one part: global_ids [n_inner + n_halo] (local order),
+ * hop [same], row_ptr [n_local + 1], col [n_edges] (local sender index).
+ * Any output pointer may be NULL. */
+xmgn_status xmgn_partset_export(const xmgn_partset* ps, int32_t part, int32_t* global_ids,
+                                int32_t* hop, int32_t* row_ptr, int32_t* col);
+void xmgn_partset_destroy(xmgn_partset* ps);
+
+/*
+ * 3. Forward over a batch of partitions (a whole graph is one partition with
+ * halo 0).  The batch is the disjoint union of parts part_ids (host int32
+ * [n_batch], distinct); its plan is built on the first call and cached.
+ * params:    dev FP32 blob (layout above)
+ * node_in:   dev FP32 [N_global][node_in]
+ * pos:       dev FP32 [N_global][3]
+ * edge_norm: host FP32 [2][edge_in]: mean then std of the edge input
+ * out:       dev FP32 [N_global][out_dim]; only the rows of the batch's inner
+ *            nodes are written (halo predictions are dropped, Sec. III.D)
+ * keep_tape: 1 keeps per-layer checkpoints (h^l, e^l, m^l) for backward.
+ */
+xmgn_status xmgn_forward(xmgn_ctx* ctx, const xmgn_model_desc* desc, const float* params,
+                         const xmgn_partset* ps, const int32_t* part_ids, int32_t n_batch,
+                         const float* node_in, const float* pos, const float* edge_norm,
+                         float* out, int32_t keep_tape, xmgn_stream stream);
+
+/*
+ * Masked MSE of the last forward (Sec. II.E; halo rows excluded, Sec. III.D):
+ * loss = sum over the batch's inner nodes i and channels c of
+ *        (out[i][c] - target[i][c])^2 / (n_total * out_dim),
+ * d_out[i][c] = 2 (out - target) / (n_total * out_dim) on the same rows
+ * (other rows untouched).  out, target, d_out: dev FP32 [N_global][out_dim];
+ * loss: dev FP32 [1], overwritten.  n_total: the normaliser (the full
+ * graph's node count, so partition losses add up to the full loss).
+ */
+xmgn_status xmgn_mse_grad(xmgn_ctx* ctx, const float* out, const float* target, int64_t n_total,
+                          float* d_out, float* loss, xmgn_stream stream);
+
+/*
+ * 4. Backward of the last forward on ctx (which must have kept its tape).
+ * d_out: dev FP32 [N_global][out_dim] (halo rows ignored).
+ * d_params: dev FP32, same layout as params; written, not added.
+ * Each layer is recomputed from its checkpoint (activation checkpointing).
+ */
+xmgn_status xmgn_backward(xmgn_ctx* ctx, const xmgn_model_desc* desc, const float* params,
+                          const float* d_out, float* d_params, xmgn_stream stream);
+
+/* 5. acc[i] += g[i] for i < n (dev FP32), elementwise, deterministic
+ * (gradient aggregation over partitions, Sec. III.A). */
+xmgn_status xmgn_grad_accumulate(float* acc, const float* g, int64_t n, xmgn_stream stream);
+
+/* Device bytes currently held by the context (tape and workspace). */
+xmgn_status xmgn_ctx_memory(const xmgn_ctx* ctx, int64_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XMGN_H */

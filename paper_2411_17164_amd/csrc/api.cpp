@@ -1,0 +1,1040 @@
+// Host side of the xmgn C ABI: argument validation, the halo partitioner,
+// batch plans, the activation tape and the forward / backward schedules.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/xmgn.h"
+#include "kernels.hpp"
+
+using namespace xmgn;
+
+namespace xmgn {
+void launch_vec_reduce_strided(const float* partial, int G, int row, int src, int runs, int inner, int src_stride,
+                               float* dst, int dst_stride, hipStream_t st);
+}
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static xmgn_status fail(xmgn_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                              \
+  do {                                                                                         \
+    hipError_t e_ = (x);                                                                       \
+    if (e_ != hipSuccess) return fail(XMGN_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                   \
+  }                                                                 \
+  catch (const std::bad_alloc&) {                                   \
+    return fail(XMGN_ERR_OOM, "host allocation failed");            \
+  }                                                                 \
+  catch (const std::exception& ex) {                                \
+    return fail(XMGN_ERR_INVALID, ex.what());                       \
+  }                                                                 \
+  catch (...) {                                                     \
+    return fail(XMGN_ERR_INVALID, "unknown error");                 \
+  }
+
+extern "C" const char* xmgn_last_error(void) { return g_err.c_str(); }
+extern "C" const char* xmgn_version(void) { return "xmgn 0.1 gfx950"; }
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // grow-only; contents are not preserved
+  xmgn_status ensure(size_t need) {
+    if (need <= bytes && p) return XMGN_OK;
+    release();
+    size_t b = need > 0 ? need : 16;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return fail(XMGN_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
+    }
+    bytes = b;
+    return XMGN_OK;
+  }
+  template <typename T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// model description and parameter layout
+// ---------------------------------------------------------------------------
+static xmgn_status check_desc(const xmgn_model_desc* d) {
+  if (!d) return fail(XMGN_ERR_INVALID, "desc is NULL");
+  if (d->hidden != 128 && d->hidden != 256) return fail(XMGN_ERR_UNSUPPORTED, "hidden must be 128 or 256");
+  if (d->n_layers < 1 || d->n_layers > 64) return fail(XMGN_ERR_INVALID, "n_layers must be in [1, 64]");
+  if (d->node_in < 1 || d->node_in > 8) return fail(XMGN_ERR_INVALID, "node_in must be in [1, 8]");
+  if (d->edge_in != 4) return fail(XMGN_ERR_INVALID, "edge_in must be 4");
+  if (d->out_dim < 1 || d->out_dim > 16) return fail(XMGN_ERR_INVALID, "out_dim must be in [1, 16]");
+  if (d->activation != 0 && d->activation != 1) return fail(XMGN_ERR_INVALID, "activation must be 0 or 1");
+  if (d->precision != 0 && d->precision != 1) return fail(XMGN_ERR_INVALID, "precision must be 0 or 1");
+  if (d->aggregate != 0 && d->aggregate != 1) return fail(XMGN_ERR_INVALID, "aggregate must be 0 or 1");
+  if (!(d->ln_eps > 0.f) || !std::isfinite(d->ln_eps)) return fail(XMGN_ERR_INVALID, "ln_eps must be positive");
+  return XMGN_OK;
+}
+
+// Sizes of the tensors of each block, in blob order.
+static std::vector<int64_t> block_sizes(const xmgn_model_desc* d, int block) {
+  const int64_t H = d->hidden;
+  switch (block) {
+    case 0:
+      return {H * d->node_in, H, H * H, H, H * H, H, H, H};
+    case 1:
+      return {H * d->edge_in, H, H * H, H, H * H, H, H, H};
+    case 2:
+      return {H * 3 * H, H, H * H, H, H, H};
+    case 3:
+      return {H * 2 * H, H, H * H, H, H, H};
+    case 4:
+      return {H * H, H, H * H, H, (int64_t)d->out_dim * H, d->out_dim};
+  }
+  return {};
+}
+
+static int64_t block_total(const xmgn_model_desc* d, int block) {
+  auto s = block_sizes(d, block);
+  return std::accumulate(s.begin(), s.end(), (int64_t)0);
+}
+
+static int64_t block_start(const xmgn_model_desc* d, int block, int layer) {
+  const int64_t e0 = block_total(d, 0), e1 = block_total(d, 1);
+  const int64_t le = block_total(d, 2), ln = block_total(d, 3);
+  switch (block) {
+    case 0:
+      return 0;
+    case 1:
+      return e0;
+    case 2:
+      return e0 + e1 + (int64_t)layer * (le + ln);
+    case 3:
+      return e0 + e1 + (int64_t)layer * (le + ln) + le;
+    case 4:
+      return e0 + e1 + (int64_t)d->n_layers * (le + ln);
+  }
+  return -1;
+}
+
+static int64_t poff(const xmgn_model_desc* d, int block, int layer, int tensor) {
+  auto s = block_sizes(d, block);
+  int64_t o = block_start(d, block, layer);
+  for (int i = 0; i < tensor; ++i) o += s[i];
+  return o;
+}
+
+extern "C" xmgn_status xmgn_param_count(const xmgn_model_desc* desc, int64_t* count) {
+  if (xmgn_status s = check_desc(desc)) return s;
+  if (!count) return fail(XMGN_ERR_INVALID, "count is NULL");
+  *count = block_start(desc, 4, 0) + block_total(desc, 4);
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_param_offset(const xmgn_model_desc* desc, int32_t block, int32_t layer, int32_t tensor,
+                                         int64_t* offset) {
+  if (xmgn_status s = check_desc(desc)) return s;
+  if (!offset) return fail(XMGN_ERR_INVALID, "offset is NULL");
+  if (block < 0 || block > 4) return fail(XMGN_ERR_INVALID, "block must be in [0, 4]");
+  if ((block == 2 || block == 3) && (layer < 0 || layer >= desc->n_layers))
+    return fail(XMGN_ERR_INVALID, "layer out of range");
+  if (tensor < 0 || tensor >= (int)block_sizes(desc, block).size()) return fail(XMGN_ERR_INVALID, "tensor out of range");
+  *offset = poff(desc, block, layer, tensor);
+  return XMGN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// graphs and partitions (host)
+// ---------------------------------------------------------------------------
+struct xmgn_graph {
+  int32_t n = 0;
+  std::vector<int32_t> row_ptr, col;
+};
+
+struct PartHost {
+  int32_t n_inner = 0;
+  std::vector<int32_t> gid, hop, row_ptr, col;
+};
+
+struct xmgn_partset {
+  int32_t n_global = 0;
+  int32_t halo = 0;
+  std::vector<PartHost> parts;
+};
+
+static xmgn_status check_csr(int32_t n, const int32_t* row_ptr, const int32_t* col) {
+  if (n < 0) return fail(XMGN_ERR_INVALID, "n must be >= 0");
+  if (!row_ptr || (row_ptr[n] > 0 && !col)) return fail(XMGN_ERR_INVALID, "row_ptr / col is NULL");
+  if (row_ptr[0] != 0) return fail(XMGN_ERR_INVALID, "row_ptr[0] must be 0");
+  for (int32_t r = 0; r < n; ++r) {
+    if (row_ptr[r + 1] < row_ptr[r]) return fail(XMGN_ERR_INVALID, "row_ptr must be non-decreasing");
+    for (int32_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+      if (col[k] < 0 || col[k] >= n) return fail(XMGN_ERR_INVALID, "sender index out of range");
+      if (col[k] == r) return fail(XMGN_ERR_INVALID, "self loops are not allowed");
+      if (k > row_ptr[r] && col[k] <= col[k - 1]) return fail(XMGN_ERR_INVALID, "segments must be strictly ascending");
+    }
+  }
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_graph_from_csr(int32_t n, const int32_t* row_ptr, const int32_t* col, xmgn_graph** out) {
+  GUARD_BEGIN
+  if (!out) return fail(XMGN_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (xmgn_status s = check_csr(n, row_ptr, col)) return s;
+  auto g = std::make_unique<xmgn_graph>();
+  g->n = n;
+  g->row_ptr.assign(row_ptr, row_ptr + n + 1);
+  g->col.assign(col, col + row_ptr[n]);
+  *out = g.release();
+  return XMGN_OK;
+  GUARD_END
+}
+
+extern "C" xmgn_status xmgn_graph_info(const xmgn_graph* g, int32_t* n_nodes, int64_t* n_edges) {
+  if (!g) return fail(XMGN_ERR_INVALID, "graph is NULL");
+  if (n_nodes) *n_nodes = g->n;
+  if (n_edges) *n_edges = (int64_t)g->col.size();
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_graph_export(const xmgn_graph* g, int32_t* row_ptr, int32_t* col) {
+  if (!g) return fail(XMGN_ERR_INVALID, "graph is NULL");
+  if (row_ptr) std::memcpy(row_ptr, g->row_ptr.data(), g->row_ptr.size() * sizeof(int32_t));
+  if (col && !g->col.empty()) std::memcpy(col, g->col.data(), g->col.size() * sizeof(int32_t));
+  return XMGN_OK;
+}
+
+extern "C" void xmgn_graph_destroy(xmgn_graph* g) { delete g; }
+
+// Recursive coordinate bisection over ids with target sizes sizes[a:b).
+static void rcb_split(const float* pos, std::vector<int32_t>& ids, size_t lo, size_t hi, const int32_t* sizes, int a,
+                      int b, std::vector<int32_t>& part, int depth) {
+  if (b - a == 1) {
+    for (size_t i = lo; i < hi; ++i) part[ids[i]] = a;
+    return;
+  }
+  const int m = a + (b - a) / 2;
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (size_t i = lo; i < hi; ++i)
+    for (int c = 0; c < 3; ++c) {
+      const double v = pos[(size_t)ids[i] * 3 + c];
+      mn[c] = std::min(mn[c], v);
+      mx[c] = std::max(mx[c], v);
+    }
+  int axis = 0;
+  double best = mx[0] - mn[0];
+  for (int c = 1; c < 3; ++c)
+    if (mx[c] - mn[c] > best) {
+      best = mx[c] - mn[c];
+      axis = c;
+    }
+  std::sort(ids.begin() + lo, ids.begin() + hi, [&](int32_t x, int32_t y) {
+    const float px = pos[(size_t)x * 3 + axis], py = pos[(size_t)y * 3 + axis];
+    return px < py || (px == py && x < y);
+  });
+  size_t n_left = 0;
+  for (int p = a; p < m; ++p) n_left += sizes[p];
+  const size_t mid = lo + n_left;
+  if (depth < 3) {
+    std::thread t([&] { rcb_split(pos, ids, lo, mid, sizes, a, m, part, depth + 1); });
+    rcb_split(pos, ids, mid, hi, sizes, m, b, part, depth + 1);
+    t.join();
+  } else {
+    rcb_split(pos, ids, lo, mid, sizes, a, m, part, depth + 1);
+    rcb_split(pos, ids, mid, hi, sizes, m, b, part, depth + 1);
+  }
+}
+
+// One partition: inner nodes (ascending) plus a depth-hop in-edge halo.
+static void build_part(const xmgn_graph* g, const std::vector<int32_t>& inner, int32_t depth, PartHost& P,
+                       std::vector<int32_t>& loc) {
+  P.n_inner = (int32_t)inner.size();
+  P.gid = inner;
+  P.hop.assign(inner.size(), 0);
+  for (size_t i = 0; i < inner.size(); ++i) loc[inner[i]] = (int32_t)i;
+  size_t f0 = 0, f1 = inner.size();
+  for (int32_t h = 1; h <= depth && f1 > f0; ++h) {
+    std::vector<int32_t> next;
+    for (size_t i = f0; i < f1; ++i) {
+      const int32_t r = P.gid[i];
+      for (int32_t k = g->row_ptr[r]; k < g->row_ptr[r + 1]; ++k) {
+        const int32_t s = g->col[k];
+        if (loc[s] == -1) {
+          loc[s] = -2;  // discovered at this hop
+          next.push_back(s);
+        }
+      }
+    }
+    std::sort(next.begin(), next.end());
+    for (int32_t s : next) {
+      loc[s] = (int32_t)P.gid.size();
+      P.gid.push_back(s);
+      P.hop.push_back(h);
+    }
+    f0 = f1;
+    f1 = P.gid.size();
+  }
+  const size_t nl = P.gid.size();
+  P.row_ptr.assign(nl + 1, 0);
+  for (size_t i = 0; i < nl; ++i) {
+    const int32_t r = P.gid[i];
+    const int32_t d = P.hop[i] < depth ? g->row_ptr[r + 1] - g->row_ptr[r] : 0;
+    P.row_ptr[i + 1] = P.row_ptr[i] + d;
+  }
+  P.col.resize(P.row_ptr[nl]);
+  for (size_t i = 0; i < nl; ++i) {
+    if (P.hop[i] >= depth) continue;
+    const int32_t r = P.gid[i];
+    int32_t o = P.row_ptr[i];
+    for (int32_t k = g->row_ptr[r]; k < g->row_ptr[r + 1]; ++k) P.col[o++] = loc[g->col[k]];
+  }
+  for (int32_t s : P.gid) loc[s] = -1;
+}
+
+static xmgn_status build_parts(const xmgn_graph* g, const std::vector<std::vector<int32_t>>& inner, int32_t depth,
+                               xmgn_partset** out) {
+  auto ps = std::make_unique<xmgn_partset>();
+  ps->n_global = g->n;
+  ps->halo = depth;
+  const int np = (int)inner.size();
+  ps->parts.resize(np);
+  const int nt = std::max(1, std::min<int>(np, (int)std::min(8u, std::max(1u, std::thread::hardware_concurrency()))));
+  std::vector<std::thread> pool;
+  std::vector<std::string> errs(nt);
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&, t] {
+      try {
+        std::vector<int32_t> loc(g->n, -1);
+        for (int p = t; p < np; p += nt) build_part(g, inner[p], depth, ps->parts[p], loc);
+      } catch (const std::exception& ex) {
+        errs[t] = ex.what();
+      }
+    });
+  for (auto& th : pool) th.join();
+  for (auto& e : errs)
+    if (!e.empty()) return fail(XMGN_ERR_OOM, e);
+  *out = ps.release();
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_partition_halo(const xmgn_graph* g, const float* pos, int32_t n_parts,
+                                           const int32_t* part_sizes, int32_t halo_hops, xmgn_partset** out) {
+  GUARD_BEGIN
+  if (!out) return fail(XMGN_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!g) return fail(XMGN_ERR_INVALID, "graph is NULL");
+  if (!pos && g->n > 0) return fail(XMGN_ERR_INVALID, "pos is NULL");
+  if (n_parts < 1) return fail(XMGN_ERR_INVALID, "n_parts must be >= 1");
+  if (halo_hops < 1) return fail(XMGN_ERR_INVALID, "halo_hops must be >= 1");
+  std::vector<int32_t> sizes(n_parts);
+  if (part_sizes) {
+    int64_t tot = 0;
+    for (int p = 0; p < n_parts; ++p) {
+      if (part_sizes[p] <= 0) return fail(XMGN_ERR_INVALID, "part sizes must be positive");
+      sizes[p] = part_sizes[p];
+      tot += part_sizes[p];
+    }
+    if (tot != g->n) return fail(XMGN_ERR_INVALID, "part sizes must sum to the node count");
+  } else {
+    if (n_parts > g->n) return fail(XMGN_ERR_INVALID, "more parts than nodes");
+    for (int p = 0; p < n_parts; ++p) sizes[p] = (int32_t)((int64_t)g->n * (p + 1) / n_parts - (int64_t)g->n * p / n_parts);
+  }
+  for (int64_t i = 0; i < 3 * (int64_t)g->n; ++i)
+    if (!std::isfinite(pos[i])) return fail(XMGN_ERR_INVALID, "pos holds NaN or Inf");
+  std::vector<int32_t> ids(g->n), part(g->n);
+  std::iota(ids.begin(), ids.end(), 0);
+  rcb_split(pos, ids, 0, ids.size(), sizes.data(), 0, n_parts, part, 0);
+  std::vector<std::vector<int32_t>> inner(n_parts);
+  for (int p = 0; p < n_parts; ++p) inner[p].reserve(sizes[p]);
+  for (int32_t i = 0; i < g->n; ++i) inner[part[i]].push_back(i);
+  return build_parts(g, inner, halo_hops, out);
+  GUARD_END
+}
+
+extern "C" xmgn_status xmgn_partition_explicit(const xmgn_graph* g, int32_t n_parts, const int32_t* n_inner,
+                                               const int32_t* inner, int32_t halo_hops, xmgn_partset** out) {
+  GUARD_BEGIN
+  if (!out) return fail(XMGN_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!g) return fail(XMGN_ERR_INVALID, "graph is NULL");
+  if (n_parts < 1 || !n_inner || !inner) return fail(XMGN_ERR_INVALID, "bad part lists");
+  if (halo_hops < 1) return fail(XMGN_ERR_INVALID, "halo_hops must be >= 1");
+  std::vector<std::vector<int32_t>> lists(n_parts);
+  int64_t o = 0;
+  for (int p = 0; p < n_parts; ++p) {
+    if (n_inner[p] <= 0) return fail(XMGN_ERR_INVALID, "each part needs at least one inner node");
+    lists[p].assign(inner + o, inner + o + n_inner[p]);
+    o += n_inner[p];
+    std::sort(lists[p].begin(), lists[p].end());
+    for (size_t i = 0; i < lists[p].size(); ++i) {
+      if (lists[p][i] < 0 || lists[p][i] >= g->n) return fail(XMGN_ERR_INVALID, "inner node out of range");
+      if (i > 0 && lists[p][i] == lists[p][i - 1]) return fail(XMGN_ERR_INVALID, "repeated inner node");
+    }
+  }
+  return build_parts(g, lists, halo_hops, out);
+  GUARD_END
+}
+
+extern "C" xmgn_status xmgn_partset_count(const xmgn_partset* ps, int32_t* n_parts, int32_t* n_global) {
+  if (!ps) return fail(XMGN_ERR_INVALID, "partset is NULL");
+  if (n_parts) *n_parts = (int32_t)ps->parts.size();
+  if (n_global) *n_global = ps->n_global;
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_partset_info(const xmgn_partset* ps, int32_t part, int32_t* n_inner, int32_t* n_halo,
+                                         int64_t* n_edges) {
+  if (!ps) return fail(XMGN_ERR_INVALID, "partset is NULL");
+  if (part < 0 || part >= (int32_t)ps->parts.size()) return fail(XMGN_ERR_INVALID, "part out of range");
+  const PartHost& P = ps->parts[part];
+  if (n_inner) *n_inner = P.n_inner;
+  if (n_halo) *n_halo = (int32_t)P.gid.size() - P.n_inner;
+  if (n_edges) *n_edges = (int64_t)P.col.size();
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_partset_export(const xmgn_partset* ps, int32_t part, int32_t* global_ids, int32_t* hop,
+                                           int32_t* row_ptr, int32_t* col) {
+  if (!ps) return fail(XMGN_ERR_INVALID, "partset is NULL");
+  if (part < 0 || part >= (int32_t)ps->parts.size()) return fail(XMGN_ERR_INVALID, "part out of range");
+  const PartHost& P = ps->parts[part];
+  if (global_ids) std::memcpy(global_ids, P.gid.data(), P.gid.size() * 4);
+  if (hop) std::memcpy(hop, P.hop.data(), P.hop.size() * 4);
+  if (row_ptr) std::memcpy(row_ptr, P.row_ptr.data(), P.row_ptr.size() * 4);
+  if (col && !P.col.empty()) std::memcpy(col, P.col.data(), P.col.size() * 4);
+  return XMGN_OK;
+}
+
+extern "C" void xmgn_partset_destroy(xmgn_partset* ps) { delete ps; }
+
+// ---------------------------------------------------------------------------
+// context, batch plans, weights, tape
+// ---------------------------------------------------------------------------
+struct Batch {
+  const xmgn_partset* ps = nullptr;
+  std::vector<int32_t> part_ids;
+  int mt_edge = 0;
+  int n = 0, n_inner = 0;
+  int64_t E = 0;
+  int n_etiles = 0;
+  DBuf ints;  // gid | row_ptr | col | recv | csc_ptr | csc_edge | etiles | inner
+  BatchView view{};
+};
+
+struct BlockW {
+  int64_t W1 = -1, W2 = -1, W3 = -1, W1T = -1, W2T = -1, W3T = -1, Brs = -1;
+};
+
+struct xmgn_ctx {
+  int device = 0;
+  int mt_edge = 0, mt_node = 0, grid = 0;  // 0 = default
+  Batch batch;
+  bool have_batch = false;
+  // weights
+  xmgn_model_desc wdesc{};
+  bool have_wplan = false;
+  std::vector<PrepJob> jobs;
+  int64_t blob_elems = 0;
+  std::vector<BlockW> bw;  // per block: 0 enc_node, 1 enc_edge, 2+2l edge, 3+2l node, 2+2L dec
+  DBuf jobs_dev, blob;
+  // tape
+  DBuf h, e, m;
+  int tape_slots_h = 0, tape_slots_e = 0, tape_slots_m = 0;
+  bool tape_full = false;
+  // backward workspace
+  DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, lossp;
+  // state of the last forward
+  bool fwd_valid = false;
+  bool fwd_tape = false;
+  xmgn_model_desc fdesc{};
+  const float* f_params = nullptr;
+  const float* f_node_in = nullptr;
+  const float* f_pos = nullptr;
+  EdgeNorm f_en{};
+};
+
+static size_t tsize(const xmgn_model_desc* d) { return d->precision == 1 ? 2 : 4; }
+
+static Shape make_shape(const xmgn_ctx* c, const xmgn_model_desc* d) {
+  Shape s{};
+  s.H = d->hidden;
+  s.prec = d->precision;
+  s.act = d->activation;
+  s.agg = d->aggregate;
+  s.eps = d->ln_eps;
+  int me = c->mt_edge > 0 ? c->mt_edge : 64, mn = c->mt_node > 0 ? c->mt_node : 64;
+  // LDS budget: H = 256 runs 32-row tiles
+  if (d->hidden == 256) {
+    me = 32;
+    mn = 32;
+  }
+  s.mt_edge = me;
+  s.mt_node = mn;
+  s.grid = c->grid > 0 ? c->grid : 1024;
+  return s;
+}
+
+extern "C" xmgn_status xmgn_ctx_create(int32_t device, xmgn_ctx** out) {
+  GUARD_BEGIN
+  if (!out) return fail(XMGN_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(XMGN_ERR_INVALID, "device out of range");
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(XMGN_ERR_UNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+  auto c = std::make_unique<xmgn_ctx>();
+  c->device = device;
+  *out = c.release();
+  return XMGN_OK;
+  GUARD_END
+}
+
+extern "C" void xmgn_ctx_destroy(xmgn_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  delete ctx;
+}
+
+extern "C" xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int32_t node_rows, int32_t grid) {
+  if (!ctx) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (edge_rows != 0 && edge_rows != 32 && edge_rows != 64) return fail(XMGN_ERR_INVALID, "edge_rows must be 0, 32 or 64");
+  if (node_rows != 0 && node_rows != 32 && node_rows != 64) return fail(XMGN_ERR_INVALID, "node_rows must be 0, 32 or 64");
+  if (grid < 0 || (grid > 0 && (grid < 8 || grid % 8 != 0 || grid > 65536)))
+    return fail(XMGN_ERR_INVALID, "grid must be 0 or a multiple of 8 in [8, 65536]");
+  ctx->mt_edge = edge_rows;
+  ctx->mt_node = node_rows;
+  ctx->grid = grid;
+  ctx->have_batch = false;
+  ctx->fwd_valid = false;
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_ctx_memory(const xmgn_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return fail(XMGN_ERR_INVALID, "NULL argument");
+  const DBuf* bufs[] = {&c->batch.ints, &c->jobs_dev, &c->blob, &c->h, &c->e, &c->m, &c->dhA, &c->dhMid,
+                        &c->dm, &c->Sr, &c->Ss, &c->deA, &c->deB, &c->fa, &c->fb, &c->fc, &c->fd,
+                        &c->dy, &c->part, &c->wpart, &c->lossp};
+  int64_t t = 0;
+  for (const DBuf* b : bufs) t += (int64_t)b->bytes;
+  *bytes = t;
+  return XMGN_OK;
+}
+
+// Weight preparation plan: compute-type copies and transposes.
+static void add_job(xmgn_ctx* c, int64_t src, int src_ld, int col0, int transpose, int rows, int cols, int64_t& dst,
+                    int dst_ld = -1, int dst_col0 = 0, bool alloc = true) {
+  PrepJob j{};
+  j.src_off = src;
+  j.src_ld = src_ld;
+  j.src_col0 = col0;
+  j.transpose = transpose;
+  if (alloc) {
+    dst = c->blob_elems;
+    c->blob_elems += (int64_t)rows * (dst_ld > 0 ? dst_ld : cols);
+    c->blob_elems = (c->blob_elems + 7) / 8 * 8;
+  }
+  j.dst_off = dst;
+  j.dst_ld = dst_ld > 0 ? dst_ld : cols;
+  j.dst_col0 = dst_col0;
+  j.rows = rows;
+  j.cols = cols;
+  c->jobs.push_back(j);
+}
+
+static xmgn_status ensure_wplan(xmgn_ctx* c, const xmgn_model_desc* d) {
+  if (c->have_wplan && std::memcmp(&c->wdesc, d, sizeof(*d)) == 0) return XMGN_OK;
+  c->jobs.clear();
+  c->blob_elems = 0;
+  const int H = d->hidden, L = d->n_layers;
+  c->bw.assign(3 + 2 * L, BlockW{});
+  for (int b = 0; b < 2; ++b) {
+    BlockW& w = c->bw[b];
+    add_job(c, poff(d, b, 0, 2), H, 0, 0, H, H, w.W2);
+    add_job(c, poff(d, b, 0, 4), H, 0, 0, H, H, w.W3);
+    add_job(c, poff(d, b, 0, 2), H, 0, 1, H, H, w.W2T);
+    add_job(c, poff(d, b, 0, 4), H, 0, 1, H, H, w.W3T);
+  }
+  for (int l = 0; l < L; ++l) {
+    BlockW& we = c->bw[2 + 2 * l];
+    const int64_t W1e = poff(d, 2, l, 0), W2e = poff(d, 2, l, 2);
+    add_job(c, W1e, 3 * H, 0, 0, H, 3 * H, we.W1);
+    add_job(c, W2e, H, 0, 0, H, H, we.W2);
+    add_job(c, W2e, H, 0, 1, H, H, we.W2T);
+    add_job(c, W1e, 3 * H, 2 * H, 1, H, H, we.W1T);  // [c][j] = W1[j][2H + c]
+    add_job(c, W1e, 3 * H, 0, 1, H, H, we.Brs, 2 * H, 0);
+    add_job(c, W1e, 3 * H, H, 1, H, H, we.Brs, 2 * H, H, false);
+    BlockW& wn = c->bw[3 + 2 * l];
+    const int64_t W1n = poff(d, 3, l, 0), W2n = poff(d, 3, l, 2);
+    add_job(c, W1n, 2 * H, 0, 0, H, 2 * H, wn.W1);
+    add_job(c, W2n, H, 0, 0, H, H, wn.W2);
+    add_job(c, W2n, H, 0, 1, H, H, wn.W2T);
+    add_job(c, W1n, 2 * H, 0, 1, 2 * H, H, wn.W1T);
+  }
+  BlockW& wd = c->bw[2 + 2 * L];
+  add_job(c, poff(d, 4, 0, 0), H, 0, 0, H, H, wd.W1);
+  add_job(c, poff(d, 4, 0, 2), H, 0, 0, H, H, wd.W2);
+  add_job(c, poff(d, 4, 0, 0), H, 0, 1, H, H, wd.W1T);
+  add_job(c, poff(d, 4, 0, 2), H, 0, 1, H, H, wd.W2T);
+  if (xmgn_status s = c->jobs_dev.ensure(c->jobs.size() * sizeof(PrepJob))) return s;
+  HIPCHK(hipMemcpy(c->jobs_dev.p, c->jobs.data(), c->jobs.size() * sizeof(PrepJob), hipMemcpyHostToDevice));
+  if (xmgn_status s = c->blob.ensure((size_t)c->blob_elems * tsize(d))) return s;
+  c->wdesc = *d;
+  c->have_wplan = true;
+  return XMGN_OK;
+}
+
+static MlpW weights(const xmgn_ctx* c, const xmgn_model_desc* d, const float* params, int bi, int block, int layer) {
+  const BlockW& b = c->bw[bi];
+  const size_t ts = tsize(d);
+  auto ptr = [&](int64_t o) -> const void* { return o < 0 ? nullptr : (const char*)c->blob.p + o * ts; };
+  MlpW w{};
+  w.W1 = ptr(b.W1);
+  w.W2 = ptr(b.W2);
+  w.W3 = ptr(b.W3);
+  w.W1T = ptr(b.W1T);
+  w.W2T = ptr(b.W2T);
+  w.W3T = ptr(b.W3T);
+  w.Brs = ptr(b.Brs);
+  auto P = [&](int t) { return params + poff(d, block, layer, t); };
+  if (block == 0 || block == 1) {
+    w.W1f = P(0);
+    w.b1 = P(1);
+    w.b2 = P(3);
+    w.b3 = P(5);
+    w.gamma = P(6);
+    w.beta = P(7);
+  } else if (block == 2 || block == 3) {
+    w.b1 = P(1);
+    w.b2 = P(3);
+    w.gamma = P(4);
+    w.beta = P(5);
+  } else {
+    w.b1 = P(1);
+    w.b2 = P(3);
+    w.W1f = P(4);  // decoder last layer W3 [out][H], FP32
+    w.b3 = P(5);
+  }
+  return w;
+}
+
+static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32_t* part_ids, int32_t n_batch,
+                                int mt_edge) {
+  if (c->have_batch && c->batch.ps == ps && c->batch.mt_edge == mt_edge &&
+      c->batch.part_ids == std::vector<int32_t>(part_ids, part_ids + n_batch))
+    return XMGN_OK;
+  c->have_batch = false;
+  Batch& B = c->batch;
+  B.ps = ps;
+  B.part_ids.assign(part_ids, part_ids + n_batch);
+  B.mt_edge = mt_edge;
+  int64_t n = 0, E = 0, ni = 0;
+  for (int32_t p : B.part_ids) {
+    const PartHost& P = ps->parts[p];
+    n += (int64_t)P.gid.size();
+    E += (int64_t)P.col.size();
+    ni += P.n_inner;
+  }
+  if (n >= (1ll << 31) - 1 || E >= (1ll << 31) - 1) return fail(XMGN_ERR_UNSUPPORTED, "batch exceeds int32 indexing");
+  std::vector<int32_t> gid(n), row_ptr(n + 1), col(E), recv(E), csc_ptr(n + 1, 0), csc_edge(E), inner(ni), etiles;
+  int64_t no = 0, eo = 0, io = 0;
+  int maxdeg = 0;
+  for (int32_t p : B.part_ids) {
+    const PartHost& P = ps->parts[p];
+    const int64_t nl = (int64_t)P.gid.size();
+    for (int64_t i = 0; i < nl; ++i) {
+      gid[no + i] = P.gid[i];
+      row_ptr[no + i] = (int32_t)(eo + P.row_ptr[i]);
+      const int d = P.row_ptr[i + 1] - P.row_ptr[i];
+      maxdeg = std::max(maxdeg, d);
+      for (int32_t k = P.row_ptr[i]; k < P.row_ptr[i + 1]; ++k) {
+        col[eo + k] = (int32_t)(no + P.col[k]);
+        recv[eo + k] = (int32_t)(no + i);
+      }
+    }
+    for (int32_t i = 0; i < P.n_inner; ++i) inner[io + i] = (int32_t)(no + i);
+    no += nl;
+    eo += (int64_t)P.col.size();
+    io += P.n_inner;
+  }
+  row_ptr[n] = (int32_t)E;
+  if (maxdeg > mt_edge)
+    return fail(XMGN_ERR_UNSUPPORTED, "in-degree " + std::to_string(maxdeg) + " exceeds the edge tile (" +
+                                          std::to_string(mt_edge) + " rows)");
+  // sender CSR: stable counting sort by sender (edges already in receiver order)
+  for (int64_t k = 0; k < E; ++k) ++csc_ptr[col[k] + 1];
+  for (int64_t i = 0; i < n; ++i) csc_ptr[i + 1] += csc_ptr[i];
+  {
+    std::vector<int32_t> fill(csc_ptr.begin(), csc_ptr.end() - 1);
+    for (int64_t k = 0; k < E; ++k) csc_edge[fill[col[k]]++] = (int32_t)k;
+  }
+  // edge tiles: whole receiver segments, at most mt_edge edges and receivers
+  etiles.push_back(0);
+  for (int64_t r = 0; r < n;) {
+    int64_t cnt = 0, r1 = r;
+    while (r1 < n && r1 - r < mt_edge && cnt + (row_ptr[r1 + 1] - row_ptr[r1]) <= mt_edge) {
+      cnt += row_ptr[r1 + 1] - row_ptr[r1];
+      ++r1;
+    }
+    etiles.push_back((int32_t)r1);
+    r = r1;
+  }
+  const int64_t nt = (int64_t)etiles.size() - 1;
+  const int64_t total = n + (n + 1) + E + E + (n + 1) + E + (nt + 1) + ni;
+  if (xmgn_status s = B.ints.ensure((size_t)total * 4)) return s;
+  int32_t* d = B.ints.as<int32_t>();
+  int64_t o = 0;
+  auto up = [&](const std::vector<int32_t>& v) -> const int* {
+    const int* ptr = d + o;
+    if (!v.empty()) (void)hipMemcpy(d + o, v.data(), v.size() * 4, hipMemcpyHostToDevice);
+    o += (int64_t)v.size();
+    return ptr;
+  };
+  BatchView& V = B.view;
+  V.n = (int)n;
+  V.E = (int)E;
+  V.gid = up(gid);
+  V.row_ptr = up(row_ptr);
+  V.col = up(col);
+  V.recv = up(recv);
+  V.csc_ptr = up(csc_ptr);
+  V.csc_edge = up(csc_edge);
+  V.etiles = up(etiles);
+  V.n_etiles = (int)nt;
+  V.inner = up(inner);
+  V.n_inner = (int)ni;
+  HIPCHK(hipGetLastError());
+  B.n = (int)n;
+  B.E = E;
+  B.n_inner = (int)ni;
+  B.n_etiles = (int)nt;
+  c->have_batch = true;
+  return XMGN_OK;
+}
+
+static xmgn_status ensure_tape(xmgn_ctx* c, const xmgn_model_desc* d, bool full) {
+  const size_t ts = tsize(d), H = d->hidden, L = d->n_layers;
+  const size_t n = c->batch.n, E = c->batch.E;
+  const size_t sh = full ? L + 1 : 2, se = full ? L : 2, sm = full ? L : 1;
+  if (xmgn_status s = c->h.ensure(sh * n * H * ts)) return s;
+  if (xmgn_status s = c->e.ensure(se * E * H * ts)) return s;
+  if (xmgn_status s = c->m.ensure(sm * n * H * 4)) return s;
+  c->tape_slots_h = (int)sh;
+  c->tape_slots_e = (int)se;
+  c->tape_slots_m = (int)sm;
+  c->tape_full = full;
+  return XMGN_OK;
+}
+
+static void* hslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
+  const size_t s = c->tape_full ? l : l % 2;
+  return (char*)c->h.p + s * c->batch.n * d->hidden * tsize(d);
+}
+static void* eslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
+  const size_t s = c->tape_full ? l : l % 2;
+  return (char*)c->e.p + s * c->batch.E * d->hidden * tsize(d);
+}
+static float* mslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
+  const size_t s = c->tape_full ? l : 0;
+  return c->m.as<float>() + s * c->batch.n * d->hidden;
+}
+
+extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const float* params, const xmgn_partset* ps,
+                                    const int32_t* part_ids, int32_t n_batch, const float* node_in, const float* pos,
+                                    const float* edge_norm, float* out, int32_t keep_tape, xmgn_stream stream) {
+  GUARD_BEGIN
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (xmgn_status s = check_desc(d)) return s;
+  if (!ps) return fail(XMGN_ERR_INVALID, "partset is NULL");
+  if (!params || !node_in || !pos || !edge_norm || !out || !part_ids) return fail(XMGN_ERR_INVALID, "NULL argument");
+  if (n_batch < 1 || n_batch > (int32_t)ps->parts.size()) return fail(XMGN_ERR_INVALID, "bad n_batch");
+  {
+    std::vector<int32_t> ids(part_ids, part_ids + n_batch);
+    std::sort(ids.begin(), ids.end());
+    for (size_t i = 0; i < ids.size(); ++i) {
+      if (ids[i] < 0 || ids[i] >= (int32_t)ps->parts.size()) return fail(XMGN_ERR_INVALID, "part id out of range");
+      if (i > 0 && ids[i] == ids[i - 1]) return fail(XMGN_ERR_INVALID, "repeated part id");
+    }
+  }
+  EdgeNorm en{};
+  for (int k = 0; k < 4; ++k) {
+    en.mu[k] = edge_norm[k];
+    en.sd[k] = edge_norm[4 + k];
+    if (!std::isfinite(en.mu[k]) || !std::isfinite(en.sd[k]) || en.sd[k] == 0.f)
+      return fail(XMGN_ERR_INVALID, "edge_norm must be finite with nonzero std");
+  }
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const Shape s = make_shape(c, d);
+  if (xmgn_status r = ensure_batch(c, ps, part_ids, n_batch, s.mt_edge)) return r;
+  if (xmgn_status r = ensure_wplan(c, d)) return r;
+  if (xmgn_status r = ensure_tape(c, d, keep_tape != 0)) return r;
+  const BatchView& b = c->batch.view;
+  const int L = d->n_layers;
+  g_config_error = 0;
+  launch_prep(params, c->blob.p, d->precision, c->jobs_dev.as<PrepJob>(), (int)c->jobs.size(), st);
+  launch_enc_node_fwd(s, b, weights(c, d, params, 0, 0, 0), node_in, d->node_in, hslot(c, d, 0), st);
+  launch_enc_edge_fwd(s, b, weights(c, d, params, 1, 1, 0), pos, en, eslot(c, d, 0), st);
+  for (int l = 0; l < L; ++l) {
+    launch_edge_fwd(s, b, weights(c, d, params, 2 + 2 * l, 2, l), hslot(c, d, l), eslot(c, d, l),
+                    l + 1 < L ? eslot(c, d, l + 1) : nullptr, mslot(c, d, l), st);
+    launch_node_fwd(s, b, weights(c, d, params, 3 + 2 * l, 3, l), hslot(c, d, l), mslot(c, d, l), hslot(c, d, l + 1),
+                    st);
+  }
+  launch_dec_fwd(s, b, weights(c, d, params, 2 + 2 * L, 4, 0), hslot(c, d, L), out, d->out_dim, st);
+  HIPCHK(hipGetLastError());
+  if (g_config_error) return fail(XMGN_ERR_UNSUPPORTED, "tile configuration does not fit this kernel");
+  c->fwd_valid = true;
+  c->fwd_tape = keep_tape != 0;
+  c->fdesc = *d;
+  c->f_params = params;
+  c->f_node_in = node_in;
+  c->f_pos = pos;
+  c->f_en = en;
+  return XMGN_OK;
+  GUARD_END
+}
+
+extern "C" xmgn_status xmgn_mse_grad(xmgn_ctx* c, const float* out, const float* target, int64_t n_total, float* d_out,
+                                     float* loss, xmgn_stream stream) {
+  GUARD_BEGIN
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (!c->fwd_valid) return fail(XMGN_ERR_STATE, "no forward on this context");
+  if (!out || !target || !d_out || !loss) return fail(XMGN_ERR_INVALID, "NULL argument");
+  if (n_total < 1) return fail(XMGN_ERR_INVALID, "n_total must be >= 1");
+  HIPCHK(hipSetDevice(c->device));
+  const int G = 256;
+  if (xmgn_status s = c->lossp.ensure(G * sizeof(float))) return s;
+  const double inv = 1.0 / ((double)n_total * c->fdesc.out_dim);
+  launch_mse(out, target, c->batch.view.gid, c->batch.view.inner, c->batch.n_inner, c->fdesc.out_dim, inv, d_out,
+             c->lossp.as<float>(), G, loss, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return XMGN_OK;
+  GUARD_END
+}
+
+static void wgrad(const Shape& s, WgradOp op, DBuf& wpart, hipStream_t st) {
+  launch_wgrad(s, op, wpart.as<float>(), st);
+}
+
+static WgradOp wop(const void* A, int a_f32, int lda, int a0, const int* ia, const void* B, int b_f32, int ldb, int b0,
+                   const int* ib, int R, int M, int N, float* dst, int ldd, int M_valid = -1) {
+  WgradOp o{};
+  o.A = A;
+  o.a_f32 = a_f32;
+  o.lda = lda;
+  o.a0 = a0;
+  o.ia = ia;
+  o.B = B;
+  o.b_f32 = b_f32;
+  o.ldb = ldb;
+  o.b0 = b0;
+  o.ib = ib;
+  o.R = R;
+  o.M = M;
+  o.N = N;
+  o.M_valid = M_valid < 0 ? M : M_valid;
+  o.dst = dst;
+  o.ldd = ldd;
+  return o;
+}
+
+extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, const float* params, const float* d_out,
+                                     float* d_params, xmgn_stream stream) {
+  GUARD_BEGIN
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (xmgn_status s = check_desc(d)) return s;
+  if (!params || !d_out || !d_params) return fail(XMGN_ERR_INVALID, "NULL argument");
+  if (!c->fwd_valid || !c->fwd_tape) return fail(XMGN_ERR_STATE, "backward needs a forward with keep_tape = 1");
+  if (std::memcmp(&c->fdesc, d, sizeof(*d)) != 0 || params != c->f_params)
+    return fail(XMGN_ERR_STATE, "backward must use the desc and params of the last forward");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const Shape s = make_shape(c, d);
+  const BatchView& b = c->batch.view;
+  const size_t H = d->hidden, n = c->batch.n, E = c->batch.E, ts = tsize(d);
+  const int L = d->n_layers, G = s.grid;
+  const size_t rows = std::max(n, E);
+  for (DBuf* p : {&c->dhA, &c->dhMid, &c->dm, &c->Sr, &c->Ss})
+    if (xmgn_status r = p->ensure(n * H * 4)) return r;
+  for (DBuf* p : {&c->deA, &c->deB})
+    if (xmgn_status r = p->ensure(E * H * 4)) return r;
+  for (DBuf* p : {&c->fa, &c->fb, &c->fc, &c->fd})
+    if (xmgn_status r = p->ensure(rows * H * ts)) return r;
+  if (xmgn_status r = c->dy.ensure((size_t)c->batch.n_inner * 16 * 4)) return r;
+  if (xmgn_status r = c->part.ensure((size_t)G * 13 * H * 4)) return r;
+  {
+    size_t need = 0;
+    const int Rs[3] = {(int)n, (int)E, c->batch.n_inner};
+    for (int R : Rs)
+      need = std::max(need, wgrad_partial_floats(s, wop(nullptr, 0, 0, 0, nullptr, nullptr, 0, 0, 0, nullptr, R,
+                                                        (int)H, (int)H, nullptr, 0)));
+    if (xmgn_status r = c->wpart.ensure(need * 4)) return r;
+  }
+  float* part = c->part.as<float>();
+  auto P = [&](int block, int layer, int t) { return d_params + poff(d, block, layer, t); };
+  auto hl = [&](int l) { return hslot(c, d, l); };
+
+  g_config_error = 0;
+  // decoder
+  launch_fill(c->dhA.as<float>(), n * H, 0.f, st);
+  {
+    DecBwdOut o{c->dhA.as<float>(), c->fa.p, c->fb.p, c->fc.p, c->fd.p, c->dy.as<float>(), part};
+    launch_dec_bwd(s, b, weights(c, d, params, 2 + 2 * L, 4, 0), hl(L), d_out, d->out_dim, o, st);
+    VecSeg segs[3] = {{0, (int)H, P(4, 0, 1)}, {(int)H, (int)H, P(4, 0, 3)}, {2 * (int)H, d->out_dim, P(4, 0, 5)}};
+    launch_vec_reduce(part, G, 2 * (int)H + 16, segs, 3, st);
+    const int ni = c->batch.n_inner;
+    wgrad(s, wop(c->dy.p, 1, 16, 0, nullptr, c->fb.p, 0, (int)H, 0, nullptr, ni, 16, (int)H, P(4, 0, 4), (int)H,
+                 d->out_dim), c->wpart, st);
+    wgrad(s, wop(c->fd.p, 0, (int)H, 0, nullptr, c->fa.p, 0, (int)H, 0, nullptr, ni, (int)H, (int)H, P(4, 0, 2), (int)H),
+          c->wpart, st);
+    wgrad(s, wop(c->fc.p, 0, (int)H, 0, nullptr, hl(L), 0, (int)H, 0, b.inner, ni, (int)H, (int)H, P(4, 0, 0), (int)H),
+          c->wpart, st);
+  }
+  // processor layers, last to first
+  const float* de_in = nullptr;
+  DBuf* de_out = &c->deA;
+  DBuf* de_other = &c->deB;
+  for (int l = L - 1; l >= 0; --l) {
+    const MlpW wn = weights(c, d, params, 3 + 2 * l, 3, l);
+    NodeBwdOut no{c->dhMid.as<float>(), c->dm.as<float>(), c->fa.p, c->fb.p, c->fc.p, part};
+    launch_node_bwd(s, b, wn, hl(l), mslot(c, d, l), c->dhA.as<float>(), no, st);
+    VecSeg ns[4] = {{0, (int)H, P(3, l, 1)}, {(int)H, (int)H, P(3, l, 3)}, {2 * (int)H, (int)H, P(3, l, 4)},
+                    {3 * (int)H, (int)H, P(3, l, 5)}};
+    launch_vec_reduce(part, G, 4 * (int)H, ns, 4, st);
+    wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 0),
+                 2 * (int)H), c->wpart, st);
+    wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, mslot(c, d, l), 1, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
+                 P(3, l, 0) + H, 2 * (int)H), c->wpart, st);
+    wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, c->fc.p, 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 2),
+                 (int)H), c->wpart, st);
+
+    const MlpW we = weights(c, d, params, 2 + 2 * l, 2, l);
+    EdgeBwdOut eo{de_out->as<float>(), c->Sr.as<float>(), c->fa.p, c->fb.p, c->fc.p, part};
+    launch_edge_bwd(s, b, we, hl(l), eslot(c, d, l), de_in, c->dm.as<float>(), eo, st);
+    VecSeg es[4] = {{0, (int)H, P(2, l, 1)}, {(int)H, (int)H, P(2, l, 3)}, {2 * (int)H, (int)H, P(2, l, 4)},
+                    {3 * (int)H, (int)H, P(2, l, 5)}};
+    launch_vec_reduce(part, G, 4 * (int)H, es, 4, st);
+    launch_sender_sum(s, b, c->fa.p, c->Ss.as<float>(), st);
+    launch_node_dh(s, b, we, c->dhMid.as<float>(), c->Sr.as<float>(), c->Ss.as<float>(), c->dhA.as<float>(), st);
+    wgrad(s, wop(c->Sr.p, 1, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(2, l, 0),
+                 3 * (int)H), c->wpart, st);
+    wgrad(s, wop(c->Ss.p, 1, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
+                 P(2, l, 0) + H, 3 * (int)H), c->wpart, st);
+    wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, eslot(c, d, l), 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H,
+                 P(2, l, 0) + 2 * H, 3 * (int)H), c->wpart, st);
+    wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, c->fc.p, 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H, P(2, l, 2),
+                 (int)H), c->wpart, st);
+    de_in = de_out->as<float>();
+    std::swap(de_out, de_other);
+  }
+  // encoders
+  for (int blk = 1; blk >= 0; --blk) {
+    const MlpW w = weights(c, d, params, blk, blk, 0);
+    EncBwdOut o{c->fa.p, c->fb.p, c->fc.p, c->fd.p, part};
+    int R;
+    int in_dim;
+    if (blk == 1) {
+      launch_enc_edge_bwd(s, b, w, c->f_pos, c->f_en, de_in, o, st);
+      R = (int)E;
+      in_dim = 4;
+    } else {
+      launch_enc_node_bwd(s, b, w, c->f_node_in, d->node_in, c->dhA.as<float>(), o, st);
+      R = (int)n;
+      in_dim = d->node_in;
+    }
+    VecSeg vs[5] = {{0, (int)H, P(blk, 0, 1)}, {(int)H, (int)H, P(blk, 0, 3)}, {2 * (int)H, (int)H, P(blk, 0, 5)},
+                    {3 * (int)H, (int)H, P(blk, 0, 6)}, {4 * (int)H, (int)H, P(blk, 0, 7)}};
+    launch_vec_reduce(part, G, 13 * (int)H, vs, 5, st);
+    launch_vec_reduce_strided(part, G, 13 * (int)H, 5 * (int)H, (int)H, in_dim, 8, P(blk, 0, 0), in_dim, st);
+    wgrad(s, wop(c->fd.p, 0, (int)H, 0, nullptr, c->fb.p, 0, (int)H, 0, nullptr, R, (int)H, (int)H, P(blk, 0, 4),
+                 (int)H), c->wpart, st);
+    wgrad(s, wop(c->fc.p, 0, (int)H, 0, nullptr, c->fa.p, 0, (int)H, 0, nullptr, R, (int)H, (int)H, P(blk, 0, 2),
+                 (int)H), c->wpart, st);
+  }
+  HIPCHK(hipGetLastError());
+  if (g_config_error) return fail(XMGN_ERR_UNSUPPORTED, "tile configuration does not fit this kernel");
+  return XMGN_OK;
+  GUARD_END
+}
+
+extern "C" xmgn_status xmgn_grad_accumulate(float* acc, const float* g, int64_t n, xmgn_stream stream) {
+  if (n < 0) return fail(XMGN_ERR_INVALID, "n must be >= 0");
+  if (n > 0 && (!acc || !g)) return fail(XMGN_ERR_INVALID, "NULL argument");
+  launch_accumulate(acc, g, n, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_build_knn(xmgn_ctx* c, const float* pos, int32_t n, const int32_t* level_end,
+                                      int32_t n_levels, int32_t k_intra, int32_t k_cross, xmgn_graph** out,
+                                      xmgn_stream stream) {
+  GUARD_BEGIN
+  if (!out) return fail(XMGN_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (!pos || !level_end) return fail(XMGN_ERR_INVALID, "NULL argument");
+  if (n < 2) return fail(XMGN_ERR_INVALID, "need at least 2 points");
+  if (n_levels < 1 || n_levels > 8) return fail(XMGN_ERR_INVALID, "n_levels must be in [1, 8]");
+  for (int l = 0; l < n_levels; ++l) {
+    if (level_end[l] <= (l ? level_end[l - 1] : 0)) return fail(XMGN_ERR_INVALID, "level_end must increase");
+  }
+  if (level_end[n_levels - 1] != n) return fail(XMGN_ERR_INVALID, "last level_end must equal n");
+  if (k_intra < 1 || k_intra > 16 || k_intra >= level_end[0]) return fail(XMGN_ERR_INVALID, "bad k_intra");
+  if (k_cross < 0 || k_cross > 16 || (n_levels > 1 && k_cross >= level_end[0])) return fail(XMGN_ERR_INVALID, "bad k_cross");
+  if (n_levels * k_intra + (n_levels - 1) * k_cross > 64) return fail(XMGN_ERR_UNSUPPORTED, "too many lists per node");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  int* rp = nullptr;
+  int* col = nullptr;
+  long long E = 0;
+  const char* err = "";
+  const int rc = knn_build(pos, n, level_end, n_levels, k_intra, n_levels > 1 ? k_cross : 0,
+                           &rp, &col, &E, st, &err);
+  if (rc != 0) return fail(rc == -2 ? XMGN_ERR_OOM : XMGN_ERR_HIP, std::string("kNN build failed: ") + err);
+  auto g = std::make_unique<xmgn_graph>();
+  g->n = n;
+  g->row_ptr.resize(n + 1);
+  g->col.resize(E);
+  hipError_t e1 = hipMemcpy(g->row_ptr.data(), rp, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost);
+  hipError_t e2 = E > 0 ? hipMemcpy(g->col.data(), col, (size_t)E * 4, hipMemcpyDeviceToHost) : hipSuccess;
+  (void)hipFree(rp);
+  (void)hipFree(col);
+  if (e1 != hipSuccess || e2 != hipSuccess) return fail(XMGN_ERR_HIP, "copy of the graph to the host failed");
+  *out = g.release();
+  return XMGN_OK;
+  GUARD_END
+}

@@ -1,0 +1,300 @@
+// Auxiliary kernels: weight gradients as row-sums of outer products
+// (split over row chunks, reduced in a fixed order), fixed-order reductions
+// of per-workgroup partial vectors, weight preparation (cast / transpose into
+// the compute type), the masked MSE and gradient accumulation.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace xmgn {
+
+int g_config_error = 0;
+
+// ---------------------------------------------------------------------------
+// wgrad: C[m][n] = sum_r A[r][a0 + m] * B[r][b0 + n].  A workgroup owns one
+// chunk of rows and one 128x128 output block; rows are staged 64 at a time,
+// transposed into LDS so that the row index is the MFMA k dimension.
+// ---------------------------------------------------------------------------
+constexpr int WG_B = 128;  // output block edge
+constexpr int WG_RC = 64;  // rows per LDS stage
+
+template <typename T>
+struct WgLds {
+  static constexpr int PAD = 16 / sizeof(T);
+  static constexpr int LD = WG_RC + PAD;
+};
+
+template <typename T, typename S>
+__device__ __forceinline__ void load4(const S* p, float (&v)[4]) {
+  if constexpr (sizeof(S) == 4) {
+    const float4 x = *(const float4*)p;
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = x.z;
+    v[3] = x.w;
+  } else {
+    const uint2 x = *(const uint2*)p;
+    const S* s = (const S*)&x;
+    v[0] = to_f(s[0]);
+    v[1] = to_f(s[1]);
+    v[2] = to_f(s[2]);
+    v[3] = to_f(s[3]);
+  }
+}
+
+template <typename T, typename S>
+__device__ __forceinline__ void stage_t(T* dst, const S* base, int ld, int col0, const int* idx, int r0, int r_end,
+                                        int c0, int C) {
+  constexpr int LD = WgLds<T>::LD;
+  // unit: (row pair, 4-column chunk), columns fastest for coalesced loads
+  for (int u = threadIdx.x; u < (WG_RC / 2) * (WG_B / 4); u += NTHR) {
+    const int mc = u % (WG_B / 4), rp = u / (WG_B / 4);
+    const int c = c0 + 4 * mc;
+    float v0[4] = {0.f, 0.f, 0.f, 0.f}, v1[4] = {0.f, 0.f, 0.f, 0.f};
+    const int ra = r0 + 2 * rp, rb = ra + 1;
+    if (c < C) {
+      if (ra < r_end) load4<T, S>(base + (size_t)(idx ? idx[ra] : ra) * ld + col0 + c, v0);
+      if (rb < r_end) load4<T, S>(base + (size_t)(idx ? idx[rb] : rb) * ld + col0 + c, v1);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      T* d = dst + (4 * mc + t) * LD + 2 * rp;
+      d[0] = from_f<T>(v0[t]);
+      d[1] = from_f<T>(v1[t]);
+    }
+  }
+}
+
+template <typename T, typename SA, typename SB>
+__global__ __launch_bounds__(NTHR) void k_wgrad(WgradOp op, int rows_per_chunk, int nbm, float* __restrict__ partial) {
+  using V = typename TT<T>::V;
+  constexpr int E = TT<T>::E, KC = 4 * E, LD = WgLds<T>::LD;
+  __shared__ __align__(16) T At[WG_B * LD];
+  __shared__ __align__(16) T Bt[WG_B * LD];
+  const int chunk = blockIdx.x;
+  const int bm = blockIdx.y % nbm, bn = blockIdx.y / nbm;
+  const int m0 = bm * WG_B, nn0 = bn * WG_B;
+  const int r_begin = chunk * rows_per_chunk;
+  const int r_end = min(op.R, r_begin + rows_per_chunk);
+  const int w = wave_id(), wm = w & 1, wn = w >> 1;
+  const int l = lane_id(), li = l & 15, lg = l >> 4;
+  f32x4 acc[4][4];
+  zero_acc(acc);
+  for (int r0 = r_begin; r0 < r_end; r0 += WG_RC) {
+    stage_t<T, SA>(At, (const SA*)op.A, op.lda, op.a0, op.ia, r0, r_end, m0, op.M);
+    stage_t<T, SB>(Bt, (const SB*)op.B, op.ldb, op.b0, op.ib, r0, r_end, nn0, op.N);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < WG_RC; k += KC) {
+      V bfr[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) bfr[nb] = *(const V*)(Bt + (wn * 64 + nb * 16 + li) * LD + k + lg * E);
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        const V a = *(const V*)(At + (wm * 64 + mb * 16 + li) * LD + k + lg * E);
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mma(a, bfr[nb], acc[mb][nb]);
+      }
+    }
+    __syncthreads();
+  }
+  float* out = partial + (size_t)chunk * op.M * op.N;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + mb * 16 + lg * 4 + r;
+        const int n = nn0 + wn * 64 + nb * 16 + li;
+        if (m < op.M && n < op.N) out[(size_t)m * op.N + n] = acc[mb][nb][r];
+      }
+}
+
+__global__ void k_wgrad_reduce(const float* __restrict__ partial, int n_chunks, int M_valid, int N,
+                               float* __restrict__ dst, int ldd, int MN) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M_valid * N) return;
+  const int m = idx / N, n = idx - m * N;
+  float s = 0.f;
+  for (int c = 0; c < n_chunks; ++c) s += partial[(size_t)c * MN + idx];
+  dst[(size_t)m * ldd + n] = s;
+}
+
+static int wgrad_chunks(int R, int* rows_per_chunk) {
+  if (R <= 0) {
+    *rows_per_chunk = WG_RC;
+    return 0;
+  }
+  int target = (R + 1023) / 1024;
+  if (target > 512) target = 512;
+  int rpc = (R + target - 1) / target;
+  rpc = (rpc + WG_RC - 1) / WG_RC * WG_RC;
+  *rows_per_chunk = rpc;
+  return (R + rpc - 1) / rpc;
+}
+
+size_t wgrad_partial_floats(const Shape&, const WgradOp& op) {
+  int rpc;
+  const int nc = wgrad_chunks(op.R, &rpc);
+  return (size_t)(nc > 0 ? nc : 1) * op.M * op.N;
+}
+
+void launch_wgrad(const Shape& s, const WgradOp& op, float* partial, hipStream_t st) {
+  int rpc;
+  const int nc = wgrad_chunks(op.R, &rpc);
+  const int nbm = (op.M + WG_B - 1) / WG_B, nbn = (op.N + WG_B - 1) / WG_B;
+  if (nc > 0) {
+    dim3 grid(nc, nbm * nbn);
+    if (s.prec == 1) {
+      if (op.a_f32 && op.b_f32) k_wgrad<bf16, float, float><<<grid, NTHR, 0, st>>>(op, rpc, nbm, partial);
+      else if (op.a_f32) k_wgrad<bf16, float, bf16><<<grid, NTHR, 0, st>>>(op, rpc, nbm, partial);
+      else if (op.b_f32) k_wgrad<bf16, bf16, float><<<grid, NTHR, 0, st>>>(op, rpc, nbm, partial);
+      else k_wgrad<bf16, bf16, bf16><<<grid, NTHR, 0, st>>>(op, rpc, nbm, partial);
+    } else {
+      k_wgrad<float, float, float><<<grid, NTHR, 0, st>>>(op, rpc, nbm, partial);
+    }
+  }
+  const int tot = op.M_valid * op.N;
+  k_wgrad_reduce<<<(tot + 255) / 256, 256, 0, st>>>(partial, nc, op.M_valid, op.N, op.dst, op.ldd, op.M * op.N);
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order reduction of per-workgroup partial rows.
+// ---------------------------------------------------------------------------
+struct VecSegs {
+  int n;
+  int src[16];
+  int len[16];
+  int inner[16];       // elements per contiguous run
+  int src_stride[16];  // partial-row stride between runs
+  int dst_stride[16];
+  float* dst[16];
+};
+
+__global__ void k_vec_reduce(const float* __restrict__ partial, int G, int row, VecSegs s) {
+  const int seg = blockIdx.y;
+  if (seg >= s.n) return;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < s.len[seg]; j += gridDim.x * blockDim.x) {
+    const int run = j / s.inner[seg], k = j - run * s.inner[seg];
+    const int src = s.src[seg] + run * s.src_stride[seg] + k;
+    float acc = 0.f;
+    for (int g = 0; g < G; ++g) acc += partial[(size_t)g * row + src];
+    s.dst[seg][run * s.dst_stride[seg] + k] = acc;
+  }
+}
+
+void launch_vec_reduce(const float* partial, int G, int row, const VecSeg* segs, int n_seg, hipStream_t st) {
+  VecSegs s{};
+  s.n = n_seg;
+  int maxlen = 1;
+  for (int i = 0; i < n_seg; ++i) {
+    s.src[i] = segs[i].src;
+    s.len[i] = segs[i].len;
+    s.inner[i] = segs[i].len;
+    s.src_stride[i] = 0;
+    s.dst_stride[i] = 0;
+    s.dst[i] = segs[i].dst;
+    if (segs[i].len > maxlen) maxlen = segs[i].len;
+  }
+  k_vec_reduce<<<dim3((maxlen + 255) / 256, n_seg), 256, 0, st>>>(partial, G, row, s);
+}
+
+// Strided variant: dst[c * dst_stride + k] = sum_g partial[g][src + c * src_stride + k],
+// c < runs, k < inner.
+void launch_vec_reduce_strided(const float* partial, int G, int row, int src, int runs, int inner, int src_stride,
+                               float* dst, int dst_stride, hipStream_t st) {
+  VecSegs s{};
+  s.n = 1;
+  s.src[0] = src;
+  s.len[0] = runs * inner;
+  s.inner[0] = inner;
+  s.src_stride[0] = src_stride;
+  s.dst_stride[0] = dst_stride;
+  s.dst[0] = dst;
+  k_vec_reduce<<<dim3((runs * inner + 255) / 256, 1), 256, 0, st>>>(partial, G, row, s);
+}
+
+// ---------------------------------------------------------------------------
+// Weight preparation: cast (and transpose) FP32 parameter matrices into the
+// compute blob.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_prep(const float* __restrict__ params, T* __restrict__ blob, const PrepJob* __restrict__ jobs) {
+  const PrepJob j = jobs[blockIdx.y];
+  const int tot = j.rows * j.cols;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
+    const int i = idx / j.cols, k = idx - i * j.cols;
+    const float v = j.transpose ? params[j.src_off + (int64_t)k * j.src_ld + j.src_col0 + i]
+                                : params[j.src_off + (int64_t)i * j.src_ld + j.src_col0 + k];
+    blob[j.dst_off + (int64_t)i * j.dst_ld + j.dst_col0 + k] = from_f<T>(v);
+  }
+}
+
+void launch_prep(const float* params, void* blob, int prec, const PrepJob* jobs_dev, int n_jobs, hipStream_t st) {
+  if (n_jobs == 0) return;
+  dim3 grid(64, n_jobs);
+  if (prec == 1) k_prep<bf16><<<grid, 256, 0, st>>>(params, (bf16*)blob, jobs_dev);
+  else k_prep<float><<<grid, 256, 0, st>>>(params, (float*)blob, jobs_dev);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_fill(float* p, size_t n, float v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+void launch_fill(float* p, size_t n, float v, hipStream_t st) {
+  if (n == 0) return;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_fill<<<(unsigned)blocks, 256, 0, st>>>(p, n, v);
+}
+
+__global__ void k_accumulate(float* __restrict__ acc, const float* __restrict__ g, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc[i] += g[i];
+}
+void launch_accumulate(float* acc, const float* g, int64_t n, hipStream_t st) {
+  if (n == 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_accumulate<<<(unsigned)blocks, 256, 0, st>>>(acc, g, n);
+}
+
+// Masked MSE over the batch's inner rows: per-workgroup partial sums in a
+// fixed order, then a single-workgroup fixed-order total.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out, const float* __restrict__ target,
+                                             const int* __restrict__ gid, const int* __restrict__ inner, int n_inner,
+                                             int C, double inv_norm, float* __restrict__ d_out,
+                                             float* __restrict__ partial) {
+  __shared__ double red[256];
+  double s = 0.0;
+  const int tot = n_inner * C;
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < tot; idx += gridDim.x * 256) {
+    const int i = idx / C, c = idx - i * C;
+    const size_t o = (size_t)gid[inner[i]] * C + c;
+    const double d = (double)out[o] - (double)target[o];
+    s += d * d;
+    d_out[o] = (float)(2.0 * d * inv_norm);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = (float)(red[0] * inv_norm);
+}
+__global__ void k_sum_partials(const float* __restrict__ partial, int G, float* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += partial[g];
+    out[0] = (float)s;
+  }
+}
+
+void launch_mse(const float* out, const float* target, const int* gid, const int* inner, int n_inner, int out_dim,
+                double inv_norm, float* d_out, float* partial, int G, float* loss, hipStream_t st) {
+  k_mse<<<G, 256, 0, st>>>(out, target, gid, inner, n_inner, out_dim, inv_norm, d_out, partial);
+  k_sum_partials<<<1, 64, 0, st>>>(partial, G, loss);
+}
+
+}  // namespace xmgn

@@ -1,0 +1,287 @@
+// Device building blocks shared by the xmgn kernels (gfx950, wave64).
+//
+// A workgroup is 256 threads = 4 waves.  A row tile of MT rows is staged in
+// LDS; each wave owns a quarter of the output columns of every GEMM and all
+// MT rows.  Matrix products use the 16x16 MFMA instructions:
+//   BF16 : v_mfma_f32_16x16x32_bf16 (8 bf16 per lane per operand)
+//   FP32 : v_mfma_f32_16x16x4_f32   (1 float per lane; 4 issued per 16 bytes)
+// Each lane loads 16 contiguous bytes of an A row and of a B column (B is
+// given as W[n][k], i.e. k contiguous).  Lane group g = lane / 16 holds the
+// k slice [g*E, g*E + E) of every 4*E-wide k chunk, identically for A and B,
+// so the products sum over exactly the chunk's k range.
+// Accumulator layout (16x16 block, 4 floats per lane):
+//   value r of lane l is C[row = 4*(l/16) + r][col = l % 16].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xmgn {
+
+typedef __bf16 bf16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+constexpr int NTHR = 256;
+constexpr int NWAVE = 4;
+
+template <typename T>
+struct TT;
+template <>
+struct TT<bf16> {
+  static constexpr int E = 8;  // elements per 16-byte fragment
+  using V = bf16x8;
+};
+template <>
+struct TT<float> {
+  static constexpr int E = 4;
+  using V = f32x4;
+};
+
+__device__ __forceinline__ f32x4 mma(const bf16x8& a, const bf16x8& b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma(const f32x4& a, const f32x4& b, f32x4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], c, 0, 0, 0);
+  return c;
+}
+
+__device__ __forceinline__ float to_f(float x) { return x; }
+__device__ __forceinline__ float to_f(bf16 x) { return (float)x; }
+template <typename T>
+__device__ __forceinline__ T from_f(float x);
+template <>
+__device__ __forceinline__ float from_f<float>(float x) { return x; }
+template <>
+__device__ __forceinline__ bf16 from_f<bf16>(float x) { return (bf16)x; }
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+// Activation and its derivative (0 = ReLU, 1 = SiLU).
+template <int ACT>
+__device__ __forceinline__ float act_f(float a) {
+  if constexpr (ACT == 0) {
+    return a > 0.f ? a : 0.f;
+  } else {
+    return a / (1.f + __expf(-a));
+  }
+}
+template <int ACT>
+__device__ __forceinline__ float act_d(float a) {
+  if constexpr (ACT == 0) {
+    return a > 0.f ? 1.f : 0.f;
+  } else {
+    float s = 1.f / (1.f + __expf(-a));
+    return s * (1.f + a * (1.f - s));
+  }
+}
+
+// acc[MB][NB] += A * B over k in [0, K):  A rows [0, 16 MB) from LDS (row
+// stride LDA elements), B[k][n] = W[n][k] with W in global memory (row stride
+// ldw elements); the wave's output columns are [n0, n0 + 16 NB).
+template <typename T, int MB, int NB, int K, int LDA>
+__device__ __forceinline__ void wave_gemm(f32x4 (&acc)[MB][NB], const T* A,
+                                          const T* __restrict__ W, int ldw, int n0) {
+  using V = typename TT<T>::V;
+  constexpr int E = TT<T>::E;
+  constexpr int KC = 4 * E;
+  static_assert(K % KC == 0, "K must be a multiple of the MFMA k chunk");
+  const int l = lane_id(), li = l & 15, lg = l >> 4;
+  const T* wrow[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) wrow[nb] = W + (size_t)(n0 + nb * 16 + li) * ldw + lg * E;
+  const T* arow = A + li * LDA + lg * E;
+#pragma unroll 4
+  for (int k = 0; k < K; k += KC) {
+    V b[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) b[nb] = *(const V*)(wrow[nb] + k);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      V a = *(const V*)(arow + mb * 16 * LDA + k);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mma(a, b[nb], acc[mb][nb]);
+    }
+  }
+}
+
+template <int MB, int NB>
+__device__ __forceinline__ void zero_acc(f32x4 (&acc)[MB][NB]) {
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Row / column of value r of block (mb, nb) for this lane.
+__device__ __forceinline__ int acc_row(int mb, int r) { return mb * 16 + (lane_id() >> 4) * 4 + r; }
+__device__ __forceinline__ int acc_col(int n0, int nb) { return n0 + nb * 16 + (lane_id() & 15); }
+
+// Sum over the 16 lanes that share a lane group (same rows, 16 columns).
+__device__ __forceinline__ float sum16(float s) {
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  s += __shfl_xor(s, 4);
+  s += __shfl_xor(s, 8);
+  return s;
+}
+// Sum over the 4 lane groups (same column, 4 x 4 rows).
+__device__ __forceinline__ float sum_groups(float s) {
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  return s;
+}
+
+// Full-row sums of x over all columns of all 4 waves.  red: LDS float
+// [NWAVE][MT].  Returns out[mb][r] = sum over the row acc_row(mb, r).
+// Contains two barriers.
+template <int MB, int NB, int MT>
+__device__ __forceinline__ void row_sum(const f32x4 (&x)[MB][NB], float* red, float (&out)[MB][4]) {
+  const int w = wave_id(), l = lane_id();
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float s = 0.f;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) s += x[mb][nb][r];
+      s = sum16(s);
+      if ((l & 15) == 0) red[w * MT + acc_row(mb, r)] = s;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = acc_row(mb, r);
+      out[mb][r] = (red[row] + red[MT + row]) + (red[2 * MT + row] + red[3 * MT + row]);
+    }
+  __syncthreads();
+}
+
+// LayerNorm of the rows of u (in place -> xhat), returning inv std per row.
+// Statistics in FP32, two passes (mean, then mean of squared deviations).
+template <int MB, int NB, int MT, int H>
+__device__ __forceinline__ void ln_normalize(f32x4 (&u)[MB][NB], float* red, float eps,
+                                             float (&inv)[MB][4]) {
+  float s[MB][4];
+  row_sum<MB, NB, MT>(u, red, s);
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) u[mb][nb][r] -= s[mb][r] * (1.f / H);
+  f32x4 sq[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sq[mb][nb][r] = u[mb][nb][r] * u[mb][nb][r];
+  row_sum<MB, NB, MT>(sq, red, s);
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) inv[mb][r] = rsqrtf(s[mb][r] * (1.f / H) + eps);
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) u[mb][nb][r] *= inv[mb][r];
+}
+
+// Column sums of x over all rows held by the wave, accumulated into acc[nb]
+// (every lane of a column ends with the same total).
+template <int MB, int NB>
+__device__ __forceinline__ void col_accumulate(const f32x4 (&x)[MB][NB], float (&acc)[NB]) {
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    float s = 0.f;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) s += (x[mb][nb][0] + x[mb][nb][1]) + (x[mb][nb][2] + x[mb][nb][3]);
+    acc[nb] += sum_groups(s);
+  }
+}
+
+// Store the accumulator (as T) into an LDS tile with row stride LD.
+template <typename T, int MB, int NB, int LD>
+__device__ __forceinline__ void acc_to_lds(const f32x4 (&x)[MB][NB], T* dst, int n0) {
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[acc_row(mb, r) * LD + acc_col(n0, nb)] = from_f<T>(x[mb][nb][r]);
+}
+
+// Copy `rows` rows of `width` elements from an LDS tile (stride LD) to global
+// rows dst + row_index(i) * ld_dst, 16 bytes per thread-step.
+template <typename T, int LD, typename RowFn>
+__device__ __forceinline__ void lds_rows_to_global(const T* src, int rows, int width, T* dst,
+                                                   size_t ld_dst, RowFn row_index) {
+  constexpr int E = 16 / sizeof(T);
+  const int cpr = width / E;
+  for (int c = threadIdx.x; c < rows * cpr; c += NTHR) {
+    const int i = c / cpr, q = c - i * cpr;
+    *(uint4*)(dst + (size_t)row_index(i) * ld_dst + q * E) = *(const uint4*)(src + i * LD + q * E);
+  }
+}
+
+// Copy rows from global into an LDS tile (16-byte steps), zero-filling rows
+// >= rows up to MT.
+template <typename T, int LD, int MT, typename SrcFn>
+__device__ __forceinline__ void global_rows_to_lds(T* dst, int rows, int width, int col0, SrcFn src_row) {
+  constexpr int E = 16 / sizeof(T);
+  const int cpr = width / E;
+  for (int c = threadIdx.x; c < MT * cpr; c += NTHR) {
+    const int i = c / cpr, q = c - i * cpr;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (i < rows) v = *(const uint4*)(src_row(i) + q * E);
+    *(uint4*)(dst + i * LD + col0 + q * E) = v;
+  }
+}
+
+// FP32 global rows converted into a T tile in LDS (8 floats per step).
+template <typename T, int LD, int MT, typename SrcFn>
+__device__ __forceinline__ void global_f32_rows_to_lds(T* dst, int rows, int width, int col0, SrcFn src_row) {
+  const int cpr = width / 4;
+  for (int c = threadIdx.x; c < MT * cpr; c += NTHR) {
+    const int i = c / cpr, q = c - i * cpr;
+    float4 v = {0.f, 0.f, 0.f, 0.f};
+    if (i < rows) v = *(const float4*)(src_row(i) + q * 4);
+    T* d = dst + i * LD + col0 + q * 4;
+    d[0] = from_f<T>(v.x);
+    d[1] = from_f<T>(v.y);
+    d[2] = from_f<T>(v.z);
+    d[3] = from_f<T>(v.w);
+  }
+}
+
+// Persistent-grid tile schedule.  The workgroups of the grid are dealt
+// round-robin to the 8 XCDs (workgroup b runs on XCD b % 8); each XCD takes a
+// contiguous eighth of the tiles so that neighbouring tiles, which share
+// gathered node rows, meet in the same L2.  Tiles of an XCD are taken in
+// order by its workgroups.  The mapping depends only on (n_tiles, grid), so
+// the work of each workgroup -- and every partial sum -- is deterministic.
+struct TileSched {
+  int begin, end, step;
+  __device__ TileSched(int n_tiles) {
+    const int G = gridDim.x, b = blockIdx.x;
+    const int x = b & 7, j = b >> 3;
+    const int per_x = (G + 7 - x) >> 3;  // workgroups on XCD x
+    const int t0 = (int)(((long long)n_tiles * x) >> 3);
+    const int t1 = (int)(((long long)n_tiles * (x + 1)) >> 3);
+    begin = t0 + j;
+    end = t1;
+    step = per_x;
+  }
+};
+
+}  // namespace xmgn

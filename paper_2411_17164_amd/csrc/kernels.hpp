@@ -1,0 +1,179 @@
+// Kernel argument blocks and launcher declarations of the xmgn library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xmgn {
+
+// Set by a launcher when the requested tile configuration does not fit the
+// hardware (LDS); the host turns it into XMGN_ERR_UNSUPPORTED.
+extern int g_config_error;
+
+// Device view of a batch (disjoint union of partitions).
+struct BatchView {
+  int n;                 // nodes
+  int E;                 // edges
+  const int* gid;        // [n] global node id
+  const int* row_ptr;    // [n+1] receiver CSR
+  const int* col;        // [E] sender (batch index)
+  const int* recv;       // [E] receiver (batch index)
+  const int* csc_ptr;    // [n+1] sender CSR
+  const int* csc_edge;   // [E] CSR edge of each sender slot
+  const int* etiles;     // [n_etiles+1] receiver bounds of edge tiles
+  int n_etiles;
+  const int* inner;      // [n_inner] batch rows of inner nodes
+  int n_inner;
+};
+
+// Per-MLP weight views.  W* are the compute-type copies ([out][in]);
+// W*T are transposes ([in][out]) used by the backward products; vectors are
+// FP32 views into the parameter blob.
+struct MlpW {
+  const void* W1;
+  const void* W2;
+  const void* W3;
+  const void* W1T;  // edge: [H][H] block of W1^T for the e input; node/dec: full W1^T
+  const void* W2T;
+  const void* W3T;
+  const void* Brs;  // edge layers: [H][2H] = [W1_r^T | W1_s^T]
+  const float* W1f; // FP32 first-layer weights (encoders) / last layer (decoder)
+  const float* b1;
+  const float* b2;
+  const float* b3;
+  const float* gamma;
+  const float* beta;
+};
+
+struct Shape {
+  int H;
+  int prec;     // 0 fp32, 1 bf16
+  int act;      // 0 relu, 1 silu
+  int agg;      // 0 message, 1 edge
+  int mt_edge;  // rows per edge tile
+  int mt_node;  // rows per node tile
+  int grid;     // persistent grid (workgroups)
+  float eps;
+};
+
+struct EdgeNorm {
+  float mu[4];
+  float sd[4];
+};
+
+// ---- forward ----
+void launch_enc_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const float* node_in,
+                         int in_dim, void* h0, hipStream_t st);
+void launch_enc_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const float* pos,
+                         EdgeNorm en, void* e0, hipStream_t st);
+void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h,
+                     const void* e, void* e_out, float* m, hipStream_t st);
+void launch_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h,
+                     const float* m, void* h_out, hipStream_t st);
+void launch_dec_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, float* out,
+                    int out_dim, hipStream_t st);
+
+// ---- backward ----
+struct EdgeBwdOut {
+  float* de_out;   // [E][H]
+  float* S_r;      // [n][H] receiver sums of da
+  void* da;        // [E][H] T
+  void* du;        // [E][H] T
+  void* z;         // [E][H] T
+  float* partial;  // [grid][4H]: db1, db2, dgamma, dbeta
+};
+void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
+                     const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st);
+
+struct NodeBwdOut {
+  float* dh_mid;   // [n][H]
+  float* dm;       // [n][H]
+  void* da;        // [n][H] T
+  void* du;        // [n][H] T
+  void* z;         // [n][H] T
+  float* partial;  // [grid][4H]
+};
+void launch_node_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h,
+                     const float* m, const float* dh_in, const NodeBwdOut& o, hipStream_t st);
+// dh_out = dh_mid + [S_r | S_s] * [W1_r ; W1_s]  (edge-layer input gradients)
+void launch_node_dh(const Shape& s, const BatchView& b, const MlpW& w, const float* dh_mid,
+                    const float* S_r, const float* S_s, float* dh_out, hipStream_t st);
+void launch_sender_sum(const Shape& s, const BatchView& b, const void* da, float* S_s, hipStream_t st);
+
+struct DecBwdOut {
+  float* dh;       // [n][H], rows of inner nodes written (caller zeroes the rest)
+  void* z1;        // [n_inner][H] T
+  void* z2;
+  void* da1;
+  void* da2;
+  float* dy;       // [n_inner][16]
+  float* partial;  // [grid][2H + 16]
+};
+void launch_dec_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h,
+                    const float* d_out, int out_dim, const DecBwdOut& o, hipStream_t st);
+
+struct EncBwdOut {
+  void* z1;
+  void* z2;
+  void* da2;
+  void* du3;
+  float* partial;  // [grid][5H + 8H]: db1 db2 db3 dgamma dbeta dW1[H][8]
+};
+void launch_enc_node_bwd(const Shape& s, const BatchView& b, const MlpW& w, const float* node_in,
+                         int in_dim, const float* dh0, const EncBwdOut& o, hipStream_t st);
+void launch_enc_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const float* pos,
+                         EdgeNorm en, const float* de0, const EncBwdOut& o, hipStream_t st);
+
+// ---- auxiliary ----
+// C[m][n] = sum_r A[ia(r)][a0 + m] * B[ib(r)][b0 + n] over r < R; partial
+// sums per row chunk, then dst[m * ldd + n] = sum over chunks (m < M_valid).
+struct WgradOp {
+  const void* A;
+  int a_f32;  // 1: A is FP32, else compute type
+  int lda, a0;
+  const int* ia;
+  const void* B;
+  int b_f32;
+  int ldb, b0;
+  const int* ib;
+  int R, M, N, M_valid;
+  float* dst;
+  int ldd;
+};
+size_t wgrad_partial_floats(const Shape& s, const WgradOp& op);
+void launch_wgrad(const Shape& s, const WgradOp& op, float* partial, hipStream_t st);
+
+struct VecSeg {
+  int src;  // offset in the partial row
+  int len;
+  float* dst;
+};
+// dst[j] = sum over g < G of partial[g * row + src + j] for every segment.
+void launch_vec_reduce(const float* partial, int G, int row, const VecSeg* segs, int n_seg,
+                       hipStream_t st);
+
+struct PrepJob {
+  int64_t src_off;   // element offset in the FP32 params
+  int src_ld;        // row stride of the source matrix
+  int src_col0;      // first source column
+  int transpose;     // 0: dst[i][j] = src[i][col0 + j]; 1: dst[i][j] = src[j][col0 + i]
+  int64_t dst_off;   // element offset in the compute blob
+  int dst_ld;
+  int dst_col0;
+  int rows, cols;
+};
+void launch_prep(const float* params, void* blob, int prec, const PrepJob* jobs_dev, int n_jobs,
+                 hipStream_t st);
+
+void launch_fill(float* p, size_t n, float v, hipStream_t st);
+void launch_accumulate(float* acc, const float* g, int64_t n, hipStream_t st);
+void launch_mse(const float* out, const float* target, const int* gid, const int* inner, int n_inner,
+                int out_dim, double inv_norm, float* d_out, float* partial, int G, float* loss,
+                hipStream_t st);
+
+// ---- kNN ----
+int knn_build(const float* pos, int n, const int* level_end, int n_levels, int k_intra,
+              int k_cross, int** row_ptr_out, int** col_out, long long* n_edges, hipStream_t st,
+              const char** err);
+
+}  // namespace xmgn

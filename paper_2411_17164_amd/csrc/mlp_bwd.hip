@@ -1,0 +1,836 @@
+// Backward kernels: hand-written adjoints of the processor, encoders and
+// decoder.  Every layer is recomputed from its checkpoint (h^l, e^l, m^l)
+// inside the kernel (activation checkpointing), so only layer inputs are kept
+// between forward and backward.
+//
+// Edge adjoint, for v = LN(u), u = W2 z + b2, z = act(a), a = W1 x + b1,
+// x = [h_r ; h_s ; e]:
+//   dv   = dm_r + de'_k                (v feeds m_r and the residual e')
+//   du   = LN^T(dv),  dz = W2^T du,  da = dz * act'(a)
+//   de_k = de'_k + (W1^T da)[2H:3H]     (plus dm_r when m sums e')
+// The node-input parts of W1^T da are linear in da, so they are summed over
+// edges first:  S_r = sum_{in(r)} da_k,  S_s = sum_{out(s)} da_k,
+//   dh_r += W1_r^T S_r,  dh_s += W1_s^T S_s
+// (the same value as summing W1^T da_k per edge, re-associated).  S_r is a
+// tile-local segmented sum; S_s a sender-ordered (CSC) sum.  Weight
+// gradients are row-sums of outer products and are formed by the wgrad
+// kernel from the per-row factors written here; bias / LayerNorm gradients
+// are per-workgroup column sums reduced in a fixed order.  No float atomics.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace xmgn {
+
+template <typename T, int H>
+struct BD {
+  static constexpr int PAD = 16 / sizeof(T);
+  static constexpr int LDH = H + PAD;
+  static constexpr int LD2 = 2 * H + PAD;
+  static constexpr int LD3 = 3 * H + PAD;
+  static constexpr int LDF = H + 4;
+  static constexpr int NB = H / 64;
+  static constexpr int CPW = H / 4;
+};
+
+// Copy an FP32 [rows][H] block from global into an FP32 LDS tile (zero fill).
+template <int H, int LDF, int MT, typename SrcFn>
+__device__ __forceinline__ void f32_rows_to_lds(float* dst, int rows, SrcFn src) {
+  for (int c = threadIdx.x; c < MT * (H / 4); c += NTHR) {
+    const int i = c / (H / 4), q = c - i * (H / 4);
+    float4 v = {0.f, 0.f, 0.f, 0.f};
+    if (i < rows) v = src(i, q);
+    *(float4*)(dst + i * LDF + 4 * q) = v;
+  }
+}
+
+template <int MB, int NB, int LDF>
+__device__ __forceinline__ void acc_to_ldsf(const f32x4 (&x)[MB][NB], float* dst, int n0) {
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[acc_row(mb, r) * LDF + acc_col(n0, nb)] = x[mb][nb][r];
+}
+
+// LayerNorm adjoint in registers.  On entry xh = xhat, dv = upstream
+// gradient (C layout); on exit dv holds du.  Accumulates dgamma, dbeta.
+template <int MB, int NB, int MT, int H>
+__device__ __forceinline__ void ln_backward(const f32x4 (&xh)[MB][NB], f32x4 (&dv)[MB][NB], const float (&inv)[MB][4],
+                                            const float* gamma, int n0, float* red, float (&cg)[NB],
+                                            float (&cbt)[NB]) {
+  f32x4 g[MB][NB], gx[MB][NB], t[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const float gm = gamma[acc_col(n0, nb)];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        t[mb][nb][r] = dv[mb][nb][r] * xh[mb][nb][r];
+        g[mb][nb][r] = dv[mb][nb][r] * gm;
+        gx[mb][nb][r] = g[mb][nb][r] * xh[mb][nb][r];
+      }
+    }
+  col_accumulate(t, cg);
+  col_accumulate(dv, cbt);
+  float sg[MB][4], sgx[MB][4];
+  row_sum<MB, NB, MT>(g, red, sg);
+  row_sum<MB, NB, MT>(gx, red, sgx);
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        dv[mb][nb][r] = (g[mb][nb][r] - sg[mb][r] * (1.f / H) - xh[mb][nb][r] * (sgx[mb][r] * (1.f / H))) * inv[mb][r];
+}
+
+template <int NB>
+__device__ __forceinline__ void write_partial(float* p, int n0, const float (&v)[NB]) {
+  if ((lane_id() >> 4) == 0)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) p[acc_col(n0, nb)] = v[nb];
+}
+
+// ---------------------------------------------------------------------------
+// Edge adjoint (with recompute).
+// ---------------------------------------------------------------------------
+template <typename T, int H, int MT, int ACT, int AGG>
+__global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T* __restrict__ h,
+                                                   const T* __restrict__ e, const float* __restrict__ de_in,
+                                                   const float* __restrict__ dm, EdgeBwdOut o, float eps) {
+  using D = BD<T, H>;
+  constexpr int MB = MT / 16, NB = D::NB;
+  constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
+  constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
+  __shared__ __align__(16) unsigned char smem[XS + ZS + NWAVE * MT * 4 + 2 * MT * 4];
+  T* xs = (T*)smem;
+  float* ft = (float*)smem;
+  T* zs = (T*)(smem + XS);
+  float* red = (float*)(smem + XS + ZS);
+  int* rs = (int*)(red + NWAVE * MT);
+  const T* W1 = (const T*)w.W1;
+  const T* W2 = (const T*)w.W2;
+  const T* W2T = (const T*)w.W2T;
+  const T* W1Te = (const T*)w.W1T;
+  const int n0 = wave_id() * D::CPW;
+  float cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
+
+  TileSched sch(b.n_etiles);
+  for (int t = sch.begin; t < sch.end; t += sch.step) {
+    const int r0 = b.etiles[t], r1 = b.etiles[t + 1];
+    const int e0 = b.row_ptr[r0], ne = b.row_ptr[r1] - e0;
+    int* ss = rs + MT;
+    if (threadIdx.x < MT) {
+      const bool ok = (int)threadIdx.x < ne;
+      rs[threadIdx.x] = ok ? b.recv[e0 + threadIdx.x] : 0;
+      ss[threadIdx.x] = ok ? b.col[e0 + threadIdx.x] : 0;
+    }
+    __syncthreads();
+    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, 0, [&](int i) { return h + (size_t)rs[i] * H; });
+    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, H, [&](int i) { return h + (size_t)ss[i] * H; });
+    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, 2 * H, [&](int i) { return e + (size_t)(e0 + i) * H; });
+    __syncthreads();
+
+    // recompute: a, z, u, xhat
+    f32x4 a[MB][NB];
+    zero_acc(a);
+    wave_gemm<T, MB, NB, 3 * H, D::LD3>(a, xs, W1, 3 * H, n0);
+    f32x4 x[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b1[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          a[mb][nb][r] += bb;
+          x[mb][nb][r] = act_f<ACT>(a[mb][nb][r]);
+        }
+      }
+    acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
+    __syncthreads();
+    zero_acc(x);
+    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b2[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[mb][nb][r] += bb;
+      }
+    float inv[MB][4];
+    ln_normalize<MB, NB, MT, H>(x, red, eps, inv);  // x = xhat
+
+    // upstream gradient dv = dm_r + de'_k  (FP32 tile over the dead gather)
+    f32_rows_to_lds<H, D::LDF, MT>(ft, ne, [&](int i, int q) {
+      float4 v = *(const float4*)(dm + (size_t)rs[i] * H + 4 * q);
+      if (de_in) {
+        const float4 d = *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q);
+        v.x += d.x;
+        v.y += d.y;
+        v.z += d.z;
+        v.w += d.w;
+      }
+      return v;
+    });
+    lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.z + (size_t)e0 * H, H, [](int i) { return i; });
+    __syncthreads();
+    f32x4 g[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[mb][nb][r] = ft[acc_row(mb, r) * D::LDF + acc_col(n0, nb)];
+    ln_backward<MB, NB, MT, H>(x, g, inv, w.gamma, n0, red, cg, cbt);  // g = du (barriers inside)
+    col_accumulate(g, cb2);
+    acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
+    __syncthreads();
+    lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.du + (size_t)e0 * H, H, [](int i) { return i; });
+    // dz = W2^T du ; da = dz * act'(a)
+    zero_acc(x);
+    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2T, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a[mb][nb][r]);
+    col_accumulate(x, cb1);
+    __syncthreads();
+    acc_to_ldsf<MB, NB, D::LDF>(x, ft, n0);
+    acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
+    __syncthreads();
+    // S_r: receiver-segment sums of da (FP32, ascending sender order)
+    const int nr = r1 - r0;
+    for (int task = threadIdx.x; task < nr * (H / 4); task += NTHR) {
+      const int rl = task / (H / 4), q = task - rl * (H / 4);
+      const int lo = b.row_ptr[r0 + rl] - e0, hi = b.row_ptr[r0 + rl + 1] - e0;
+      float4 s = {0.f, 0.f, 0.f, 0.f};
+      for (int i = lo; i < hi; ++i) {
+        const float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
+        s.x += v.x;
+        s.y += v.y;
+        s.z += v.z;
+        s.w += v.w;
+      }
+      *(float4*)(o.S_r + (size_t)(r0 + rl) * H + 4 * q) = s;
+    }
+    lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.da + (size_t)e0 * H, H, [](int i) { return i; });
+    // de = de' (+ dm_r) + (W1^T da)[2H:3H]
+    zero_acc(g);
+    wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1Te, H, n0);
+    __syncthreads();
+    acc_to_ldsf<MB, NB, D::LDF>(g, ft, n0);
+    __syncthreads();
+    for (int c = threadIdx.x; c < ne * (H / 4); c += NTHR) {
+      const int i = c / (H / 4), q = c - i * (H / 4);
+      float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
+      if (de_in) {
+        const float4 d = *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q);
+        v.x += d.x;
+        v.y += d.y;
+        v.z += d.z;
+        v.w += d.w;
+      }
+      if (AGG) {
+        const float4 d = *(const float4*)(dm + (size_t)rs[i] * H + 4 * q);
+        v.x += d.x;
+        v.y += d.y;
+        v.z += d.z;
+        v.w += d.w;
+      }
+      *(float4*)(o.de_out + (size_t)(e0 + i) * H + 4 * q) = v;
+    }
+    __syncthreads();
+  }
+  float* p = o.partial + (size_t)blockIdx.x * 4 * H;
+  write_partial<NB>(p, n0, cb1);
+  write_partial<NB>(p + H, n0, cb2);
+  write_partial<NB>(p + 2 * H, n0, cg);
+  write_partial<NB>(p + 3 * H, n0, cbt);
+}
+
+// ---------------------------------------------------------------------------
+// Node adjoint (with recompute).  dh_mid = dh' + (W1^T da)[0:H], dm = (W1^T da)[H:2H].
+// ---------------------------------------------------------------------------
+template <typename T, int H, int MT, int ACT>
+__global__ __launch_bounds__(NTHR) void k_node_bwd(int n, MlpW w, const T* __restrict__ h, const float* __restrict__ m,
+                                                   const float* __restrict__ dh_in, NodeBwdOut o, float eps) {
+  using D = BD<T, H>;
+  constexpr int MB = MT / 16, NB = D::NB;
+  constexpr size_t XS = (size_t)MT * D::LD2 * sizeof(T);
+  constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
+  __shared__ __align__(16) unsigned char smem[XS + ZS + NWAVE * MT * 4];
+  T* xs = (T*)smem;
+  float* ft = (float*)smem;
+  T* zs = (T*)(smem + XS);
+  float* red = (float*)(smem + XS + ZS);
+  const T* W1 = (const T*)w.W1;
+  const T* W2 = (const T*)w.W2;
+  const T* W2T = (const T*)w.W2T;
+  const T* W1T = (const T*)w.W1T;
+  const int n0 = wave_id() * D::CPW;
+  float cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
+  const int n_tiles = (n + MT - 1) / MT;
+
+  TileSched sch(n_tiles);
+  for (int t = sch.begin; t < sch.end; t += sch.step) {
+    const int row0 = t * MT, nr = min(MT, n - row0);
+    global_rows_to_lds<T, D::LD2, MT>(xs, nr, H, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
+    global_f32_rows_to_lds<T, D::LD2, MT>(xs, nr, H, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
+    __syncthreads();
+    f32x4 a[MB][NB], x[MB][NB];
+    zero_acc(a);
+    wave_gemm<T, MB, NB, 2 * H, D::LD2>(a, xs, W1, 2 * H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b1[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          a[mb][nb][r] += bb;
+          x[mb][nb][r] = act_f<ACT>(a[mb][nb][r]);
+        }
+      }
+    acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
+    __syncthreads();
+    zero_acc(x);
+    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b2[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[mb][nb][r] += bb;
+      }
+    float inv[MB][4];
+    ln_normalize<MB, NB, MT, H>(x, red, eps, inv);
+    f32_rows_to_lds<H, D::LDF, MT>(ft, nr, [&](int i, int q) { return *(const float4*)(dh_in + (size_t)(row0 + i) * H + 4 * q); });
+    lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z + (size_t)row0 * H, H, [](int i) { return i; });
+    __syncthreads();
+    f32x4 g[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[mb][nb][r] = ft[acc_row(mb, r) * D::LDF + acc_col(n0, nb)];
+    ln_backward<MB, NB, MT, H>(x, g, inv, w.gamma, n0, red, cg, cbt);
+    col_accumulate(g, cb2);
+    acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
+    __syncthreads();
+    lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.du + (size_t)row0 * H, H, [](int i) { return i; });
+    zero_acc(x);
+    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2T, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a[mb][nb][r]);
+    col_accumulate(x, cb1);
+    __syncthreads();
+    acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
+    __syncthreads();
+    lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.da + (size_t)row0 * H, H, [](int i) { return i; });
+    zero_acc(g);
+    wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1T, H, n0);            // -> dh part
+    zero_acc(x);
+    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W1T + (size_t)H * H, H, n0);  // -> dm
+    acc_to_ldsf<MB, NB, D::LDF>(g, ft, n0);
+    __syncthreads();
+    for (int c = threadIdx.x; c < nr * (H / 4); c += NTHR) {
+      const int i = c / (H / 4), q = c - i * (H / 4);
+      float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
+      const float4 d = *(const float4*)(dh_in + (size_t)(row0 + i) * H + 4 * q);
+      v.x += d.x;
+      v.y += d.y;
+      v.z += d.z;
+      v.w += d.w;
+      *(float4*)(o.dh_mid + (size_t)(row0 + i) * H + 4 * q) = v;
+    }
+    __syncthreads();
+    acc_to_ldsf<MB, NB, D::LDF>(x, ft, n0);
+    __syncthreads();
+    for (int c = threadIdx.x; c < nr * (H / 4); c += NTHR) {
+      const int i = c / (H / 4), q = c - i * (H / 4);
+      *(float4*)(o.dm + (size_t)(row0 + i) * H + 4 * q) = *(const float4*)(ft + i * D::LDF + 4 * q);
+    }
+    __syncthreads();
+  }
+  float* p = o.partial + (size_t)blockIdx.x * 4 * H;
+  write_partial<NB>(p, n0, cb1);
+  write_partial<NB>(p + H, n0, cb2);
+  write_partial<NB>(p + 2 * H, n0, cg);
+  write_partial<NB>(p + 3 * H, n0, cbt);
+}
+
+// dh_out = dh_mid + [S_r | S_s] B_rs^T, B_rs = [W1_r^T | W1_s^T] ([H][2H]).
+template <typename T, int H, int MT>
+__global__ __launch_bounds__(NTHR) void k_node_dh(int n, const T* __restrict__ Brs, const float* __restrict__ dh_mid,
+                                                  const float* __restrict__ S_r, const float* __restrict__ S_s,
+                                                  float* __restrict__ dh_out) {
+  using D = BD<T, H>;
+  constexpr int MB = MT / 16, NB = D::NB;
+  constexpr size_t XS = (size_t)MT * D::LD2 * sizeof(T);
+  __shared__ __align__(16) unsigned char smem[XS + (size_t)MT * D::LDF * 4];
+  T* xs = (T*)smem;
+  float* ft = (float*)(smem + XS);
+  const int n0 = wave_id() * D::CPW;
+  const int n_tiles = (n + MT - 1) / MT;
+  TileSched sch(n_tiles);
+  for (int t = sch.begin; t < sch.end; t += sch.step) {
+    const int row0 = t * MT, nr = min(MT, n - row0);
+    global_f32_rows_to_lds<T, D::LD2, MT>(xs, nr, H, 0, [&](int i) { return S_r + (size_t)(row0 + i) * H; });
+    global_f32_rows_to_lds<T, D::LD2, MT>(xs, nr, H, H, [&](int i) { return S_s + (size_t)(row0 + i) * H; });
+    __syncthreads();
+    f32x4 acc[MB][NB];
+    zero_acc(acc);
+    wave_gemm<T, MB, NB, 2 * H, D::LD2>(acc, xs, Brs, 2 * H, n0);
+    acc_to_ldsf<MB, NB, D::LDF>(acc, ft, n0);
+    __syncthreads();
+    for (int c = threadIdx.x; c < nr * (H / 4); c += NTHR) {
+      const int i = c / (H / 4), q = c - i * (H / 4);
+      float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
+      const float4 d = *(const float4*)(dh_mid + (size_t)(row0 + i) * H + 4 * q);
+      v.x += d.x;
+      v.y += d.y;
+      v.z += d.z;
+      v.w += d.w;
+      *(float4*)(dh_out + (size_t)(row0 + i) * H + 4 * q) = v;
+    }
+    __syncthreads();
+  }
+}
+
+// S_s[s] = sum over the out-edges of s (CSC order: ascending receiver) of da.
+// One wave per sender; each lane owns H/64 consecutive columns.
+template <typename T, int H>
+__global__ __launch_bounds__(NTHR) void k_sender_sum(int n, const int* __restrict__ csc_ptr, const int* __restrict__ csc_edge,
+                                                     const T* __restrict__ da, float* __restrict__ S_s) {
+  constexpr int C = H / 64;
+  const int l = lane_id();
+  const int nw = gridDim.x * NWAVE;
+  for (int s = blockIdx.x * NWAVE + wave_id(); s < n; s += nw) {
+    const int lo = csc_ptr[s], hi = csc_ptr[s + 1];
+    float acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.f;
+    for (int j = lo; j < hi; ++j) {
+      const T* row = da + (size_t)csc_edge[j] * H + l * C;
+      if constexpr (sizeof(T) == 2 && C == 2) {
+        const bf16x2 v = *(const bf16x2*)row;
+        acc[0] += (float)v[0];
+        acc[1] += (float)v[1];
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] += to_f(row[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) S_s[(size_t)s * H + l * C + c] = acc[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decoder adjoint on inner rows: dy -> dz2 = W3^T dy, da2, dz1 = W2^T da2,
+// da1, dh = W1^T da1.  Writes the factors of the weight gradients.
+// ---------------------------------------------------------------------------
+template <typename T, int H, int MT, int ACT>
+__global__ __launch_bounds__(NTHR) void k_dec_bwd(BatchView b, MlpW w, const T* __restrict__ h,
+                                                  const float* __restrict__ d_out, int out_dim, DecBwdOut o) {
+  using D = BD<T, H>;
+  constexpr int MB = MT / 16, NB = D::NB;
+  constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  constexpr size_t FS = (size_t)MT * D::LDF * 4;
+  __shared__ __align__(16) unsigned char smem[3 * ZS + FS + MT * 16 * 4];
+  T* xs = (T*)smem;
+  T* zs = (T*)(smem + ZS);
+  T* z2s = (T*)(smem + 2 * ZS);
+  float* ft = (float*)(smem + 3 * ZS);
+  float* dys = (float*)(smem + 3 * ZS + FS);
+  const T* W1 = (const T*)w.W1;
+  const T* W2 = (const T*)w.W2;
+  const T* W1T = (const T*)w.W1T;
+  const T* W2T = (const T*)w.W2T;
+  const float* W3 = w.W1f;
+  const int n0 = wave_id() * D::CPW;
+  float cb1[NB] = {}, cb2[NB] = {};
+  float cb3 = 0.f;
+  const int n_tiles = (b.n_inner + MT - 1) / MT;
+
+  TileSched sch(n_tiles);
+  for (int t = sch.begin; t < sch.end; t += sch.step) {
+    const int row0 = t * MT, nr = min(MT, b.n_inner - row0);
+    global_rows_to_lds<T, D::LDH, MT>(xs, nr, H, 0, [&](int i) { return h + (size_t)b.inner[row0 + i] * H; });
+    for (int c = threadIdx.x; c < MT * 16; c += NTHR) {
+      const int i = c >> 4, oo = c & 15;
+      dys[c] = (i < nr && oo < out_dim) ? d_out[(size_t)b.gid[b.inner[row0 + i]] * out_dim + oo] : 0.f;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < out_dim)
+      for (int i = 0; i < nr; ++i) cb3 += dys[i * 16 + threadIdx.x];
+    f32x4 a1[MB][NB], a2[MB][NB], x[MB][NB];
+    zero_acc(a1);
+    wave_gemm<T, MB, NB, H, D::LDH>(a1, xs, W1, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b1[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          a1[mb][nb][r] += bb;
+          x[mb][nb][r] = act_f<ACT>(a1[mb][nb][r]);
+        }
+      }
+    acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
+    __syncthreads();
+    zero_acc(a2);
+    wave_gemm<T, MB, NB, H, D::LDH>(a2, zs, W2, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int c = acc_col(n0, nb);
+        const float bb = w.b2[c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          a2[mb][nb][r] += bb;
+          x[mb][nb][r] = act_f<ACT>(a2[mb][nb][r]);
+          const float* dy = dys + acc_row(mb, r) * 16;
+          float dz = 0.f;
+          for (int oo = 0; oo < out_dim; ++oo) dz += dy[oo] * W3[oo * H + c];
+          a2[mb][nb][r] = dz * act_d<ACT>(a2[mb][nb][r]);  // a2 := da2
+        }
+      }
+    col_accumulate(a2, cb2);
+    acc_to_lds<T, MB, NB, D::LDH>(x, z2s, n0);
+    __syncthreads();
+    lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.z2 + (size_t)row0 * H, H, [](int i) { return i; });
+    lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z1 + (size_t)row0 * H, H, [](int i) { return i; });
+    for (int c = threadIdx.x; c < nr * 16; c += NTHR) o.dy[(size_t)row0 * 16 + c] = dys[c];
+    __syncthreads();
+    acc_to_lds<T, MB, NB, D::LDH>(a2, z2s, n0);
+    __syncthreads();
+    lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.da2 + (size_t)row0 * H, H, [](int i) { return i; });
+    zero_acc(x);
+    wave_gemm<T, MB, NB, H, D::LDH>(x, z2s, W2T, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a1[mb][nb][r]);
+    col_accumulate(x, cb1);
+    __syncthreads();
+    acc_to_lds<T, MB, NB, D::LDH>(x, z2s, n0);
+    __syncthreads();
+    lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.da1 + (size_t)row0 * H, H, [](int i) { return i; });
+    zero_acc(x);
+    wave_gemm<T, MB, NB, H, D::LDH>(x, z2s, W1T, H, n0);
+    acc_to_ldsf<MB, NB, D::LDF>(x, ft, n0);
+    __syncthreads();
+    for (int c = threadIdx.x; c < nr * (H / 4); c += NTHR) {
+      const int i = c / (H / 4), q = c - i * (H / 4);
+      *(float4*)(o.dh + (size_t)b.inner[row0 + i] * H + 4 * q) = *(const float4*)(ft + i * D::LDF + 4 * q);
+    }
+    __syncthreads();
+  }
+  float* p = o.partial + (size_t)blockIdx.x * (2 * H + 16);
+  write_partial<NB>(p, n0, cb1);
+  write_partial<NB>(p + H, n0, cb2);
+  if (threadIdx.x < 16) p[2 * H + threadIdx.x] = (int)threadIdx.x < out_dim ? cb3 : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Encoder adjoint: y = LN(W3 act(W2 act(W1 x + b1) + b2) + b3).
+// Writes du3, z2, da2, z1 for dW3, dW2; dW1 (H x in) is accumulated per
+// workgroup since in <= 8.
+// ---------------------------------------------------------------------------
+template <typename T, int H, int MT, int ACT, int KIND>
+__global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w, const float* __restrict__ src, int in_dim,
+                                                  EdgeNorm en, const float* __restrict__ dout, EncBwdOut o, float eps) {
+  using D = BD<T, H>;
+  constexpr int MB = MT / 16, NB = D::NB;
+  constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  constexpr size_t FS = (size_t)MT * D::LDF * 4;
+  __shared__ __align__(16) unsigned char smem[2 * ZS + FS + MT * 8 * 4 + NWAVE * MT * 4];
+  T* zs = (T*)smem;
+  T* z2s = (T*)(smem + ZS);
+  float* ft = (float*)(smem + 2 * ZS);
+  float* xin = (float*)(smem + 2 * ZS + FS);
+  float* red = xin + MT * 8;
+  const T* W2 = (const T*)w.W2;
+  const T* W3 = (const T*)w.W3;
+  const T* W2T = (const T*)w.W2T;
+  const T* W3T = (const T*)w.W3T;
+  const int n0 = wave_id() * D::CPW;
+  float cb1[NB] = {}, cb2[NB] = {}, cb3[NB] = {}, cg[NB] = {}, cbt[NB] = {};
+  float cw1[NB][8] = {};
+  const int n_tiles = (rows + MT - 1) / MT;
+
+  TileSched sch(n_tiles);
+  for (int t = sch.begin; t < sch.end; t += sch.step) {
+    const int row0 = t * MT, nr = min(MT, rows - row0);
+    if (threadIdx.x < MT) {
+      const int i = threadIdx.x;
+      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (i < nr) {
+        if constexpr (KIND == 0) {
+          const float* p = src + (size_t)b.gid[row0 + i] * in_dim;
+          for (int k = 0; k < in_dim; ++k) v[k] = p[k];
+        } else {
+          const int k = row0 + i;
+          const float* ps = src + (size_t)b.gid[b.col[k]] * 3;
+          const float* pr = src + (size_t)b.gid[b.recv[k]] * 3;
+          const float dx = ps[0] - pr[0], dy = ps[1] - pr[1], dz = ps[2] - pr[2];
+          const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+          v[0] = (dx - en.mu[0]) / en.sd[0];
+          v[1] = (dy - en.mu[1]) / en.sd[1];
+          v[2] = (dz - en.mu[2]) / en.sd[2];
+          v[3] = (d - en.mu[3]) / en.sd[3];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) xin[i * 8 + k] = v[k];
+    }
+    __syncthreads();
+    f32x4 a1[MB][NB], a2[MB][NB], x[MB][NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int c = acc_col(n0, nb);
+      float wr[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) wr[k] = k < in_dim ? w.W1f[c * in_dim + k] : 0.f;
+      const float bb = w.b1[c];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float* xi = xin + acc_row(mb, r) * 8;
+          float s = bb;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) s += wr[k] * xi[k];
+          a1[mb][nb][r] = s;
+          x[mb][nb][r] = act_f<ACT>(s);
+        }
+    }
+    acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
+    __syncthreads();
+    zero_acc(a2);
+    wave_gemm<T, MB, NB, H, D::LDH>(a2, zs, W2, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b2[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          a2[mb][nb][r] += bb;
+          x[mb][nb][r] = act_f<ACT>(a2[mb][nb][r]);
+        }
+      }
+    acc_to_lds<T, MB, NB, D::LDH>(x, z2s, n0);
+    __syncthreads();
+    zero_acc(x);
+    wave_gemm<T, MB, NB, H, D::LDH>(x, z2s, W3, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b3[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[mb][nb][r] += bb;
+      }
+    float inv[MB][4];
+    ln_normalize<MB, NB, MT, H>(x, red, eps, inv);
+    f32_rows_to_lds<H, D::LDF, MT>(ft, nr, [&](int i, int q) { return *(const float4*)(dout + (size_t)(row0 + i) * H + 4 * q); });
+    lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z1 + (size_t)row0 * H, H, [](int i) { return i; });
+    lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.z2 + (size_t)row0 * H, H, [](int i) { return i; });
+    __syncthreads();
+    f32x4 g[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[mb][nb][r] = ft[acc_row(mb, r) * D::LDF + acc_col(n0, nb)];
+    ln_backward<MB, NB, MT, H>(x, g, inv, w.gamma, n0, red, cg, cbt);
+    col_accumulate(g, cb3);
+    acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
+    __syncthreads();
+    lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.du3 + (size_t)row0 * H, H, [](int i) { return i; });
+    zero_acc(x);
+    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W3T, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a2[mb][nb][r]);
+    col_accumulate(x, cb2);
+    __syncthreads();
+    acc_to_lds<T, MB, NB, D::LDH>(x, z2s, n0);
+    __syncthreads();
+    lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.da2 + (size_t)row0 * H, H, [](int i) { return i; });
+    zero_acc(x);
+    wave_gemm<T, MB, NB, H, D::LDH>(x, z2s, W2T, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a1[mb][nb][r]);
+    col_accumulate(x, cb1);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        float s = 0.f;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) s += x[mb][nb][r] * xin[acc_row(mb, r) * 8 + k];
+        cw1[nb][k] += sum_groups(s);
+      }
+    __syncthreads();
+  }
+  float* p = o.partial + (size_t)blockIdx.x * 13 * H;
+  write_partial<NB>(p, n0, cb1);
+  write_partial<NB>(p + H, n0, cb2);
+  write_partial<NB>(p + 2 * H, n0, cb3);
+  write_partial<NB>(p + 3 * H, n0, cg);
+  write_partial<NB>(p + 4 * H, n0, cbt);
+  if ((lane_id() >> 4) == 0)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) p[5 * H + acc_col(n0, nb) * 8 + k] = cw1[nb][k];
+}
+
+// ---------------------------------------------------------------------------
+#define XMGN_DISPATCH_T(prec, ...) \
+  if (prec == 1) {                 \
+    using T = bf16;                \
+    __VA_ARGS__                    \
+  } else {                         \
+    using T = float;               \
+    __VA_ARGS__                    \
+  }
+#define XMGN_DISPATCH_H(Hv, ...) \
+  if (Hv == 128) {               \
+    constexpr int H = 128;       \
+    __VA_ARGS__                  \
+  } else {                       \
+    constexpr int H = 256;       \
+    __VA_ARGS__                  \
+  }
+#define XMGN_DISPATCH_ACT(a, ...) \
+  if (a == 0) {                   \
+    constexpr int ACT = 0;        \
+    __VA_ARGS__                   \
+  } else {                        \
+    constexpr int ACT = 1;        \
+    __VA_ARGS__                   \
+  }
+// 64-row tiles only at H = 128; H = 256 uses 32-row tiles (LDS budget)
+#define XMGN_DISPATCH_MT(mt, ...)          \
+  if (mt == 64 && H == 128) {              \
+    constexpr int MT = H == 128 ? 64 : 32; \
+    __VA_ARGS__                            \
+  } else {                                 \
+    constexpr int MT = 32;                 \
+    __VA_ARGS__                            \
+  }
+
+template <typename T, int H, int MT>
+constexpr bool edge_bwd_fits() {
+  return (size_t)MT * (3 * H + 16 / sizeof(T)) * sizeof(T) + (size_t)MT * (H + 16 / sizeof(T)) * sizeof(T) +
+             (size_t)MT * 4 * 8 <= 160 * 1024;
+}
+template <typename T, int H, int MT>
+constexpr bool node_fits() {
+  return 3 * (size_t)MT * (H + 16 / sizeof(T)) * sizeof(T) + (size_t)MT * (H + 4) * 4 + MT * 64 <= 160 * 1024 &&
+         (size_t)MT * (2 * H + 16 / sizeof(T)) * sizeof(T) + (size_t)MT * (H + 4) * 4 <= 160 * 1024;
+}
+
+void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
+                     const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st) {
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
+    if constexpr (edge_bwd_fits<T, H, MT>()) {
+      if (s.agg)
+        k_edge_bwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, de_in, dm, o, s.eps);
+      else
+        k_edge_bwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, de_in, dm, o, s.eps);
+    } else {
+      g_config_error = 1;
+    }
+  }))));
+}
+
+void launch_node_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const float* m,
+                     const float* dh_in, const NodeBwdOut& o, hipStream_t st) {
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
+    if constexpr (node_fits<T, H, MT>())
+      k_node_bwd<T, H, MT, ACT><<<s.grid, NTHR, 0, st>>>(b.n, w, (const T*)h, m, dh_in, o, s.eps);
+    else
+      g_config_error = 1;
+  }))));
+}
+
+void launch_node_dh(const Shape& s, const BatchView& b, const MlpW& w, const float* dh_mid, const float* S_r,
+                    const float* S_s, float* dh_out, hipStream_t st) {
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_MT(s.mt_node, {
+    if constexpr (node_fits<T, H, MT>())
+      k_node_dh<T, H, MT><<<s.grid, NTHR, 0, st>>>(b.n, (const T*)w.Brs, dh_mid, S_r, S_s, dh_out);
+    else
+      g_config_error = 1;
+  })));
+}
+
+void launch_sender_sum(const Shape& s, const BatchView& b, const void* da, float* S_s, hipStream_t st) {
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, {
+    k_sender_sum<T, H><<<s.grid, NTHR, 0, st>>>(b.n, b.csc_ptr, b.csc_edge, (const T*)da, S_s);
+  }));
+}
+
+void launch_dec_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const float* d_out,
+                    int out_dim, const DecBwdOut& o, hipStream_t st) {
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
+    if constexpr (node_fits<T, H, MT>())
+      k_dec_bwd<T, H, MT, ACT><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, d_out, out_dim, o);
+    else
+      g_config_error = 1;
+  }))));
+}
+
+void launch_enc_node_bwd(const Shape& s, const BatchView& b, const MlpW& w, const float* node_in, int in_dim,
+                         const float* dh0, const EncBwdOut& o, hipStream_t st) {
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
+    if constexpr (node_fits<T, H, MT>())
+      k_enc_bwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, EdgeNorm{}, dh0, o, s.eps);
+    else
+      g_config_error = 1;
+  }))));
+}
+
+void launch_enc_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const float* pos, EdgeNorm en,
+                         const float* de0, const EncBwdOut& o, hipStream_t st) {
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
+    if constexpr (node_fits<T, H, MT>())
+      k_enc_bwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b.E, b, w, pos, 4, en, de0, o, s.eps);
+    else
+      g_config_error = 1;
+  }))));
+}
+
+}  // namespace xmgn

@@ -1,0 +1,464 @@
+// Forward kernels: node/edge encoders, the fused edge processor, the node
+// processor and the decoder.  All are persistent-grid kernels over row tiles
+// (see TileSched); each tile is staged in LDS, multiplied on MFMA with FP32
+// accumulation, and post-processed (bias, activation, LayerNorm, residual)
+// in registers before a coalesced write.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace xmgn {
+
+template <typename T, int H>
+struct Dims {
+  static constexpr int PAD = 16 / sizeof(T);
+  static constexpr int LDH = H + PAD;          // one H-wide tile
+  static constexpr int LD2 = 2 * H + PAD;      // [h | m]
+  static constexpr int LD3 = 3 * H + PAD;      // [h_r | h_s | e]
+  static constexpr int LDF = H + 4;            // FP32 tile
+  static constexpr int NB = H / 64;            // 16-column blocks per wave
+  static constexpr int CPW = H / 4;            // columns per wave
+};
+
+// ---------------------------------------------------------------------------
+// Fused edge processor, forward (Eq. 1-2):
+//   x = [h_r ; h_s ; e],  v = LN(W2 act(W1 x + b1) + b2),  e' = e + v,
+//   m_r = sum over the tile-local segment of r of v (or of e').
+// A tile holds whole receiver segments, so m_r is summed in one workgroup in
+// ascending sender order (the CSR order) -- deterministic, no atomics.
+// ---------------------------------------------------------------------------
+template <typename T, int H, int MT, int ACT, int AGG>
+__global__ __launch_bounds__(NTHR) void k_edge_fwd(BatchView b, MlpW w, const T* __restrict__ h,
+                                                   const T* __restrict__ e, T* __restrict__ e_out,
+                                                   float* __restrict__ m, float eps) {
+  using D = Dims<T, H>;
+  constexpr int MB = MT / 16, NB = D::NB;
+  constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
+  constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
+  __shared__ __align__(16) unsigned char smem[XS + ZS + NWAVE * MT * 4 + 2 * MT * 4];
+  T* xs = (T*)smem;
+  float* ft = (float*)smem;  // aliases xs once the gathered tile is dead
+  T* zs = (T*)(smem + XS);
+  float* red = (float*)(smem + XS + ZS);
+  int* rs = (int*)(red + NWAVE * MT);
+  int* ss = rs + MT;
+  const T* W1 = (const T*)w.W1;
+  const T* W2 = (const T*)w.W2;
+  const int n0 = wave_id() * D::CPW;
+
+  TileSched sch(b.n_etiles);
+  for (int t = sch.begin; t < sch.end; t += sch.step) {
+    const int r0 = b.etiles[t], r1 = b.etiles[t + 1];
+    const int e0 = b.row_ptr[r0], ne = b.row_ptr[r1] - e0;
+    if (threadIdx.x < MT) {
+      const bool ok = (int)threadIdx.x < ne;
+      rs[threadIdx.x] = ok ? b.recv[e0 + threadIdx.x] : 0;
+      ss[threadIdx.x] = ok ? b.col[e0 + threadIdx.x] : 0;
+    }
+    __syncthreads();
+    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, 0, [&](int i) { return h + (size_t)rs[i] * H; });
+    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, H, [&](int i) { return h + (size_t)ss[i] * H; });
+    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, 2 * H, [&](int i) { return e + (size_t)(e0 + i) * H; });
+    __syncthreads();
+
+    f32x4 acc[MB][NB];
+    zero_acc(acc);
+    wave_gemm<T, MB, NB, 3 * H, D::LD3>(acc, xs, W1, 3 * H, n0);
+    f32x4 ev[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int c = acc_col(n0, nb);
+        const float bb = w.b1[c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r] + bb);
+          ev[mb][nb][r] = to_f(xs[acc_row(mb, r) * D::LD3 + 2 * H + c]);
+        }
+      }
+    acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
+    __syncthreads();
+
+    zero_acc(acc);
+    wave_gemm<T, MB, NB, H, D::LDH>(acc, zs, W2, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b2[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mb][nb][r] += bb;
+      }
+    float inv[MB][4];
+    ln_normalize<MB, NB, MT, H>(acc, red, eps, inv);  // barriers: GEMM2 done everywhere
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int c = acc_col(n0, nb);
+        const float g = w.gamma[c], be = w.beta[c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = acc_row(mb, r);
+          const float v = g * acc[mb][nb][r] + be;
+          const float en = ev[mb][nb][r] + v;
+          ft[row * D::LDF + c] = AGG ? en : v;
+          zs[row * D::LDH + c] = from_f<T>(en);
+        }
+      }
+    __syncthreads();
+
+    // m_r: sequential sum over the receiver's edges (ascending sender id)
+    const int nr = r1 - r0;
+    for (int task = threadIdx.x; task < nr * (H / 4); task += NTHR) {
+      const int rl = task / (H / 4), q = task - rl * (H / 4);
+      const int lo = b.row_ptr[r0 + rl] - e0, hi = b.row_ptr[r0 + rl + 1] - e0;
+      float4 s = {0.f, 0.f, 0.f, 0.f};
+      for (int i = lo; i < hi; ++i) {
+        const float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
+        s.x += v.x;
+        s.y += v.y;
+        s.z += v.z;
+        s.w += v.w;
+      }
+      *(float4*)(m + (size_t)(r0 + rl) * H + 4 * q) = s;
+    }
+    if (e_out) lds_rows_to_global<T, D::LDH>(zs, ne, H, e_out + (size_t)e0 * H, H, [](int i) { return i; });
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Node processor, forward (Eq. 3): h' = h + LN(W2 act(W1 [h ; m] + b1) + b2)
+// ---------------------------------------------------------------------------
+template <typename T, int H, int MT, int ACT>
+__global__ __launch_bounds__(NTHR) void k_node_fwd(int n, MlpW w, const T* __restrict__ h,
+                                                   const float* __restrict__ m, T* __restrict__ h_out,
+                                                   float eps) {
+  using D = Dims<T, H>;
+  constexpr int MB = MT / 16, NB = D::NB;
+  constexpr size_t XS = (size_t)MT * D::LD2 * sizeof(T);
+  constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  __shared__ __align__(16) unsigned char smem[XS + ZS + NWAVE * MT * 4];
+  T* xs = (T*)smem;
+  T* zs = (T*)(smem + XS);
+  float* red = (float*)(smem + XS + ZS);
+  const T* W1 = (const T*)w.W1;
+  const T* W2 = (const T*)w.W2;
+  const int n0 = wave_id() * D::CPW;
+  const int n_tiles = (n + MT - 1) / MT;
+
+  TileSched sch(n_tiles);
+  for (int t = sch.begin; t < sch.end; t += sch.step) {
+    const int row0 = t * MT, nr = min(MT, n - row0);
+    global_rows_to_lds<T, D::LD2, MT>(xs, nr, H, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
+    global_f32_rows_to_lds<T, D::LD2, MT>(xs, nr, H, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
+    __syncthreads();
+    f32x4 acc[MB][NB];
+    zero_acc(acc);
+    wave_gemm<T, MB, NB, 2 * H, D::LD2>(acc, xs, W1, 2 * H, n0);
+    f32x4 hv[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int c = acc_col(n0, nb);
+        const float bb = w.b1[c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r] + bb);
+          hv[mb][nb][r] = to_f(xs[acc_row(mb, r) * D::LD2 + c]);
+        }
+      }
+    acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
+    __syncthreads();
+    zero_acc(acc);
+    wave_gemm<T, MB, NB, H, D::LDH>(acc, zs, W2, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b2[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mb][nb][r] += bb;
+      }
+    float inv[MB][4];
+    ln_normalize<MB, NB, MT, H>(acc, red, eps, inv);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int c = acc_col(n0, nb);
+        const float g = w.gamma[c], be = w.beta[c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          zs[acc_row(mb, r) * D::LDH + c] = from_f<T>(hv[mb][nb][r] + g * acc[mb][nb][r] + be);
+      }
+    __syncthreads();
+    lds_rows_to_global<T, D::LDH>(zs, nr, H, h_out + (size_t)row0 * H, H, [](int i) { return i; });
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Encoders: in -> H -> H -> H, LN.  The first layer (in <= 8) is a plain FMA
+// product in the accumulator layout; the other two run on MFMA.
+// Node input: node_in[gid]; edge input: ([x_s - x_r, |x_s - x_r|] - mu) / sd.
+// ---------------------------------------------------------------------------
+template <int KIND>
+struct EncIn;
+
+template <typename T, int H, int MT, int ACT, int KIND>
+__global__ __launch_bounds__(NTHR) void k_enc_fwd(int rows, BatchView b, MlpW w, const float* __restrict__ src,
+                                                  int in_dim, EdgeNorm en, T* __restrict__ out, float eps) {
+  using D = Dims<T, H>;
+  constexpr int MB = MT / 16, NB = D::NB;
+  constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  __shared__ __align__(16) unsigned char smem[2 * ZS + MT * 8 * 4 + NWAVE * MT * 4];
+  T* zs = (T*)smem;
+  T* z2 = (T*)(smem + ZS);
+  float* xin = (float*)(smem + 2 * ZS);
+  float* red = xin + MT * 8;
+  const T* W2 = (const T*)w.W2;
+  const T* W3 = (const T*)w.W3;
+  const int n0 = wave_id() * D::CPW;
+  const int n_tiles = (rows + MT - 1) / MT;
+
+  TileSched sch(n_tiles);
+  for (int t = sch.begin; t < sch.end; t += sch.step) {
+    const int row0 = t * MT, nr = min(MT, rows - row0);
+    if (threadIdx.x < MT) {
+      const int i = threadIdx.x;
+      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (i < nr) {
+        if constexpr (KIND == 0) {
+          const float* p = src + (size_t)b.gid[row0 + i] * in_dim;
+          for (int k = 0; k < in_dim; ++k) v[k] = p[k];
+        } else {
+          const int k = row0 + i;
+          const float* ps = src + (size_t)b.gid[b.col[k]] * 3;
+          const float* pr = src + (size_t)b.gid[b.recv[k]] * 3;
+          const float dx = ps[0] - pr[0], dy = ps[1] - pr[1], dz = ps[2] - pr[2];
+          const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+          v[0] = (dx - en.mu[0]) / en.sd[0];
+          v[1] = (dy - en.mu[1]) / en.sd[1];
+          v[2] = (dz - en.mu[2]) / en.sd[2];
+          v[3] = (d - en.mu[3]) / en.sd[3];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) xin[i * 8 + k] = v[k];
+    }
+    __syncthreads();
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int c = acc_col(n0, nb);
+      float wr[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) wr[k] = k < in_dim ? w.W1f[c * in_dim + k] : 0.f;
+      const float bb = w.b1[c];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float* x = xin + acc_row(mb, r) * 8;
+          float a = bb;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) a += wr[k] * x[k];
+          acc[mb][nb][r] = act_f<ACT>(a);
+        }
+    }
+    acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
+    __syncthreads();
+    zero_acc(acc);
+    wave_gemm<T, MB, NB, H, D::LDH>(acc, zs, W2, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b2[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r] + bb);
+      }
+    acc_to_lds<T, MB, NB, D::LDH>(acc, z2, n0);
+    __syncthreads();
+    zero_acc(acc);
+    wave_gemm<T, MB, NB, H, D::LDH>(acc, z2, W3, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b3[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mb][nb][r] += bb;
+      }
+    float inv[MB][4];
+    ln_normalize<MB, NB, MT, H>(acc, red, eps, inv);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int c = acc_col(n0, nb);
+        const float g = w.gamma[c], be = w.beta[c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) zs[acc_row(mb, r) * D::LDH + c] = from_f<T>(g * acc[mb][nb][r] + be);
+      }
+    __syncthreads();
+    lds_rows_to_global<T, D::LDH>(zs, nr, H, out + (size_t)row0 * H, H, [](int i) { return i; });
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decoder: y = W3 act(W2 act(W1 h + b1) + b2) + b3 on the batch's inner rows,
+// written to out[gid][0:out_dim].  The last layer (out_dim <= 16) is FMA.
+// ---------------------------------------------------------------------------
+template <typename T, int H, int MT, int ACT>
+__global__ __launch_bounds__(NTHR) void k_dec_fwd(BatchView b, MlpW w, const T* __restrict__ h,
+                                                  float* __restrict__ out, int out_dim) {
+  using D = Dims<T, H>;
+  constexpr int MB = MT / 16, NB = D::NB;
+  constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  __shared__ __align__(16) unsigned char smem[2 * ZS];
+  T* xs = (T*)smem;
+  T* zs = (T*)(smem + ZS);
+  const T* W1 = (const T*)w.W1;
+  const T* W2 = (const T*)w.W2;
+  const int n0 = wave_id() * D::CPW;
+  const int n_tiles = (b.n_inner + MT - 1) / MT;
+
+  TileSched sch(n_tiles);
+  for (int t = sch.begin; t < sch.end; t += sch.step) {
+    const int row0 = t * MT, nr = min(MT, b.n_inner - row0);
+    global_rows_to_lds<T, D::LDH, MT>(xs, nr, H, 0, [&](int i) { return h + (size_t)b.inner[row0 + i] * H; });
+    __syncthreads();
+    f32x4 acc[MB][NB];
+    zero_acc(acc);
+    wave_gemm<T, MB, NB, H, D::LDH>(acc, xs, W1, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b1[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r] + bb);
+      }
+    acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
+    __syncthreads();
+    zero_acc(acc);
+    wave_gemm<T, MB, NB, H, D::LDH>(acc, zs, W2, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b2[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r] + bb);
+      }
+    acc_to_lds<T, MB, NB, D::LDH>(acc, xs, n0);
+    __syncthreads();
+    for (int task = threadIdx.x; task < nr * out_dim; task += NTHR) {
+      const int i = task / out_dim, o = task - i * out_dim;
+      const float* wr = w.W1f + (size_t)o * H;  // decoder W3 (FP32)
+      const T* z = xs + i * D::LDH;
+      float y = 0.f;
+      for (int j = 0; j < H; ++j) y += wr[j] * to_f(z[j]);
+      out[(size_t)b.gid[b.inner[row0 + i]] * out_dim + o] = y + w.b3[o];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+#define XMGN_DISPATCH_T(prec, ...)      \
+  if (prec == 1) {                      \
+    using T = bf16;                     \
+    __VA_ARGS__                         \
+  } else {                              \
+    using T = float;                    \
+    __VA_ARGS__                         \
+  }
+#define XMGN_DISPATCH_H(Hv, ...)        \
+  if (Hv == 128) {                      \
+    constexpr int H = 128;              \
+    __VA_ARGS__                         \
+  } else {                              \
+    constexpr int H = 256;              \
+    __VA_ARGS__                         \
+  }
+#define XMGN_DISPATCH_ACT(a, ...)       \
+  if (a == 0) {                         \
+    constexpr int ACT = 0;              \
+    __VA_ARGS__                         \
+  } else {                              \
+    constexpr int ACT = 1;              \
+    __VA_ARGS__                         \
+  }
+// 64-row tiles only at H = 128; H = 256 uses 32-row tiles (LDS budget)
+#define XMGN_DISPATCH_MT(mt, ...)          \
+  if (mt == 64 && H == 128) {              \
+    constexpr int MT = H == 128 ? 64 : 32; \
+    __VA_ARGS__                            \
+  } else {                                 \
+    constexpr int MT = 32;                 \
+    __VA_ARGS__                            \
+  }
+
+template <typename T, int H, int MT>
+constexpr bool edge_fits() {
+  return (size_t)MT * (3 * H + 16 / sizeof(T)) * sizeof(T) + (size_t)MT * (H + 16 / sizeof(T)) * sizeof(T) +
+             (size_t)MT * 4 * 8 <= 160 * 1024;
+}
+
+void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
+                     void* e_out, float* m, hipStream_t st) {
+  if (b.n_etiles == 0) return;
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
+    if constexpr (edge_fits<T, H, MT>()) {
+      if (s.agg)
+        k_edge_fwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m, s.eps);
+      else
+        k_edge_fwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m, s.eps);
+    } else {
+      g_config_error = 1;
+    }
+  }))));
+}
+
+void launch_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const float* m,
+                     void* h_out, hipStream_t st) {
+  if (b.n == 0) return;
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
+    k_node_fwd<T, H, MT, ACT><<<s.grid, NTHR, 0, st>>>(b.n, w, (const T*)h, m, (T*)h_out, s.eps);
+  }))));
+}
+
+void launch_enc_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const float* node_in, int in_dim,
+                         void* h0, hipStream_t st) {
+  if (b.n == 0) return;
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
+    k_enc_fwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, EdgeNorm{}, (T*)h0, s.eps);
+  }))));
+}
+
+void launch_enc_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const float* pos, EdgeNorm en,
+                         void* e0, hipStream_t st) {
+  if (b.E == 0) return;
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
+    k_enc_fwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b.E, b, w, pos, 4, en, (T*)e0, s.eps);
+  }))));
+}
+
+void launch_dec_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, float* out, int out_dim,
+                    hipStream_t st) {
+  if (b.n_inner == 0) return;
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
+    k_dec_fwd<T, H, MT, ACT><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, out, out_dim);
+  }))));
+}
+
+}  // namespace xmgn
