@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark: MeshGraphNet processor edge-updates/s, forward + backward,
+BF16 against plain FP32, 15 layers, one MI355X.
+
+A step is one full training pass of the hot path over the workload:
+forward (encoders, 15 fused edge + node processor layers, decoder), masked
+MSE gradient, and the hand-written backward with per-layer recompute and all
+parameter gradients.  Inputs (graph, partition plan, parameters, features,
+targets) are resident in HBM before the timed region starts; the kNN graph
+build and the partitioner run once beforehand and are reported separately.
+
+edge-updates/s = E_useful * L / t_step.
+
+Prints one JSON line (rank 0).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3
+
+WORKLOADS = {
+    # name: (config index, hidden override)
+    "ellipsoid-ms-400k": 3,
+    "ellipsoid-200k": 2,
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(name: str, n: int, E: int, H: int, s: int) -> float | None:
+    """Algorithmic HBM bytes of one launch of a processor kernel (minimal
+    traffic for its inputs and outputs; s = bytes per stored latent)."""
+    if name == "edge_fwd":
+        # per edge: e and the gathered h_s read, e' written; per receiver:
+        # h_r read, m (FP32) written
+        return E * 3 * H * s + n * (H * s + 4 * H)
+    if name == "edge_bwd":
+        # per edge: h_s, e, de' (FP32) read; de (FP32), z, du, da written;
+        # per receiver: h_r, dm (FP32) read, S_r (FP32) written
+        return E * (5 * H * s + 8 * H) + n * (H * s + 8 * H)
+    if name == "node_fwd":
+        return n * (2 * H * s + 4 * H)
+    if name == "node_bwd":
+        return n * (H * s + 4 * H + 4 * H + 3 * H * s + 12 * H)
+    return None
+
+
+def kernel_flops(name: str, n: int, E: int, H: int) -> float | None:
+    if name == "edge_fwd":
+        return E * 8.0 * H * H
+    if name == "edge_bwd":
+        return E * 12.0 * H * H
+    if name == "node_fwd":
+        return n * 6.0 * H * H
+    if name == "node_bwd":
+        return n * 12.0 * H * H
+    return None
+
+
+def cpu_baseline(cfg_idx: int, layers: int, hidden: int):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload:
+    the same geometry / multi-scale recipe at 1/200 of the points, full depth
+    and width, one forward + backward."""
+    from oracle import graph as og
+    from oracle import model as om
+    from synth import CONFIGS, init_params, make_inputs
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        cores = os.cpu_count() or 1
+    cfg = CONFIGS[cfg_idx]
+    levels = tuple(max(200, lv // 200) for lv in cfg.levels)
+    inp = make_inputs(cfg, levels=levels)
+    G = og.build_graph(inp.pos, levels, cfg.k_intra, cfg.k_cross if len(levels) > 1 else 0)
+    d = om.Desc(hidden=hidden, layers=layers)
+    params = init_params(om.param_entries(d), cfg.seed("weights")).astype(np.float64)
+    t0 = time.perf_counter()
+    om.step_full(d, params, G, inp.node_in, inp.pos, inp.edge_norm, inp.targets)
+    t = time.perf_counter() - t0
+    return {"value": G.n_edges * layers / t, "unit": "edge-updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"FP64 oracle fwd+bwd on the same recipe at levels {list(levels)} "
+                      f"({G.n_edges} edges, {layers} layers, H={hidden}); {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ellipsoid-ms-400k", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay each step from a captured HIP graph")
+    ap.add_argument("--edge-rows", type=int, default=0)
+    ap.add_argument("--node-rows", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(partitions would be spread over GPUs with one gradient all-reduce)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2411_17164_amd import api
+    from synth import CONFIGS, init_params, make_inputs
+
+    cfg = CONFIGS[WORKLOADS[args.workload]]
+    H, L = cfg.hidden, cfg.layers
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload {args.workload}: generating inputs")
+    inp = make_inputs(cfg)
+    levels = [int(x) for x in inp.level_end]
+    to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    pos, node_in, tgt = to(inp.pos), to(inp.node_in), to(inp.targets)
+    ctx = api.Context(0)
+    ctx.set_tiles(args.edge_rows, args.node_rows, args.grid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = ctx.build_knn(pos, levels, cfg.k_intra, cfg.k_cross if len(levels) > 1 else 0)
+    t_knn = time.perf_counter() - t0
+    N, E = g.info()
+    t0 = time.perf_counter()
+    ps = api.Partset.halo(g, inp.pos, None, L)
+    t_part = time.perf_counter() - t0
+    log(f"[bench] graph N={N} E={E} kNN {t_knn * 1e3:.1f} ms, plan {t_part * 1e3:.1f} ms")
+
+    results = {}
+    for prec in (["bf16"] if args.no_fp32 else ["bf16", "fp32"]):
+        model = api.Model(H, L, precision=prec)
+        entries = [(kind, shape) for (_, _, _, kind, shape, _) in model.param_tensors()]
+        params = to(init_params(entries, cfg.seed("weights")))
+        out = torch.zeros(N, 4, device=dev)
+        d_out = torch.zeros_like(out)
+        loss = torch.zeros(1, device=dev)
+        d_params = torch.zeros_like(params)
+
+        def step():
+            ctx.forward(model, params, ps, [0], node_in, pos, inp.edge_norm, out, keep_tape=True)
+            ctx.mse_grad(out, tgt, N, d_out, loss)
+            ctx.backward(model, params, d_out, d_params)
+
+        log(f"[bench] {prec}: warmup {args.warmup}")
+        for _ in range(max(1, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        run = step
+        if args.graph:
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr):
+                step()
+            run = gr.replay
+            run()
+            torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(args.steps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        ev = e0.elapsed_time(e1) / 1e3 / args.steps
+        log(f"[bench] {prec}: {wall * 1e3:.2f} ms/step wall, {ev * 1e3:.2f} ms/step events, loss {loss.item():.5f}")
+        # per-kernel breakdown from one extra (untimed) step
+        ctx.set_timing(True)
+        step()
+        torch.cuda.synchronize()
+        tk = ctx.timings()
+        ctx.set_timing(False)
+        results[prec] = dict(wall=wall, ev=ev, kernels=tk, mem=ctx.memory())
+        log(f"[bench] {prec} kernels: " + ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in
+                                                     sorted(tk.items(), key=lambda kv: -kv[1][0])))
+        del params, out, d_out, d_params
+
+    bf = results["bf16"]
+    value = E * L / bf["wall"]
+    # dominant kernel of the BF16 step and its roofline
+    kern = bf["kernels"]
+    dom = max((k for k in kern if kernel_bytes(k, N, E, H, 2) is not None), key=lambda k: kern[k][0])
+    avg_ms = kern[dom][0] / kern[dom][1]
+    by = kernel_bytes(dom, N, E, H, 2)
+    achieved = by / (avg_ms * 1e-3) / 1e9
+    fl = kernel_flops(dom, N, E, H)
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": by,
+                "mfma_tflops": round(fl / (avg_ms * 1e-3) / 1e12, 2),
+                "mfma_frac_bf16": round(fl / (avg_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4)}
+    line = {
+        "metric": "processor edge-updates/s fwd+bwd, BF16 vs FP32 plain, 15 layers, 1 MI355X",
+        "value": value,
+        "unit": "edge-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(bf["wall"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "nodes": N, "edges": E, "hidden": H, "layers": L,
+                   "levels": levels, "k": [cfg.k_intra, cfg.k_cross], "partitions": 1, "parallelism": "none",
+                   "graph_replay": bool(args.graph)},
+        "roofline": roofline,
+        "knn_build_ms": round(t_knn * 1e3, 2),
+        "partition_plan_ms": round(t_part * 1e3, 2),
+    }
+    if "fp32" in results:
+        f = results["fp32"]
+        line["fp32_value"] = E * L / f["wall"]
+        line["fp32_ms_per_step"] = round(f["wall"] * 1e3, 3)
+        line["bf16_over_fp32"] = round(f["wall"] / bf["wall"], 3)
+    line["kernels_ms"] = {p: {k: round(v[0], 3) for k, v in r["kernels"].items()} for p, r in results.items()}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(WORKLOADS[args.workload], L, H)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -175,6 +175,9 @@ void xmgn_partset_destroy(xmgn_partset* ps);
  * out:       dev FP32 [N_global][out_dim]; only the rows of the batch's inner
  *            nodes are written (halo predictions are dropped, Sec. III.D)
  * keep_tape: 1 keeps per-layer checkpoints (h^l, e^l, m^l) for backward.
+ * params, node_in and pos must stay valid and unchanged until the matching
+ * xmgn_backward has been enqueued: the backward re-reads them (the
+ * encoders are recomputed from their inputs).
  */
 xmgn_status xmgn_forward(xmgn_ctx* ctx, const xmgn_model_desc* desc, const float* params,
                          const xmgn_partset* ps, const int32_t* part_ids, int32_t n_batch,
@@ -205,6 +208,20 @@ xmgn_status xmgn_backward(xmgn_ctx* ctx, const xmgn_model_desc* desc, const floa
 /* 5. acc[i] += g[i] for i < n (dev FP32), elementwise, deterministic
  * (gradient aggregation over partitions, Sec. III.A). */
 xmgn_status xmgn_grad_accumulate(float* acc, const float* g, int64_t n, xmgn_stream stream);
+
+/*
+ * Per-kernel timing (tracing).  While enabled, every kernel the context
+ * launches is bracketed by a pair of HIP events on its stream; the totals per
+ * kernel class since the last xmgn_ctx_set_timing call are read with
+ * xmgn_ctx_timing_read (which synchronises those events).  Do not enable it
+ * while the stream is being captured into a graph.
+ */
+xmgn_status xmgn_ctx_set_timing(xmgn_ctx* ctx, int32_t enable);
+xmgn_status xmgn_ctx_timing_count(const xmgn_ctx* ctx, int32_t* n_classes);
+/* Class i: name (NUL-terminated, truncated to name_len), summed duration in
+ * milliseconds and number of launches. */
+xmgn_status xmgn_ctx_timing_read(xmgn_ctx* ctx, int32_t i, char* name, int32_t name_len, double* total_ms,
+                                 int64_t* launches);
 
 /* Device bytes currently held by the context (tape and workspace). */
 xmgn_status xmgn_ctx_memory(const xmgn_ctx* ctx, int64_t* bytes);

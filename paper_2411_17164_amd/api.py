@@ -110,9 +110,9 @@ class Graph:
         check(lib.xmgn_graph_export(self._h, _ptr32(rp), _ptr32(cl)))
         return rp, cl[:e]
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.xmgn_graph_destroy):
         if getattr(self, "_h", None):
-            lib.xmgn_graph_destroy(self._h)
+            _destroy(self._h)
             self._h = None
 
 
@@ -161,9 +161,9 @@ class Partset:
         check(lib.xmgn_partset_export(self._h, part, _ptr32(gid), _ptr32(hop), _ptr32(rp), _ptr32(cl)))
         return dict(gid=gid, hop=hop, row_ptr=rp, col=cl[:ne], n_inner=ni)
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.xmgn_partset_destroy):
         if getattr(self, "_h", None):
-            lib.xmgn_partset_destroy(self._h)
+            _destroy(self._h)
             self._h = None
 
 
@@ -178,6 +178,21 @@ class Context:
 
     def set_tiles(self, edge_rows: int = 0, node_rows: int = 0, grid: int = 0):
         check(lib.xmgn_ctx_set_tiles(self._h, edge_rows, node_rows, grid))
+
+    def set_timing(self, enable: bool):
+        check(lib.xmgn_ctx_set_timing(self._h, 1 if enable else 0))
+
+    def timings(self) -> dict:
+        """{kernel class: (total_ms, launches)} since set_timing(True)."""
+        n = C.c_int32()
+        check(lib.xmgn_ctx_timing_count(self._h, C.byref(n)))
+        out = {}
+        for i in range(n.value):
+            buf = C.create_string_buffer(64)
+            ms, cnt = C.c_double(), C.c_int64()
+            check(lib.xmgn_ctx_timing_read(self._h, i, buf, 64, C.byref(ms), C.byref(cnt)))
+            out[buf.value.decode()] = (ms.value, cnt.value)
+        return out
 
     def memory(self) -> int:
         b = C.c_int64()
@@ -195,6 +210,8 @@ class Context:
                 pos: torch.Tensor, edge_norm, out: torch.Tensor, keep_tape: bool = True, stream=None):
         ids = _i32(part_ids)
         en = np.ascontiguousarray(edge_norm, dtype=np.float32).reshape(-1)
+        # the backward re-reads node_in and pos: keep them alive until then
+        self._fwd_refs = (params, node_in, pos)
         check(lib.xmgn_forward(self._h, C.byref(model.desc()), _dev(params), ps._h, _ptr32(ids), len(ids),
                                _dev(node_in), _dev(pos), en.ctypes.data_as(C.POINTER(C.c_float)), _dev(out),
                                1 if keep_tape else 0, _stream(stream)))
@@ -209,9 +226,9 @@ class Context:
         check(lib.xmgn_backward(self._h, C.byref(model.desc()), _dev(params), _dev(d_out), _dev(d_params),
                                 _stream(stream)))
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.xmgn_ctx_destroy):
         if getattr(self, "_h", None):
-            lib.xmgn_ctx_destroy(self._h)
+            _destroy(self._h)
             self._h = None
 
 

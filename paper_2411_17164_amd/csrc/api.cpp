@@ -473,6 +473,12 @@ struct xmgn_ctx {
   bool tape_full = false;
   // backward workspace
   DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, lossp;
+  // per-kernel timing
+  bool timing = false;
+  std::vector<std::string> tnames;
+  std::vector<std::vector<std::pair<hipEvent_t, hipEvent_t>>> tev;
+  std::vector<hipEvent_t> tpool;
+  size_t tpool_used = 0;
   // state of the last forward
   bool fwd_valid = false;
   bool fwd_tape = false;
@@ -484,6 +490,43 @@ struct xmgn_ctx {
 };
 
 static size_t tsize(const xmgn_model_desc* d) { return d->precision == 1 ? 2 : 4; }
+
+static hipEvent_t pooled_event(xmgn_ctx* c) {
+  if (c->tpool_used == c->tpool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->tpool.push_back(e);
+  }
+  return c->tpool[c->tpool_used++];
+}
+
+// Brackets the launches of one kernel class with events when timing is on.
+struct KTimer {
+  xmgn_ctx* c;
+  hipStream_t st;
+  int cls = -1;
+  hipEvent_t a = nullptr;
+  KTimer(xmgn_ctx* ctx, const char* name, hipStream_t s) : c(ctx), st(s) {
+    if (!c->timing) return;
+    for (size_t i = 0; i < c->tnames.size(); ++i)
+      if (c->tnames[i] == name) cls = (int)i;
+    if (cls < 0) {
+      c->tnames.push_back(name);
+      c->tev.emplace_back();
+      cls = (int)c->tnames.size() - 1;
+    }
+    a = pooled_event(c);
+    if (a) (void)hipEventRecord(a, st);
+  }
+  ~KTimer() {
+    if (!c->timing || !a) return;
+    hipEvent_t b = pooled_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    c->tev[cls].emplace_back(a, b);
+  }
+};
+#define KT(name) KTimer kt_##__LINE__(c, name, st)
 
 static Shape make_shape(const xmgn_ctx* c, const xmgn_model_desc* d) {
   Shape s{};
@@ -526,7 +569,45 @@ extern "C" void xmgn_ctx_destroy(xmgn_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  for (hipEvent_t e : ctx->tpool) (void)hipEventDestroy(e);
   delete ctx;
+}
+
+extern "C" xmgn_status xmgn_ctx_set_timing(xmgn_ctx* c, int32_t enable) {
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipDeviceSynchronize());
+  c->timing = enable != 0;
+  c->tnames.clear();
+  c->tev.clear();
+  c->tpool_used = 0;
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_ctx_timing_count(const xmgn_ctx* c, int32_t* n) {
+  if (!c || !n) return fail(XMGN_ERR_INVALID, "NULL argument");
+  *n = (int32_t)c->tnames.size();
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_ctx_timing_read(xmgn_ctx* c, int32_t i, char* name, int32_t name_len, double* total_ms,
+                                            int64_t* launches) {
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (i < 0 || i >= (int32_t)c->tnames.size()) return fail(XMGN_ERR_INVALID, "class out of range");
+  double t = 0.0;
+  for (auto& pr : c->tev[i]) {
+    HIPCHK(hipEventSynchronize(pr.second));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+    t += ms;
+  }
+  if (name && name_len > 0) {
+    std::strncpy(name, c->tnames[i].c_str(), (size_t)name_len - 1);
+    name[name_len - 1] = 0;
+  }
+  if (total_ms) *total_ms = t;
+  if (launches) *launches = (int64_t)c->tev[i].size();
+  return XMGN_OK;
 }
 
 extern "C" xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int32_t node_rows, int32_t grid) {
@@ -805,16 +886,16 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
   const BatchView& b = c->batch.view;
   const int L = d->n_layers;
   g_config_error = 0;
-  launch_prep(params, c->blob.p, d->precision, c->jobs_dev.as<PrepJob>(), (int)c->jobs.size(), st);
-  launch_enc_node_fwd(s, b, weights(c, d, params, 0, 0, 0), node_in, d->node_in, hslot(c, d, 0), st);
-  launch_enc_edge_fwd(s, b, weights(c, d, params, 1, 1, 0), pos, en, eslot(c, d, 0), st);
+  { KT("prep"); launch_prep(params, c->blob.p, d->precision, c->jobs_dev.as<PrepJob>(), (int)c->jobs.size(), st); }
+  { KT("enc_node_fwd"); launch_enc_node_fwd(s, b, weights(c, d, params, 0, 0, 0), node_in, d->node_in, hslot(c, d, 0), st); }
+  { KT("enc_edge_fwd"); launch_enc_edge_fwd(s, b, weights(c, d, params, 1, 1, 0), pos, en, eslot(c, d, 0), st); }
   for (int l = 0; l < L; ++l) {
-    launch_edge_fwd(s, b, weights(c, d, params, 2 + 2 * l, 2, l), hslot(c, d, l), eslot(c, d, l),
-                    l + 1 < L ? eslot(c, d, l + 1) : nullptr, mslot(c, d, l), st);
-    launch_node_fwd(s, b, weights(c, d, params, 3 + 2 * l, 3, l), hslot(c, d, l), mslot(c, d, l), hslot(c, d, l + 1),
-                    st);
+    { KT("edge_fwd"); launch_edge_fwd(s, b, weights(c, d, params, 2 + 2 * l, 2, l), hslot(c, d, l), eslot(c, d, l),
+                    l + 1 < L ? eslot(c, d, l + 1) : nullptr, mslot(c, d, l), st); }
+    { KT("node_fwd"); launch_node_fwd(s, b, weights(c, d, params, 3 + 2 * l, 3, l), hslot(c, d, l), mslot(c, d, l), hslot(c, d, l + 1),
+                    st); }
   }
-  launch_dec_fwd(s, b, weights(c, d, params, 2 + 2 * L, 4, 0), hslot(c, d, L), out, d->out_dim, st);
+  { KT("dec_fwd"); launch_dec_fwd(s, b, weights(c, d, params, 2 + 2 * L, 4, 0), hslot(c, d, L), out, d->out_dim, st); }
   HIPCHK(hipGetLastError());
   if (g_config_error) return fail(XMGN_ERR_UNSUPPORTED, "tile configuration does not fit this kernel");
   c->fwd_valid = true;
@@ -839,16 +920,20 @@ extern "C" xmgn_status xmgn_mse_grad(xmgn_ctx* c, const float* out, const float*
   const int G = 256;
   if (xmgn_status s = c->lossp.ensure(G * sizeof(float))) return s;
   const double inv = 1.0 / ((double)n_total * c->fdesc.out_dim);
+  hipStream_t st = (hipStream_t)stream;
+  KT("mse");
   launch_mse(out, target, c->batch.view.gid, c->batch.view.inner, c->batch.n_inner, c->fdesc.out_dim, inv, d_out,
-             c->lossp.as<float>(), G, loss, (hipStream_t)stream);
+             c->lossp.as<float>(), G, loss, st);
   HIPCHK(hipGetLastError());
   return XMGN_OK;
   GUARD_END
 }
 
-static void wgrad(const Shape& s, WgradOp op, DBuf& wpart, hipStream_t st) {
+static void wgrad_run(xmgn_ctx* c, const Shape& s, WgradOp op, DBuf& wpart, hipStream_t st) {
+  KT("wgrad");
   launch_wgrad(s, op, wpart.as<float>(), st);
 }
+#define wgrad(s_, op_, wp_, st_) wgrad_run(c, s_, op_, wp_, st_)
 
 static WgradOp wop(const void* A, int a_f32, int lda, int a0, const int* ia, const void* B, int b_f32, int ldb, int b0,
                    const int* ib, int R, int M, int N, float* dst, int ldd, int M_valid = -1) {
@@ -910,10 +995,10 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
 
   g_config_error = 0;
   // decoder
-  launch_fill(c->dhA.as<float>(), n * H, 0.f, st);
+  { KT("fill"); launch_fill(c->dhA.as<float>(), n * H, 0.f, st); }
   {
     DecBwdOut o{c->dhA.as<float>(), c->fa.p, c->fb.p, c->fc.p, c->fd.p, c->dy.as<float>(), part};
-    launch_dec_bwd(s, b, weights(c, d, params, 2 + 2 * L, 4, 0), hl(L), d_out, d->out_dim, o, st);
+    { KT("dec_bwd"); launch_dec_bwd(s, b, weights(c, d, params, 2 + 2 * L, 4, 0), hl(L), d_out, d->out_dim, o, st); }
     VecSeg segs[3] = {{0, (int)H, P(4, 0, 1)}, {(int)H, (int)H, P(4, 0, 3)}, {2 * (int)H, d->out_dim, P(4, 0, 5)}};
     launch_vec_reduce(part, G, 2 * (int)H + 16, segs, 3, st);
     const int ni = c->batch.n_inner;
@@ -931,7 +1016,7 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   for (int l = L - 1; l >= 0; --l) {
     const MlpW wn = weights(c, d, params, 3 + 2 * l, 3, l);
     NodeBwdOut no{c->dhMid.as<float>(), c->dm.as<float>(), c->fa.p, c->fb.p, c->fc.p, part};
-    launch_node_bwd(s, b, wn, hl(l), mslot(c, d, l), c->dhA.as<float>(), no, st);
+    { KT("node_bwd"); launch_node_bwd(s, b, wn, hl(l), mslot(c, d, l), c->dhA.as<float>(), no, st); }
     VecSeg ns[4] = {{0, (int)H, P(3, l, 1)}, {(int)H, (int)H, P(3, l, 3)}, {2 * (int)H, (int)H, P(3, l, 4)},
                     {3 * (int)H, (int)H, P(3, l, 5)}};
     launch_vec_reduce(part, G, 4 * (int)H, ns, 4, st);
@@ -944,12 +1029,12 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
 
     const MlpW we = weights(c, d, params, 2 + 2 * l, 2, l);
     EdgeBwdOut eo{de_out->as<float>(), c->Sr.as<float>(), c->fa.p, c->fb.p, c->fc.p, part};
-    launch_edge_bwd(s, b, we, hl(l), eslot(c, d, l), de_in, c->dm.as<float>(), eo, st);
+    { KT("edge_bwd"); launch_edge_bwd(s, b, we, hl(l), eslot(c, d, l), de_in, c->dm.as<float>(), eo, st); }
     VecSeg es[4] = {{0, (int)H, P(2, l, 1)}, {(int)H, (int)H, P(2, l, 3)}, {2 * (int)H, (int)H, P(2, l, 4)},
                     {3 * (int)H, (int)H, P(2, l, 5)}};
     launch_vec_reduce(part, G, 4 * (int)H, es, 4, st);
-    launch_sender_sum(s, b, c->fa.p, c->Ss.as<float>(), st);
-    launch_node_dh(s, b, we, c->dhMid.as<float>(), c->Sr.as<float>(), c->Ss.as<float>(), c->dhA.as<float>(), st);
+    { KT("sender_sum"); launch_sender_sum(s, b, c->fa.p, c->Ss.as<float>(), st); }
+    { KT("node_dh"); launch_node_dh(s, b, we, c->dhMid.as<float>(), c->Sr.as<float>(), c->Ss.as<float>(), c->dhA.as<float>(), st); }
     wgrad(s, wop(c->Sr.p, 1, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(2, l, 0),
                  3 * (int)H), c->wpart, st);
     wgrad(s, wop(c->Ss.p, 1, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
@@ -968,11 +1053,11 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     int R;
     int in_dim;
     if (blk == 1) {
-      launch_enc_edge_bwd(s, b, w, c->f_pos, c->f_en, de_in, o, st);
+      { KT("enc_edge_bwd"); launch_enc_edge_bwd(s, b, w, c->f_pos, c->f_en, de_in, o, st); }
       R = (int)E;
       in_dim = 4;
     } else {
-      launch_enc_node_bwd(s, b, w, c->f_node_in, d->node_in, c->dhA.as<float>(), o, st);
+      { KT("enc_node_bwd"); launch_enc_node_bwd(s, b, w, c->f_node_in, d->node_in, c->dhA.as<float>(), o, st); }
       R = (int)n;
       in_dim = d->node_in;
     }

@@ -1,0 +1,144 @@
+"""GPU checks at the workloads' full sizes, in the launch configuration the
+benchmark times.
+
+* Outputs: the oracle evaluates sampled nodes one by one through their
+  L-hop in-cones (an output depends only on its L-hop in-neighbourhood,
+  Eq. 4), compared with the GPU's full-graph forward on the same rows.
+* kNN: sampled receivers' segments against the oracle's exact lists.
+* Gradients: properties that hold at any size -- a central directional
+  difference of the GPU loss, and determinism of the whole step.
+* Graph replay: the step captured into a HIP graph and replayed several
+  times, with eager work in between, equals the eager step bit for bit.
+"""
+import numpy as np
+import pytest
+
+from cases import Case, log, rel_l2
+from oracle import graph as og
+from oracle import model as om
+from oracle import partition as opart
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2411_17164_amd import api as a
+    return a
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+class Run:
+    def __init__(self, api, ctx, case, part_ids=(0,), ps=None, g=None):
+        self.api, self.ctx, self.case = api, ctx, case
+        self.g = g or ctx.build_knn(dev(case.inp.pos), case.levels, case.k_intra, case.k_cross)
+        self.ps = ps or api.Partset.halo(self.g, case.inp.pos, None, case.L)
+        self.part_ids = list(part_ids)
+        self.model = case.model(api)
+        self.p = dev(case.params)
+        self.node_in, self.pos, self.tgt = dev(case.inp.node_in), dev(case.inp.pos), dev(case.inp.targets)
+        self.out = torch.zeros(case.N, 4, device="cuda")
+        self.d_out = torch.zeros_like(self.out)
+        self.loss = torch.zeros(1, device="cuda")
+        self.dp = torch.zeros_like(self.p)
+
+    def step(self, backward=True, params=None):
+        p = self.p if params is None else params
+        self.ctx.forward(self.model, p, self.ps, self.part_ids, self.node_in, self.pos, self.case.inp.edge_norm,
+                         self.out, keep_tape=backward)
+        self.ctx.mse_grad(self.out, self.tgt, self.case.N, self.d_out, self.loss)
+        if backward:
+            self.ctx.backward(self.model, p, self.d_out, self.dp)
+
+
+def sampled_outputs(case, G, seeds):
+    """Oracle outputs of the seed nodes from their L-hop in-cone."""
+    c = opart.in_cone(G, seeds, case.L)
+    y = om.forward(case.desc, case.params.astype(np.float64), c.graph, case.inp.node_in[c.gid],
+                   case.inp.pos[c.gid], case.inp.edge_norm)
+    return y[: len(seeds)], len(c.gid)
+
+
+@pytest.mark.parametrize("cfg,precision,tol,n_seeds", [(2, "fp32", 1e-4, 6), (2, "bf16", 2e-2, 6),
+                                                       (3, "bf16", 2e-2, 2), (3, "fp32", 1e-4, 2)])
+def test_fullsize_sampled_outputs(api, ctx, cfg, precision, tol, n_seeds):
+    case = Case(cfg, precision=precision)
+    log(f"full-size cfg={cfg} {precision}: N={case.N}")
+    r = Run(api, ctx, case)
+    r.step(backward=False)
+    torch.cuda.synchronize()
+    y = r.out.cpu().numpy()
+    assert np.isfinite(y).all()
+    G = case.oracle_graph()
+    rp, col = r.g.export()
+    rng = np.random.default_rng(99)
+    seeds = np.sort(rng.choice(case.N, n_seeds, replace=False))
+    # kNN segments of sampled receivers, bit for bit
+    for s in rng.choice(case.N, 200, replace=False):
+        assert (col[rp[s]:rp[s + 1]] == G.col[G.row_ptr[s]:G.row_ptr[s + 1]]).all()
+    errs = []
+    for s in seeds:
+        yo, cone = sampled_outputs(case, G, [s])
+        errs.append(rel_l2(y[s], yo[0]))
+        log(f"  seed {s}: in-cone {cone} nodes, rel-L2 {errs[-1]:.2e}")
+    assert max(errs) <= tol, errs
+
+
+def test_fullsize_directional_derivative(api, ctx):
+    """(loss(p + eps v) - loss(p - eps v)) / 2 eps against grad . v, FP32,
+    15 layers on the 200k-node ellipsoid."""
+    case = Case(2, precision="fp32", activation="silu")
+    r = Run(api, ctx, case)
+    r.step()
+    torch.cuda.synchronize()
+    grad = r.dp.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(5)
+    # direction half along the gradient, half random, so grad . v is large
+    v = rng.standard_normal(len(case.params))
+    v = v / np.linalg.norm(v) + grad / np.linalg.norm(grad)
+    v = (v / np.linalg.norm(v)).astype(np.float32)
+    eps = 1e-2
+    losses = []
+    for sgn in (1, -1):
+        p = dev((case.params + sgn * eps * v).astype(np.float32))
+        r.step(backward=False, params=p)
+        torch.cuda.synchronize()
+        losses.append(float(r.loss.item()))
+    fd = (losses[0] - losses[1]) / (2 * eps)
+    an = float(grad @ v.astype(np.float64))
+    log(f"  fd {fd:.6e} analytic {an:.6e}")
+    assert abs(fd - an) <= 1e-2 * max(abs(an), 1e-6)
+
+
+def test_graph_replay_equals_eager(api, ctx):
+    case = Case(3, levels=(2000, 8000, 32000), layers=4, precision="bf16")
+    r = Run(api, ctx, case)
+    r.step()
+    torch.cuda.synchronize()
+    y0, g0, l0 = r.out.clone(), r.dp.clone(), r.loss.clone()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        r.step()
+    for i in range(3):
+        r.out.zero_()
+        r.dp.fill_(float("nan"))
+        gr.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(r.out, y0), i
+        assert torch.equal(r.dp, g0), i
+        assert torch.equal(r.loss, l0), i
+        # eager work between replays
+        r.step()
+        torch.cuda.synchronize()
+        assert torch.equal(r.dp, g0)
