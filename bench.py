@@ -31,9 +31,11 @@ BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
 
 WORKLOADS = {
-    # name: (config index, hidden override)
-    "ellipsoid-ms-400k": 3,
+    # name: config index (synth.CONFIGS)
     "ellipsoid-200k": 2,
+    "ellipsoid-ms-400k": 3,
+    "ellipsoid-ms-1m-24p": 4,
+    "car-ms-4m-16p": 5,
 }
 
 
@@ -69,6 +71,30 @@ def kernel_flops(name: str, n: int, E: int, H: int) -> float | None:
     if name == "node_bwd":
         return n * 12.0 * H * H
     return None
+
+
+def kernel_source_hash() -> str:
+    """Hash of the kernel sources; HBM counters taken on other sources are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2411_17164_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/traffic_<kernel>_<workload>.json), if it was taken on
+    the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(cfg_idx: int, layers: int, hidden: int):
@@ -109,6 +135,11 @@ def main():
     ap.add_argument("--edge-rows", type=int, default=0)
     ap.add_argument("--node-rows", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tiles")
+    ap.add_argument("--wave-parts", type=int, default=0,
+                    help="partitions per batch (wave) for partitioned workloads (0 = all in one batch)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 256 MiB device copy first (to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -128,6 +159,12 @@ def main():
     levels = [int(x) for x in inp.level_end]
     to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
     pos, node_in, tgt = to(inp.pos), to(inp.node_in), to(inp.targets)
+    if args.calib_copy:
+        a = torch.ones(64 << 20, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ctx = api.Context(0)
     ctx.set_tiles(args.edge_rows, args.node_rows, args.grid)
     torch.cuda.synchronize()
@@ -136,9 +173,16 @@ def main():
     t_knn = time.perf_counter() - t0
     N, E = g.info()
     t0 = time.perf_counter()
-    ps = api.Partset.halo(g, inp.pos, None, L)
+    n_parts = cfg.n_parts
+    ps = api.Partset.halo(g, inp.pos, inp.part_sizes if n_parts > 1 else None, L)
     t_part = time.perf_counter() - t0
-    log(f"[bench] graph N={N} E={E} kNN {t_knn * 1e3:.1f} ms, plan {t_part * 1e3:.1f} ms")
+    infos = [ps.info(p) for p in range(n_parts)]
+    E_proc = int(sum(i[2] for i in infos))
+    wp = args.wave_parts if args.wave_parts > 0 else n_parts
+    waves = [list(range(i, min(i + wp, n_parts))) for i in range(0, n_parts, wp)]
+    wave_sizes = [(sum(infos[p][0] + infos[p][1] for p in w), sum(infos[p][2] for p in w)) for w in waves]
+    log(f"[bench] graph N={N} E={E} (processed {E_proc}, {n_parts} parts in {len(waves)} waves) "
+        f"kNN {t_knn * 1e3:.1f} ms, plan {t_part * 1e3:.1f} ms")
 
     results = {}
     for prec in (["bf16"] if args.no_fp32 else ["bf16", "fp32"]):
@@ -149,18 +193,33 @@ def main():
         d_out = torch.zeros_like(out)
         loss = torch.zeros(1, device=dev)
         d_params = torch.zeros_like(params)
+        acc = torch.zeros_like(params) if len(waves) > 1 else None
 
         def step():
-            ctx.forward(model, params, ps, [0], node_in, pos, inp.edge_norm, out, keep_tape=True)
-            ctx.mse_grad(out, tgt, N, d_out, loss)
-            ctx.backward(model, params, d_out, d_params)
+            if acc is None:
+                ctx.forward(model, params, ps, waves[0], node_in, pos, inp.edge_norm, out, keep_tape=True)
+                ctx.mse_grad(out, tgt, N, d_out, loss)
+                ctx.backward(model, params, d_out, d_params)
+                return
+            acc.zero_()
+            for w in waves:  # gradient aggregation over partition waves
+                ctx.forward(model, params, ps, w, node_in, pos, inp.edge_norm, out, keep_tape=True)
+                ctx.mse_grad(out, tgt, N, d_out, loss)
+                ctx.backward(model, params, d_out, d_params)
+                api.grad_accumulate(acc, d_params)
 
+        tuned = None
+        if not args.no_autotune and not (args.edge_rows or args.node_rows or args.grid):
+            ctx.set_tiles(0, 0, 0)
+            tuned = ctx.autotune(model, params, ps, waves[0], node_in, pos, inp.edge_norm, out, d_out, d_params)
+            log(f"[bench] {prec}: autotuned edge_rows={tuned[0]} node_rows={tuned[1]} grid={tuned[2]} "
+                f"({tuned[3]:.2f} ms)")
         log(f"[bench] {prec}: warmup {args.warmup}")
         for _ in range(max(1, args.warmup)):
             step()
         torch.cuda.synchronize()
         run = step
-        if args.graph:
+        if args.graph and len(waves) == 1:
             gr = torch.cuda.CUDAGraph()
             with torch.cuda.graph(gr):
                 step()
@@ -184,7 +243,7 @@ def main():
         torch.cuda.synchronize()
         tk = ctx.timings()
         ctx.set_timing(False)
-        results[prec] = dict(wall=wall, ev=ev, kernels=tk, mem=ctx.memory())
+        results[prec] = dict(wall=wall, ev=ev, kernels=tk, mem=ctx.memory(), tiles=tuned)
         log(f"[bench] {prec} kernels: " + ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in
                                                      sorted(tk.items(), key=lambda kv: -kv[1][0])))
         del params, out, d_out, d_params
@@ -195,11 +254,16 @@ def main():
     kern = bf["kernels"]
     dom = max((k for k in kern if kernel_bytes(k, N, E, H, 2) is not None), key=lambda k: kern[k][0])
     avg_ms = kern[dom][0] / kern[dom][1]
-    by = kernel_bytes(dom, N, E, H, 2)
+    # launches of a processor kernel per step: L per wave (edge/node kernels)
+    per_step = kern[dom][1]
+    tot_bytes = sum(kernel_bytes(dom, n_w, e_w, H, 2) for n_w, e_w in wave_sizes) * per_step / len(waves)
+    tot_flops = sum(kernel_flops(dom, n_w, e_w, H) for n_w, e_w in wave_sizes) * per_step / len(waves)
+    by = tot_bytes / per_step
+    fl = tot_flops / per_step
     achieved = by / (avg_ms * 1e-3) / 1e9
-    fl = kernel_flops(dom, N, E, H)
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.workload, dom), "source_hash": kernel_source_hash(),
                 "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": by,
                 "mfma_tflops": round(fl / (avg_ms * 1e-3) / 1e12, 2),
                 "mfma_frac_bf16": round(fl / (avg_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4)}
@@ -217,8 +281,11 @@ def main():
         "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": args.workload, "nodes": N, "edges": E, "hidden": H, "layers": L,
-                   "levels": levels, "k": [cfg.k_intra, cfg.k_cross], "partitions": 1, "parallelism": "none",
-                   "graph_replay": bool(args.graph)},
+                   "levels": levels, "k": [cfg.k_intra, cfg.k_cross], "partitions": n_parts,
+                   "halo": L if n_parts > 1 else 0, "waves": len(waves), "processed_edges": E_proc,
+                   "parallelism": "halo-partition batches" if n_parts > 1 else "none",
+                   "graph_replay": bool(args.graph and len(waves) == 1)},
+        "processed_edge_updates_per_s": E_proc * L / bf["wall"],
         "roofline": roofline,
         "knn_build_ms": round(t_knn * 1e3, 2),
         "partition_plan_ms": round(t_part * 1e3, 2),
@@ -228,6 +295,7 @@ def main():
         line["fp32_value"] = E * L / f["wall"]
         line["fp32_ms_per_step"] = round(f["wall"] * 1e3, 3)
         line["bf16_over_fp32"] = round(f["wall"] / bf["wall"], 3)
+    line["tiles"] = {p: (list(r["tiles"][:3]) if r["tiles"] else None) for p, r in results.items()}
     line["kernels_ms"] = {p: {k: round(v[0], 3) for k, v in r["kernels"].items()} for p, r in results.items()}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -205,6 +205,26 @@ xmgn_status xmgn_mse_grad(xmgn_ctx* ctx, const float* out, const float* target, 
 xmgn_status xmgn_backward(xmgn_ctx* ctx, const xmgn_model_desc* desc, const float* params,
                           const float* d_out, float* d_params, xmgn_stream stream);
 
+/*
+ * Tile autotuner (batching).  Times one forward + backward of the batch for
+ * every candidate configuration -- edge-tile rows {32, 64}, node-tile rows
+ * {32, 64} (64 only at H = 128) and persistent grid {2, 4, 8} workgroups per
+ * compute unit -- and keeps the fastest in ctx (as xmgn_ctx_set_tiles would).
+ * Arguments as for xmgn_forward / xmgn_backward; out and d_params are
+ * overwritten, d_out is only read.  cache_path (host string or NULL): a text
+ * file of "key edge_rows node_rows grid ms" lines; a hit skips the timing,
+ * a miss appends a line.  The key holds the device name, the model
+ * description and the batch's node and edge counts.  The chosen
+ * configuration and its step time are returned (any output pointer may be
+ * NULL).  Synchronises the stream.
+ */
+xmgn_status xmgn_autotune(xmgn_ctx* ctx, const xmgn_model_desc* desc, const float* params,
+                          const xmgn_partset* ps, const int32_t* part_ids, int32_t n_batch,
+                          const float* node_in, const float* pos, const float* edge_norm,
+                          float* out, const float* d_out, float* d_params, const char* cache_path,
+                          int32_t* edge_rows, int32_t* node_rows, int32_t* grid, float* step_ms,
+                          xmgn_stream stream);
+
 /* 5. acc[i] += g[i] for i < n (dev FP32), elementwise, deterministic
  * (gradient aggregation over partitions, Sec. III.A). */
 xmgn_status xmgn_grad_accumulate(float* acc, const float* g, int64_t n, xmgn_stream stream);

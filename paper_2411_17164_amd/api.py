@@ -216,6 +216,21 @@ class Context:
                                _dev(node_in), _dev(pos), en.ctypes.data_as(C.POINTER(C.c_float)), _dev(out),
                                1 if keep_tape else 0, _stream(stream)))
 
+    def autotune(self, model: Model, params: torch.Tensor, ps: Partset, part_ids, node_in: torch.Tensor,
+                 pos: torch.Tensor, edge_norm, out: torch.Tensor, d_out: torch.Tensor, d_params: torch.Tensor,
+                 cache_path: str | None = None, stream=None):
+        """Pick the fastest tile configuration for this batch (see
+        xmgn_autotune); returns (edge_rows, node_rows, grid, step_ms)."""
+        ids = _i32(part_ids)
+        en = np.ascontiguousarray(edge_norm, dtype=np.float32).reshape(-1)
+        self._fwd_refs = (params, node_in, pos)
+        er, nr, g, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
+        check(lib.xmgn_autotune(self._h, C.byref(model.desc()), _dev(params), ps._h, _ptr32(ids), len(ids),
+                                _dev(node_in), _dev(pos), en.ctypes.data_as(C.POINTER(C.c_float)), _dev(out),
+                                _dev(d_out), _dev(d_params), cache_path.encode() if cache_path else None,
+                                C.byref(er), C.byref(nr), C.byref(g), C.byref(ms), _stream(stream)))
+        return er.value, nr.value, g.value, ms.value
+
     def mse_grad(self, out: torch.Tensor, target: torch.Tensor, n_total: int, d_out: torch.Tensor,
                  loss: torch.Tensor, stream=None):
         check(lib.xmgn_mse_grad(self._h, _dev(out), _dev(target), n_total, _dev(d_out), _dev(loss),

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <fstream>
+#include <sstream>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -472,7 +474,7 @@ struct xmgn_ctx {
   int tape_slots_h = 0, tape_slots_e = 0, tape_slots_m = 0;
   bool tape_full = false;
   // backward workspace
-  DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, lossp;
+  DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, wfused, lossp;
   // per-kernel timing
   bool timing = false;
   std::vector<std::string> tnames;
@@ -628,7 +630,7 @@ extern "C" xmgn_status xmgn_ctx_memory(const xmgn_ctx* c, int64_t* bytes) {
   if (!c || !bytes) return fail(XMGN_ERR_INVALID, "NULL argument");
   const DBuf* bufs[] = {&c->batch.ints, &c->jobs_dev, &c->blob, &c->h, &c->e, &c->m, &c->dhA, &c->dhMid,
                         &c->dm, &c->Sr, &c->Ss, &c->deA, &c->deB, &c->fa, &c->fb, &c->fc, &c->fd,
-                        &c->dy, &c->part, &c->wpart, &c->lossp};
+                        &c->dy, &c->part, &c->wpart, &c->wfused, &c->lossp};
   int64_t t = 0;
   for (const DBuf* b : bufs) t += (int64_t)b->bytes;
   *bytes = t;
@@ -989,6 +991,12 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
                                                         (int)H, (int)H, nullptr, 0)));
     if (xmgn_status r = c->wpart.ensure(need * 4)) return r;
   }
+  // the edge adjoint may accumulate its dense weight gradients itself
+  const bool fw = edge_bwd_fuses_wgrad(s);
+  Shape se = s;
+  if (fw) se.grid = std::min(s.grid, 512);
+  if (fw)
+    if (xmgn_status r = c->wfused.ensure((size_t)se.grid * 2 * H * H * 4)) return r;
   float* part = c->part.as<float>();
   auto P = [&](int block, int layer, int t) { return d_params + poff(d, block, layer, t); };
   auto hl = [&](int l) { return hslot(c, d, l); };
@@ -1028,21 +1036,30 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
                  (int)H), c->wpart, st);
 
     const MlpW we = weights(c, d, params, 2 + 2 * l, 2, l);
-    EdgeBwdOut eo{de_out->as<float>(), c->Sr.as<float>(), c->fa.p, c->fb.p, c->fc.p, part};
-    { KT("edge_bwd"); launch_edge_bwd(s, b, we, hl(l), eslot(c, d, l), de_in, c->dm.as<float>(), eo, st); }
+    EdgeBwdOut eo{de_out->as<float>(), c->Sr.as<float>(), c->fa.p, c->fb.p, c->fc.p, part,
+                  fw ? c->wfused.as<float>() : nullptr};
+    { KT("edge_bwd"); launch_edge_bwd(se, b, we, hl(l), eslot(c, d, l), de_in, c->dm.as<float>(), eo, st); }
     VecSeg es[4] = {{0, (int)H, P(2, l, 1)}, {(int)H, (int)H, P(2, l, 3)}, {2 * (int)H, (int)H, P(2, l, 4)},
                     {3 * (int)H, (int)H, P(2, l, 5)}};
-    launch_vec_reduce(part, G, 4 * (int)H, es, 4, st);
+    launch_vec_reduce(part, se.grid, 4 * (int)H, es, 4, st);
+    if (fw) {
+      KT("wgrad");
+      launch_wgrad_reduce(c->wfused.as<float>(), se.grid, (int)H, (int)H, P(2, l, 2), (int)H, 2 * (int)(H * H), st);
+      launch_wgrad_reduce(c->wfused.as<float>() + H * H, se.grid, (int)H, (int)H, P(2, l, 0) + 2 * H, 3 * (int)H,
+                          2 * (int)(H * H), st);
+    }
     { KT("sender_sum"); launch_sender_sum(s, b, c->fa.p, c->Ss.as<float>(), st); }
     { KT("node_dh"); launch_node_dh(s, b, we, c->dhMid.as<float>(), c->Sr.as<float>(), c->Ss.as<float>(), c->dhA.as<float>(), st); }
     wgrad(s, wop(c->Sr.p, 1, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(2, l, 0),
                  3 * (int)H), c->wpart, st);
     wgrad(s, wop(c->Ss.p, 1, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
                  P(2, l, 0) + H, 3 * (int)H), c->wpart, st);
-    wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, eslot(c, d, l), 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H,
-                 P(2, l, 0) + 2 * H, 3 * (int)H), c->wpart, st);
-    wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, c->fc.p, 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H, P(2, l, 2),
-                 (int)H), c->wpart, st);
+    if (!fw) {
+      wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, eslot(c, d, l), 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H,
+                   P(2, l, 0) + 2 * H, 3 * (int)H), c->wpart, st);
+      wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, c->fc.p, 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H,
+                   P(2, l, 2), (int)H), c->wpart, st);
+    }
     de_in = de_out->as<float>();
     std::swap(de_out, de_other);
   }
@@ -1120,6 +1137,106 @@ extern "C" xmgn_status xmgn_build_knn(xmgn_ctx* c, const float* pos, int32_t n, 
   (void)hipFree(col);
   if (e1 != hipSuccess || e2 != hipSuccess) return fail(XMGN_ERR_HIP, "copy of the graph to the host failed");
   *out = g.release();
+  return XMGN_OK;
+  GUARD_END
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+static std::string tune_key(const xmgn_ctx* c, const xmgn_model_desc* d) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+  std::ostringstream k;
+  k << arch.substr(0, arch.find(':')) << ":H" << d->hidden << ":L" << d->n_layers << ":p" << d->precision << ":a"
+    << d->activation << ":g" << d->aggregate << ":n" << c->batch.n << ":E" << c->batch.E;
+  return k.str();
+}
+
+extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, const float* params,
+                                     const xmgn_partset* ps, const int32_t* part_ids, int32_t n_batch,
+                                     const float* node_in, const float* pos, const float* edge_norm, float* out,
+                                     const float* d_out, float* d_params, const char* cache_path,
+                                     int32_t* edge_rows, int32_t* node_rows, int32_t* grid, float* step_ms,
+                                     xmgn_stream stream) {
+  GUARD_BEGIN
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (xmgn_status s = check_desc(d)) return s;
+  if (!d_out || !d_params) return fail(XMGN_ERR_INVALID, "NULL argument");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, c->device));
+  const int cus = prop.multiProcessorCount;
+  // key needs the batch sizes: build the plan with the current tiles first
+  if (xmgn_status r = xmgn_forward(c, d, params, ps, part_ids, n_batch, node_in, pos, edge_norm, out, 1, stream))
+    return r;
+  const std::string key = tune_key(c, d);
+  int best_e = 0, best_n = 0, best_g = 0;
+  float best = -1.f;
+  if (cache_path) {
+    std::ifstream f(cache_path);
+    std::string line;
+    while (std::getline(f, line)) {
+      std::istringstream is(line);
+      std::string k;
+      int e, n, g;
+      float ms;
+      if (is >> k >> e >> n >> g >> ms && k == key) {
+        best_e = e;
+        best_n = n;
+        best_g = g;
+        best = ms;
+      }
+    }
+  }
+  if (best < 0.f) {
+    std::vector<int> rows = d->hidden == 128 ? std::vector<int>{32, 64} : std::vector<int>{32};
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    xmgn_status err = XMGN_OK;
+    for (int er : rows)
+      for (int nr : rows)
+        for (int wpc : {2, 4, 8}) {
+          const int g = ((cus * wpc + 7) / 8) * 8;
+          if ((err = xmgn_ctx_set_tiles(c, er, nr, g))) break;
+          auto step = [&]() -> xmgn_status {
+            if (xmgn_status r = xmgn_forward(c, d, params, ps, part_ids, n_batch, node_in, pos, edge_norm, out, 1,
+                                             stream))
+              return r;
+            return xmgn_backward(c, d, params, d_out, d_params, stream);
+          };
+          if ((err = step())) break;
+          (void)hipEventRecord(a, st);
+          for (int i = 0; i < 2 && !err; ++i) err = step();
+          (void)hipEventRecord(b, st);
+          if (err) break;
+          (void)hipEventSynchronize(b);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, a, b);
+          ms *= 0.5f;
+          if (best < 0.f || ms < best) {
+            best = ms;
+            best_e = er;
+            best_n = nr;
+            best_g = g;
+          }
+        }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (err) return err;
+    if (cache_path) {
+      std::ofstream f(cache_path, std::ios::app);
+      f << key << " " << best_e << " " << best_n << " " << best_g << " " << best << "\n";
+    }
+  }
+  if (xmgn_status r = xmgn_ctx_set_tiles(c, best_e, best_n, best_g)) return r;
+  if (edge_rows) *edge_rows = best_e;
+  if (node_rows) *node_rows = best_n;
+  if (grid) *grid = best_g;
+  if (step_ms) *step_ms = best;
   return XMGN_OK;
   GUARD_END
 }

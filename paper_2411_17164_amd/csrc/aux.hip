@@ -120,6 +120,12 @@ __global__ void k_wgrad_reduce(const float* __restrict__ partial, int n_chunks, 
   dst[(size_t)m * ldd + n] = s;
 }
 
+void launch_wgrad_reduce(const float* partial, int n_chunks, int M_valid, int N, float* dst, int ldd, int MN,
+                         hipStream_t st) {
+  const int tot = M_valid * N;
+  k_wgrad_reduce<<<(tot + 255) / 256, 256, 0, st>>>(partial, n_chunks, M_valid, N, dst, ldd, MN);
+}
+
 static int wgrad_chunks(int R, int* rows_per_chunk) {
   if (R <= 0) {
     *rows_per_chunk = WG_RC;

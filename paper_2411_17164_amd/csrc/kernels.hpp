@@ -81,7 +81,13 @@ struct EdgeBwdOut {
   void* du;        // [E][H] T
   void* z;         // [E][H] T
   float* partial;  // [grid][4H]: db1, db2, dgamma, dbeta
+  float* wpart;    // fused weight gradients [grid][2][H][H] (dW2, e-block of dW1) or NULL
 };
+// True when the edge adjoint accumulates dW2 and the e-block of dW1 itself
+// (then du and z are not written and wpart must be given).
+bool edge_bwd_fuses_wgrad(const Shape& s);
+void launch_wgrad_reduce(const float* partial, int n_chunks, int M_valid, int N, float* dst, int ldd, int MN,
+                         hipStream_t st);
 void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
                      const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st);
 

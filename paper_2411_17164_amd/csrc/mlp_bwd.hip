@@ -86,6 +86,43 @@ __device__ __forceinline__ void ln_backward(const f32x4 (&xh)[MB][NB], f32x4 (&d
         dv[mb][nb][r] = (g[mb][nb][r] - sg[mb][r] * (1.f / H) - xh[mb][nb][r] * (sgx[mb][r] * (1.f / H))) * inv[mb][r];
 }
 
+// Store the accumulator transposed ([col][row], row stride LDT) -- the four
+// values of a lane are consecutive rows of one column: one 8-byte store.
+template <int MB, int NB, int LDT>
+__device__ __forceinline__ void acc_to_lds_t(const f32x4 (&x)[MB][NB], bf16* dst, int n0) {
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      bf16x2 lo = {(bf16)x[mb][nb][0], (bf16)x[mb][nb][1]};
+      bf16x2 hi = {(bf16)x[mb][nb][2], (bf16)x[mb][nb][3]};
+      uint2 v;
+      v.x = *(const uint32_t*)&lo;
+      v.y = *(const uint32_t*)&hi;
+      *(uint2*)(dst + acc_col(n0, nb) * LDT + acc_row(mb, 0)) = v;
+    }
+}
+
+// acc (128 x 128, this wave's 64 x 64 quarter) += A^T-tile * B-tile over the
+// MT rows of a tile, with AT[m][k], BT[n][k] transposed tiles in LDS.
+template <int MT, int LDT>
+__device__ __forceinline__ void wave_wgrad(f32x4 (&acc)[4][4], const bf16* AT, const bf16* BT) {
+  const int w = wave_id(), wm = w & 1, wn = w >> 1;
+  const int l = lane_id(), li = l & 15, lg = l >> 4;
+#pragma unroll
+  for (int ks = 0; ks < MT; ks += 32) {
+    bf16x8 b[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) b[nb] = *(const bf16x8*)(BT + (wn * 64 + nb * 16 + li) * LDT + ks + lg * 8);
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const bf16x8 a = *(const bf16x8*)(AT + (wm * 64 + mb * 16 + li) * LDT + ks + lg * 8);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mma(a, b[nb], acc[mb][nb]);
+    }
+  }
+}
+
 template <int NB>
 __device__ __forceinline__ void write_partial(float* p, int n0, const float (&v)[NB]) {
   if ((lane_id() >> 4) == 0)
@@ -96,7 +133,10 @@ __device__ __forceinline__ void write_partial(float* p, int n0, const float (&v)
 // ---------------------------------------------------------------------------
 // Edge adjoint (with recompute).
 // ---------------------------------------------------------------------------
-template <typename T, int H, int MT, int ACT, int AGG>
+// FW: also accumulate dW2 = sum du z^T and the e-block of dW1 = sum da e^T
+// per workgroup on MFMA (BF16, H = 128), from transposed tiles in LDS, so
+// that z and du never travel to HBM; partials go to o.wpart.
+template <typename T, int H, int MT, int ACT, int AGG, int FW>
 __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T* __restrict__ h,
                                                    const T* __restrict__ e, const float* __restrict__ de_in,
                                                    const float* __restrict__ dm, EdgeBwdOut o, float eps) {
@@ -104,12 +144,18 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  constexpr int LDT = MT + 8;                              // transposed tiles (BF16)
+  constexpr size_t TS = FW ? (size_t)H * LDT * 2 : 0;
+  static_assert(!FW || (sizeof(T) == 2 && H == 128), "fused weight gradients: BF16, H = 128");
   static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
-  __shared__ __align__(16) unsigned char smem[XS + ZS + NWAVE * MT * 4 + 2 * MT * 4];
+  __shared__ __align__(16) unsigned char smem[XS + ZS + 3 * TS + NWAVE * MT * 4 + 2 * MT * 4];
   T* xs = (T*)smem;
   float* ft = (float*)smem;
   T* zs = (T*)(smem + XS);
-  float* red = (float*)(smem + XS + ZS);
+  bf16* eT = (bf16*)(smem + XS + ZS);
+  bf16* zT = (bf16*)(smem + XS + ZS + TS);
+  bf16* dT = (bf16*)(smem + XS + ZS + 2 * TS);  // du^T, then da^T
+  float* red = (float*)(smem + XS + ZS + 3 * TS);
   int* rs = (int*)(red + NWAVE * MT);
   const T* W1 = (const T*)w.W1;
   const T* W2 = (const T*)w.W2;
@@ -117,6 +163,11 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
   const T* W1Te = (const T*)w.W1T;
   const int n0 = wave_id() * D::CPW;
   float cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
+  f32x4 accW2[4][4], accW1[4][4];
+  if constexpr (FW) {
+    zero_acc(accW2);
+    zero_acc(accW1);
+  }
 
   TileSched sch(b.n_etiles);
   for (int t = sch.begin; t < sch.end; t += sch.step) {
@@ -132,6 +183,17 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
     global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, 0, [&](int i) { return h + (size_t)rs[i] * H; });
     global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, H, [&](int i) { return h + (size_t)ss[i] * H; });
     global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, 2 * H, [&](int i) { return e + (size_t)(e0 + i) * H; });
+    if constexpr (FW) {
+      // e^T for the dW1 e-block: 8 columns of one row per step
+      for (int c = threadIdx.x; c < MT * (H / 8); c += NTHR) {
+        const int i = c / (H / 8), q = c - i * (H / 8);
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (i < ne) v = *(const uint4*)(e + (size_t)(e0 + i) * H + q * 8);
+        const bf16* pv = (const bf16*)&v;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) eT[(q * 8 + t) * LDT + i] = pv[t];
+      }
+    }
     __syncthreads();
 
     // recompute: a, z, u, xhat
@@ -151,6 +213,7 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
         }
       }
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
+    if constexpr (FW) acc_to_lds_t<MB, NB, LDT>(x, zT, n0);
     __syncthreads();
     zero_acc(x);
     wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2, H, n0);
@@ -177,7 +240,7 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
       }
       return v;
     });
-    lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.z + (size_t)e0 * H, H, [](int i) { return i; });
+    if constexpr (!FW) lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.z + (size_t)e0 * H, H, [](int i) { return i; });
     __syncthreads();
     f32x4 g[MB][NB];
 #pragma unroll
@@ -189,8 +252,13 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
     ln_backward<MB, NB, MT, H>(x, g, inv, w.gamma, n0, red, cg, cbt);  // g = du (barriers inside)
     col_accumulate(g, cb2);
     acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
+    if constexpr (FW) acc_to_lds_t<MB, NB, LDT>(g, dT, n0);
     __syncthreads();
-    lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.du + (size_t)e0 * H, H, [](int i) { return i; });
+    if constexpr (FW) {
+      wave_wgrad<MT, LDT>(accW2, dT, zT);  // dW2 += du^T z
+    } else {
+      lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.du + (size_t)e0 * H, H, [](int i) { return i; });
+    }
     // dz = W2^T du ; da = dz * act'(a)
     zero_acc(x);
     wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2T, H, n0);
@@ -204,6 +272,7 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
     __syncthreads();
     acc_to_ldsf<MB, NB, D::LDF>(x, ft, n0);
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
+    if constexpr (FW) acc_to_lds_t<MB, NB, LDT>(x, dT, n0);
     __syncthreads();
     // S_r: receiver-segment sums of da (FP32, ascending sender order)
     const int nr = r1 - r0;
@@ -224,6 +293,7 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
     // de = de' (+ dm_r) + (W1^T da)[2H:3H]
     zero_acc(g);
     wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1Te, H, n0);
+    if constexpr (FW) wave_wgrad<MT, LDT>(accW1, dT, eT);  // dW1[:, 2H:3H] += da^T e
     __syncthreads();
     acc_to_ldsf<MB, NB, D::LDF>(g, ft, n0);
     __syncthreads();
@@ -253,6 +323,22 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
   write_partial<NB>(p + H, n0, cb2);
   write_partial<NB>(p + 2 * H, n0, cg);
   write_partial<NB>(p + 3 * H, n0, cbt);
+  if constexpr (FW) {
+    const int wv = wave_id(), wm = wv & 1, wn = wv >> 1;
+    const int li = lane_id() & 15, lg = lane_id() >> 4;
+    float* q2 = o.wpart + (size_t)blockIdx.x * 2 * H * H;
+    float* q1 = q2 + H * H;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = wm * 64 + mb * 16 + lg * 4 + r, n = wn * 64 + nb * 16 + li;
+          q2[m * H + n] = accW2[mb][nb][r];
+          q1[m * H + n] = accW1[mb][nb][r];
+        }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -763,14 +849,17 @@ constexpr bool node_fits() {
          (size_t)MT * (2 * H + 16 / sizeof(T)) * sizeof(T) + (size_t)MT * (H + 4) * 4 <= 160 * 1024;
 }
 
+bool edge_bwd_fuses_wgrad(const Shape& s) { return s.prec == 1 && s.H == 128; }
+
 void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
                      const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st) {
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
+    constexpr int FW = (sizeof(T) == 2 && H == 128) ? 1 : 0;
     if constexpr (edge_bwd_fits<T, H, MT>()) {
       if (s.agg)
-        k_edge_bwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, de_in, dm, o, s.eps);
+        k_edge_bwd<T, H, MT, ACT, 1, FW><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, de_in, dm, o, s.eps);
       else
-        k_edge_bwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, de_in, dm, o, s.eps);
+        k_edge_bwd<T, H, MT, ACT, 0, FW><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, de_in, dm, o, s.eps);
     } else {
       g_config_error = 1;
     }

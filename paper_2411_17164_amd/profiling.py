@@ -1,0 +1,109 @@
+"""Summaries of rocprofv3 output for the xmgn kernels.
+
+  python -m paper_2411_17164_amd.profiling stats <rocprof output dir>
+      per-kernel table from the --kernel-trace --stats CSV
+  python -m paper_2411_17164_amd.profiling traffic --fetch <dir> --write <dir>
+      --kernel <name substring> --calib <name substring> --calib-bytes <B>
+      --workload <name> --out <json>
+      HBM bytes per launch of a kernel from two --pmc runs (FETCH_SIZE, then
+      WRITE_SIZE, KiB per dispatch), each scaled by what the same counter
+      reads for a plain copy kernel of known size in the same process.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+import sys
+from collections import defaultdict
+
+
+def _find(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[-1]
+
+
+def short(name: str) -> str:
+    """Kernel name without template arguments and parameter lists."""
+    n = name
+    for tok in ("void ", "xmgn::"):
+        n = n.replace(tok, "")
+    return n.split("(")[0]
+
+
+def stats(d: str):
+    rows = []
+    with open(_find(d, "kernel_stats.csv")) as f:
+        for r in csv.DictReader(f):
+            rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6,
+                         float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[2])
+    return rows
+
+
+def counters(d: str, counter: str):
+    """{kernel name: [value per dispatch]} for one counter."""
+    out = defaultdict(list)
+    with open(_find(d, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") == counter:
+                out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return out
+
+
+def _match(table, sub):
+    names = [k for k in table if sub in k]
+    if not names:
+        raise KeyError(f"no kernel matching {sub!r}")
+    vals = [v for k in names for v in table[k]]
+    return sum(vals) / len(vals), len(vals), names
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--top", type=int, default=25)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--calib", required=True)
+    t.add_argument("--calib-bytes", type=float, required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--source-hash", required=True)
+    t.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        rows = stats(a.dir)
+        print("| kernel | calls | total ms | avg us | % |")
+        print("|---|---|---|---|---|")
+        for name, calls, tot, avg, pct in rows[: a.top]:
+            print(f"| {short(name)[:90]} | {calls} | {tot:.3f} | {avg:.1f} | {pct:.2f} |")
+        return 0
+    fetch = counters(a.fetch, "FETCH_SIZE")
+    write = counters(a.write, "WRITE_SIZE")
+    cf, _, _ = _match(fetch, a.calib)
+    cw, _, _ = _match(write, a.calib)
+    kf, nf, names = _match(fetch, a.kernel)
+    kw, nw, _ = _match(write, a.kernel)
+    sf = a.calib_bytes / (cf * 1024.0)
+    sw = a.calib_bytes / (cw * 1024.0)
+    rec = {"kernel": a.kernel, "workload": a.workload, "source_hash": a.source_hash,
+           "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "dispatches": [nf, nw],
+           "calib_fetch_kib": cf, "calib_write_kib": cw, "calib_bytes": a.calib_bytes,
+           "scale_fetch": sf, "scale_write": sw,
+           "bytes_per_launch": kf * 1024.0 * sf + kw * 1024.0 * sw, "kernel_names": names[:4]}
+    with open(a.out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

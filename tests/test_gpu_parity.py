@@ -126,6 +126,24 @@ def test_fwd_bwd_multiscale(api, ctx, precision, tol, agg):
     assert errs[worst] <= tol, errs
 
 
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 2e-2)])
+def test_fwd_bwd_15_layers(api, ctx, precision, tol):
+    """Full depth (15 layers) on the multi-scale recipe at reduced size: the
+    BF16 error budget has to hold through every layer, forward and back."""
+    case = Case(3, levels=(250, 1000, 4000), layers=15, precision=precision)
+    log(f"fwd+bwd 15 layers {precision}")
+    g = gpu_graph(api, ctx, case)
+    ps = api.Partset.halo(g, case.inp.pos, None, case.L)
+    out, loss, grad = gpu_step(api, ctx, case, ps, [0])
+    loss_r, y_r, g_r = om.step_full(case.desc, case.params.astype(np.float64), case.oracle_graph(),
+                                    case.inp.node_in, case.inp.pos, case.inp.edge_norm, case.inp.targets)
+    errs = per_tensor_errors(case, grad, g_r)
+    worst = sorted(errs.items(), key=lambda kv: -kv[1])[:5]
+    log(f"  out {rel_l2(out, y_r):.2e} loss {abs(loss - loss_r) / loss_r:.2e} worst grads {worst}")
+    assert rel_l2(out, y_r) <= tol
+    assert worst[0][1] <= tol, worst
+
+
 def test_fwd_bwd_silu_fp32(api, ctx):
     case = Case(2, levels=(3000,), layers=3, activation="silu")
     log("fwd+bwd silu fp32")
@@ -172,12 +190,19 @@ def test_partitions_equal_full_graph(api, ctx, precision):
     assert (y_parts == y_full).all()
     assert abs(loss_sum - loss_full) <= 1e-5 * loss_full
     g_acc = acc.cpu().numpy()
+    # FP32: the two sums differ by summation order only.  BF16: each
+    # partition rounds its own partial factors (e.g. sender sums over its
+    # local out-edges) to BF16, so the two agree to BF16 rounding, and both
+    # must meet the BF16 bound against the FP64 oracle.
+    tol_pair = 1e-5 if precision == "fp32" else 5e-3
     errs = per_tensor_errors(case, g_acc, g_full)
-    assert max(errs.values()) <= 1e-5, errs
+    worst = sorted(errs.items(), key=lambda kv: -kv[1])[:4]
+    log(f"  partition-sum vs full: {worst}")
+    assert worst[0][1] <= tol_pair, worst
     # all partitions in one batch (the ragged union) gives the same gradient
     y_b, loss_b, g_b = gpu_step(api, ctx, case, ps, list(range(len(sizes))))
     errs_b = per_tensor_errors(case, g_b, g_full)
-    assert max(errs_b.values()) <= 1e-5, errs_b
+    assert max(errs_b.values()) <= tol_pair, sorted(errs_b.items(), key=lambda kv: -kv[1])[:4]
     assert (y_b == y_full).all()
 
 
