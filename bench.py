@@ -99,8 +99,9 @@ def measured_traffic(workload: str, kernel: str):
 
 def cpu_baseline(cfg_idx: int, layers: int, hidden: int):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
-    the same geometry / multi-scale recipe at 1/200 of the points, full depth
-    and width, one forward + backward."""
+    the same geometry / multi-scale recipe at 1/200 of the points (1/800 at
+    H = 256, to keep the same amount of work), full depth and width, one
+    forward + backward."""
     from oracle import graph as og
     from oracle import model as om
     from synth import CONFIGS, init_params, make_inputs
@@ -110,7 +111,8 @@ def cpu_baseline(cfg_idx: int, layers: int, hidden: int):
     except Exception:  # noqa: BLE001
         cores = os.cpu_count() or 1
     cfg = CONFIGS[cfg_idx]
-    levels = tuple(max(200, lv // 200) for lv in cfg.levels)
+    div = 200 * (hidden // 128) ** 2
+    levels = tuple(max(200, lv // div) for lv in cfg.levels)
     inp = make_inputs(cfg, levels=levels)
     G = og.build_graph(inp.pos, levels, cfg.k_intra, cfg.k_cross if len(levels) > 1 else 0)
     d = om.Desc(hidden=hidden, layers=layers)
@@ -135,6 +137,7 @@ def main():
     ap.add_argument("--edge-rows", type=int, default=0)
     ap.add_argument("--node-rows", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--edge-waves", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tiles")
     ap.add_argument("--wave-parts", type=int, default=0,
                     help="partitions per batch (wave) for partitioned workloads (0 = all in one batch)")
@@ -166,7 +169,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     ctx = api.Context(0)
-    ctx.set_tiles(args.edge_rows, args.node_rows, args.grid)
+    ctx.set_tiles(args.edge_rows, args.node_rows, args.grid, args.edge_waves)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g = ctx.build_knn(pos, levels, cfg.k_intra, cfg.k_cross if len(levels) > 1 else 0)
@@ -209,11 +212,11 @@ def main():
                 api.grad_accumulate(acc, d_params)
 
         tuned = None
-        if not args.no_autotune and not (args.edge_rows or args.node_rows or args.grid):
-            ctx.set_tiles(0, 0, 0)
+        if not args.no_autotune and not (args.edge_rows or args.node_rows or args.grid or args.edge_waves):
+            ctx.set_tiles(0, 0, 0, 0)
             tuned = ctx.autotune(model, params, ps, waves[0], node_in, pos, inp.edge_norm, out, d_out, d_params)
             log(f"[bench] {prec}: autotuned edge_rows={tuned[0]} node_rows={tuned[1]} grid={tuned[2]} "
-                f"({tuned[3]:.2f} ms)")
+                f"edge_waves={tuned[3]} ({tuned[4]:.2f} ms)")
         log(f"[bench] {prec}: warmup {args.warmup}")
         for _ in range(max(1, args.warmup)):
             step()
@@ -295,7 +298,8 @@ def main():
         line["fp32_value"] = E * L / f["wall"]
         line["fp32_ms_per_step"] = round(f["wall"] * 1e3, 3)
         line["bf16_over_fp32"] = round(f["wall"] / bf["wall"], 3)
-    line["tiles"] = {p: (list(r["tiles"][:3]) if r["tiles"] else None) for p, r in results.items()}
+    line["tiles"] = {p: (dict(zip(["edge_rows", "node_rows", "grid", "edge_waves"], r["tiles"][:4]))
+                         if r["tiles"] else None) for p, r in results.items()}
     line["kernels_ms"] = {p: {k: round(v[0], 3) for k, v in r["kernels"].items()} for p, r in results.items()}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

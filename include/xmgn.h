@@ -102,11 +102,13 @@ xmgn_status xmgn_param_offset(const xmgn_model_desc* desc, int32_t block, int32_
 xmgn_status xmgn_ctx_create(int32_t device, xmgn_ctx** out);
 void xmgn_ctx_destroy(xmgn_ctx* ctx);
 
-/* Tile configuration of the processor kernels (rows per tile 32 or 64,
- * 0 = library default) and the persistent grid size in workgroups
- * (0 = library default).  Changing it invalidates cached batch plans. */
+/* Tile configuration of the processor kernels: rows per tile of the edge and
+ * node kernels (32 or 64), the persistent grid size in workgroups (a
+ * multiple of 8) and the waves per workgroup of the edge kernels (4 or 8);
+ * 0 selects the library default for any of them.  Changing it invalidates
+ * cached batch plans. */
 xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int32_t node_rows,
-                               int32_t grid);
+                               int32_t grid, int32_t edge_waves);
 
 /*
  * 1. Multi-scale kNN graph (Sec. III.B, III.C).
@@ -206,14 +208,16 @@ xmgn_status xmgn_backward(xmgn_ctx* ctx, const xmgn_model_desc* desc, const floa
                           const float* d_out, float* d_params, xmgn_stream stream);
 
 /*
- * Tile autotuner (batching).  Times one forward + backward of the batch for
- * every candidate configuration -- edge-tile rows {32, 64}, node-tile rows
- * {32, 64} (64 only at H = 128) and persistent grid {2, 4, 8} workgroups per
- * compute unit -- and keeps the fastest in ctx (as xmgn_ctx_set_tiles would).
+ * Tile autotuner (batching).  Times forward + backward of the batch over
+ * candidate configurations -- edge-tile rows {32, 64} x edge waves {4, 8} x
+ * persistent grid {4, 8} workgroups per compute unit, then node-tile rows
+ * {32, 64} for the best of those (64-row tiles only at H = 128) -- and keeps
+ * the fastest in ctx (as xmgn_ctx_set_tiles would).
  * Arguments as for xmgn_forward / xmgn_backward; out and d_params are
  * overwritten, d_out is only read.  cache_path (host string or NULL): a text
- * file of "key edge_rows node_rows grid ms" lines; a hit skips the timing,
- * a miss appends a line.  The key holds the device name, the model
+ * file of configuration lines; a hit skips the timing,
+ * a miss appends a line ("key edge_rows node_rows grid edge_waves ms").
+ * The key holds the device name, the model
  * description and the batch's node and edge counts.  The chosen
  * configuration and its step time are returned (any output pointer may be
  * NULL).  Synchronises the stream.
@@ -222,8 +226,8 @@ xmgn_status xmgn_autotune(xmgn_ctx* ctx, const xmgn_model_desc* desc, const floa
                           const xmgn_partset* ps, const int32_t* part_ids, int32_t n_batch,
                           const float* node_in, const float* pos, const float* edge_norm,
                           float* out, const float* d_out, float* d_params, const char* cache_path,
-                          int32_t* edge_rows, int32_t* node_rows, int32_t* grid, float* step_ms,
-                          xmgn_stream stream);
+                          int32_t* edge_rows, int32_t* node_rows, int32_t* grid, int32_t* edge_waves,
+                          float* step_ms, xmgn_stream stream);
 
 /* 5. acc[i] += g[i] for i < n (dev FP32), elementwise, deterministic
  * (gradient aggregation over partitions, Sec. III.A). */

@@ -44,7 +44,7 @@ _SIGS = {
     "xmgn_param_offset": (_i32, [_pdesc, _i32, _i32, _i32, _pi64]),
     "xmgn_ctx_create": (_i32, [_i32, C.POINTER(_p)]),
     "xmgn_ctx_destroy": (None, [_p]),
-    "xmgn_ctx_set_tiles": (_i32, [_p, _i32, _i32, _i32]),
+    "xmgn_ctx_set_tiles": (_i32, [_p, _i32, _i32, _i32, _i32]),
     "xmgn_ctx_memory": (_i32, [_p, _pi64]),
     "xmgn_ctx_set_timing": (_i32, [_p, _i32]),
     "xmgn_ctx_timing_count": (_i32, [_p, _pi32]),
@@ -65,7 +65,7 @@ _SIGS = {
     "xmgn_backward": (_i32, [_p, _pdesc, _p, _p, _p, _p]),
     "xmgn_grad_accumulate": (_i32, [_p, _p, _i64, _p]),
     "xmgn_autotune": (_i32, [_p, _pdesc, _p, _p, _pi32, _i32, _p, _p, _pf, _p, _p, _p, C.c_char_p,
-                             _pi32, _pi32, _pi32, _pf, _p]),
+                             _pi32, _pi32, _pi32, _pi32, _pf, _p]),
 }
 
 

@@ -176,8 +176,8 @@ class Context:
         self._h = h
         self.device = device
 
-    def set_tiles(self, edge_rows: int = 0, node_rows: int = 0, grid: int = 0):
-        check(lib.xmgn_ctx_set_tiles(self._h, edge_rows, node_rows, grid))
+    def set_tiles(self, edge_rows: int = 0, node_rows: int = 0, grid: int = 0, edge_waves: int = 0):
+        check(lib.xmgn_ctx_set_tiles(self._h, edge_rows, node_rows, grid, edge_waves))
 
     def set_timing(self, enable: bool):
         check(lib.xmgn_ctx_set_timing(self._h, 1 if enable else 0))
@@ -220,16 +220,16 @@ class Context:
                  pos: torch.Tensor, edge_norm, out: torch.Tensor, d_out: torch.Tensor, d_params: torch.Tensor,
                  cache_path: str | None = None, stream=None):
         """Pick the fastest tile configuration for this batch (see
-        xmgn_autotune); returns (edge_rows, node_rows, grid, step_ms)."""
+        xmgn_autotune); returns (edge_rows, node_rows, grid, edge_waves, step_ms)."""
         ids = _i32(part_ids)
         en = np.ascontiguousarray(edge_norm, dtype=np.float32).reshape(-1)
         self._fwd_refs = (params, node_in, pos)
-        er, nr, g, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
+        er, nr, g, wv, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
         check(lib.xmgn_autotune(self._h, C.byref(model.desc()), _dev(params), ps._h, _ptr32(ids), len(ids),
                                 _dev(node_in), _dev(pos), en.ctypes.data_as(C.POINTER(C.c_float)), _dev(out),
                                 _dev(d_out), _dev(d_params), cache_path.encode() if cache_path else None,
-                                C.byref(er), C.byref(nr), C.byref(g), C.byref(ms), _stream(stream)))
-        return er.value, nr.value, g.value, ms.value
+                                C.byref(er), C.byref(nr), C.byref(g), C.byref(wv), C.byref(ms), _stream(stream)))
+        return er.value, nr.value, g.value, wv.value, ms.value
 
     def mse_grad(self, out: torch.Tensor, target: torch.Tensor, n_total: int, d_out: torch.Tensor,
                  loss: torch.Tensor, stream=None):

@@ -18,11 +18,6 @@
 
 using namespace xmgn;
 
-namespace xmgn {
-void launch_vec_reduce_strided(const float* partial, int G, int row, int src, int runs, int inner, int src_stride,
-                               float* dst, int dst_stride, hipStream_t st);
-}
-
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
@@ -459,7 +454,7 @@ struct BlockW {
 
 struct xmgn_ctx {
   int device = 0;
-  int mt_edge = 0, mt_node = 0, grid = 0;  // 0 = default
+  int mt_edge = 0, mt_node = 0, grid = 0, nw_edge = 0;  // 0 = default
   Batch batch;
   bool have_batch = false;
   // weights
@@ -474,7 +469,7 @@ struct xmgn_ctx {
   int tape_slots_h = 0, tape_slots_e = 0, tape_slots_m = 0;
   bool tape_full = false;
   // backward workspace
-  DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, wfused, lossp;
+  DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, wfused, redtmp, lossp;
   // per-kernel timing
   bool timing = false;
   std::vector<std::string> tnames;
@@ -546,6 +541,7 @@ static Shape make_shape(const xmgn_ctx* c, const xmgn_model_desc* d) {
   s.mt_edge = me;
   s.mt_node = mn;
   s.grid = c->grid > 0 ? c->grid : 1024;
+  s.nw_edge = c->nw_edge > 0 ? c->nw_edge : 4;
   return s;
 }
 
@@ -612,8 +608,10 @@ extern "C" xmgn_status xmgn_ctx_timing_read(xmgn_ctx* c, int32_t i, char* name, 
   return XMGN_OK;
 }
 
-extern "C" xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int32_t node_rows, int32_t grid) {
+extern "C" xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int32_t node_rows, int32_t grid,
+                                          int32_t edge_waves) {
   if (!ctx) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (edge_waves != 0 && edge_waves != 4 && edge_waves != 8) return fail(XMGN_ERR_INVALID, "edge_waves must be 0, 4 or 8");
   if (edge_rows != 0 && edge_rows != 32 && edge_rows != 64) return fail(XMGN_ERR_INVALID, "edge_rows must be 0, 32 or 64");
   if (node_rows != 0 && node_rows != 32 && node_rows != 64) return fail(XMGN_ERR_INVALID, "node_rows must be 0, 32 or 64");
   if (grid < 0 || (grid > 0 && (grid < 8 || grid % 8 != 0 || grid > 65536)))
@@ -621,6 +619,7 @@ extern "C" xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int3
   ctx->mt_edge = edge_rows;
   ctx->mt_node = node_rows;
   ctx->grid = grid;
+  ctx->nw_edge = edge_waves;
   ctx->have_batch = false;
   ctx->fwd_valid = false;
   return XMGN_OK;
@@ -630,7 +629,7 @@ extern "C" xmgn_status xmgn_ctx_memory(const xmgn_ctx* c, int64_t* bytes) {
   if (!c || !bytes) return fail(XMGN_ERR_INVALID, "NULL argument");
   const DBuf* bufs[] = {&c->batch.ints, &c->jobs_dev, &c->blob, &c->h, &c->e, &c->m, &c->dhA, &c->dhMid,
                         &c->dm, &c->Sr, &c->Ss, &c->deA, &c->deB, &c->fa, &c->fb, &c->fc, &c->fd,
-                        &c->dy, &c->part, &c->wpart, &c->wfused, &c->lossp};
+                        &c->dy, &c->part, &c->wpart, &c->wfused, &c->redtmp, &c->lossp};
   int64_t t = 0;
   for (const DBuf* b : bufs) t += (int64_t)b->bytes;
   *bytes = t;
@@ -933,7 +932,7 @@ extern "C" xmgn_status xmgn_mse_grad(xmgn_ctx* c, const float* out, const float*
 
 static void wgrad_run(xmgn_ctx* c, const Shape& s, WgradOp op, DBuf& wpart, hipStream_t st) {
   KT("wgrad");
-  launch_wgrad(s, op, wpart.as<float>(), st);
+  launch_wgrad(s, op, wpart.as<float>(), c->redtmp.as<float>(), st);
 }
 #define wgrad(s_, op_, wp_, st_) wgrad_run(c, s_, op_, wp_, st_)
 
@@ -997,6 +996,8 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   if (fw) se.grid = std::min(s.grid, 512);
   if (fw)
     if (xmgn_status r = c->wfused.ensure((size_t)se.grid * 2 * H * H * 4)) return r;
+  if (xmgn_status r = c->redtmp.ensure(reduce_tmp_floats((int)std::max<size_t>(H * H, 16 * H)) * 4)) return r;
+  float* rt = c->redtmp.as<float>();
   float* part = c->part.as<float>();
   auto P = [&](int block, int layer, int t) { return d_params + poff(d, block, layer, t); };
   auto hl = [&](int l) { return hslot(c, d, l); };
@@ -1008,7 +1009,7 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     DecBwdOut o{c->dhA.as<float>(), c->fa.p, c->fb.p, c->fc.p, c->fd.p, c->dy.as<float>(), part};
     { KT("dec_bwd"); launch_dec_bwd(s, b, weights(c, d, params, 2 + 2 * L, 4, 0), hl(L), d_out, d->out_dim, o, st); }
     VecSeg segs[3] = {{0, (int)H, P(4, 0, 1)}, {(int)H, (int)H, P(4, 0, 3)}, {2 * (int)H, d->out_dim, P(4, 0, 5)}};
-    launch_vec_reduce(part, G, 2 * (int)H + 16, segs, 3, st);
+    launch_vec_reduce(part, G, 2 * (int)H + 16, segs, 3, rt, st);
     const int ni = c->batch.n_inner;
     wgrad(s, wop(c->dy.p, 1, 16, 0, nullptr, c->fb.p, 0, (int)H, 0, nullptr, ni, 16, (int)H, P(4, 0, 4), (int)H,
                  d->out_dim), c->wpart, st);
@@ -1027,7 +1028,7 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     { KT("node_bwd"); launch_node_bwd(s, b, wn, hl(l), mslot(c, d, l), c->dhA.as<float>(), no, st); }
     VecSeg ns[4] = {{0, (int)H, P(3, l, 1)}, {(int)H, (int)H, P(3, l, 3)}, {2 * (int)H, (int)H, P(3, l, 4)},
                     {3 * (int)H, (int)H, P(3, l, 5)}};
-    launch_vec_reduce(part, G, 4 * (int)H, ns, 4, st);
+    launch_vec_reduce(part, G, 4 * (int)H, ns, 4, rt, st);
     wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 0),
                  2 * (int)H), c->wpart, st);
     wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, mslot(c, d, l), 1, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
@@ -1041,12 +1042,12 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     { KT("edge_bwd"); launch_edge_bwd(se, b, we, hl(l), eslot(c, d, l), de_in, c->dm.as<float>(), eo, st); }
     VecSeg es[4] = {{0, (int)H, P(2, l, 1)}, {(int)H, (int)H, P(2, l, 3)}, {2 * (int)H, (int)H, P(2, l, 4)},
                     {3 * (int)H, (int)H, P(2, l, 5)}};
-    launch_vec_reduce(part, se.grid, 4 * (int)H, es, 4, st);
+    launch_vec_reduce(part, se.grid, 4 * (int)H, es, 4, rt, st);
     if (fw) {
       KT("wgrad");
-      launch_wgrad_reduce(c->wfused.as<float>(), se.grid, (int)H, (int)H, P(2, l, 2), (int)H, 2 * (int)(H * H), st);
+      launch_wgrad_reduce(c->wfused.as<float>(), se.grid, (int)H, (int)H, P(2, l, 2), (int)H, 2 * (int)(H * H), rt, st);
       launch_wgrad_reduce(c->wfused.as<float>() + H * H, se.grid, (int)H, (int)H, P(2, l, 0) + 2 * H, 3 * (int)H,
-                          2 * (int)(H * H), st);
+                          2 * (int)(H * H), rt, st);
     }
     { KT("sender_sum"); launch_sender_sum(s, b, c->fa.p, c->Ss.as<float>(), st); }
     { KT("node_dh"); launch_node_dh(s, b, we, c->dhMid.as<float>(), c->Sr.as<float>(), c->Ss.as<float>(), c->dhA.as<float>(), st); }
@@ -1080,8 +1081,8 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     }
     VecSeg vs[5] = {{0, (int)H, P(blk, 0, 1)}, {(int)H, (int)H, P(blk, 0, 3)}, {2 * (int)H, (int)H, P(blk, 0, 5)},
                     {3 * (int)H, (int)H, P(blk, 0, 6)}, {4 * (int)H, (int)H, P(blk, 0, 7)}};
-    launch_vec_reduce(part, G, 13 * (int)H, vs, 5, st);
-    launch_vec_reduce_strided(part, G, 13 * (int)H, 5 * (int)H, (int)H, in_dim, 8, P(blk, 0, 0), in_dim, st);
+    launch_vec_reduce(part, G, 13 * (int)H, vs, 5, rt, st);
+    launch_vec_reduce_strided(part, G, 13 * (int)H, 5 * (int)H, (int)H, in_dim, 8, P(blk, 0, 0), in_dim, rt, st);
     wgrad(s, wop(c->fd.p, 0, (int)H, 0, nullptr, c->fb.p, 0, (int)H, 0, nullptr, R, (int)H, (int)H, P(blk, 0, 4),
                  (int)H), c->wpart, st);
     wgrad(s, wop(c->fc.p, 0, (int)H, 0, nullptr, c->fa.p, 0, (int)H, 0, nullptr, R, (int)H, (int)H, P(blk, 0, 2),
@@ -1158,8 +1159,8 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
                                      const xmgn_partset* ps, const int32_t* part_ids, int32_t n_batch,
                                      const float* node_in, const float* pos, const float* edge_norm, float* out,
                                      const float* d_out, float* d_params, const char* cache_path,
-                                     int32_t* edge_rows, int32_t* node_rows, int32_t* grid, float* step_ms,
-                                     xmgn_stream stream) {
+                                     int32_t* edge_rows, int32_t* node_rows, int32_t* grid, int32_t* edge_waves,
+                                     float* step_ms, xmgn_stream stream) {
   GUARD_BEGIN
   if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
   if (xmgn_status s = check_desc(d)) return s;
@@ -1169,74 +1170,80 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, c->device));
   const int cus = prop.multiProcessorCount;
-  // key needs the batch sizes: build the plan with the current tiles first
+  // the key needs the batch sizes: build the plan with the current tiles first
   if (xmgn_status r = xmgn_forward(c, d, params, ps, part_ids, n_batch, node_in, pos, edge_norm, out, 1, stream))
     return r;
   const std::string key = tune_key(c, d);
-  int best_e = 0, best_n = 0, best_g = 0;
-  float best = -1.f;
+  int best[4] = {0, 0, 0, 0};
+  float best_ms = -1.f;
   if (cache_path) {
     std::ifstream f(cache_path);
     std::string line;
     while (std::getline(f, line)) {
       std::istringstream is(line);
       std::string k;
-      int e, n, g;
+      int e, n, g, wv;
       float ms;
-      if (is >> k >> e >> n >> g >> ms && k == key) {
-        best_e = e;
-        best_n = n;
-        best_g = g;
-        best = ms;
+      if (is >> k >> e >> n >> g >> wv >> ms && k == key) {
+        best[0] = e;
+        best[1] = n;
+        best[2] = g;
+        best[3] = wv;
+        best_ms = ms;
       }
     }
   }
-  if (best < 0.f) {
-    std::vector<int> rows = d->hidden == 128 ? std::vector<int>{32, 64} : std::vector<int>{32};
+  if (best_ms < 0.f) {
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     xmgn_status err = XMGN_OK;
+    auto trial = [&](int er, int nr, int g, int wv) -> xmgn_status {
+      if (xmgn_status r = xmgn_ctx_set_tiles(c, er, nr, g, wv)) return r;
+      auto step = [&]() -> xmgn_status {
+        if (xmgn_status r = xmgn_forward(c, d, params, ps, part_ids, n_batch, node_in, pos, edge_norm, out, 1, stream))
+          return r;
+        return xmgn_backward(c, d, params, d_out, d_params, stream);
+      };
+      if (xmgn_status r = step()) return r;
+      (void)hipEventRecord(a, st);
+      for (int i = 0; i < 2; ++i)
+        if (xmgn_status r = step()) return r;
+      (void)hipEventRecord(b, st);
+      (void)hipEventSynchronize(b);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      ms *= 0.5f;
+      if (best_ms < 0.f || ms < best_ms) {
+        best_ms = ms;
+        best[0] = er;
+        best[1] = nr;
+        best[2] = g;
+        best[3] = wv;
+      }
+      return XMGN_OK;
+    };
+    const std::vector<int> rows = d->hidden == 128 ? std::vector<int>{32, 64} : std::vector<int>{32};
+    // stage 1: edge kernels (the bulk of the step), stage 2: node tiles
     for (int er : rows)
-      for (int nr : rows)
-        for (int wpc : {2, 4, 8}) {
-          const int g = ((cus * wpc + 7) / 8) * 8;
-          if ((err = xmgn_ctx_set_tiles(c, er, nr, g))) break;
-          auto step = [&]() -> xmgn_status {
-            if (xmgn_status r = xmgn_forward(c, d, params, ps, part_ids, n_batch, node_in, pos, edge_norm, out, 1,
-                                             stream))
-              return r;
-            return xmgn_backward(c, d, params, d_out, d_params, stream);
-          };
-          if ((err = step())) break;
-          (void)hipEventRecord(a, st);
-          for (int i = 0; i < 2 && !err; ++i) err = step();
-          (void)hipEventRecord(b, st);
-          if (err) break;
-          (void)hipEventSynchronize(b);
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, a, b);
-          ms *= 0.5f;
-          if (best < 0.f || ms < best) {
-            best = ms;
-            best_e = er;
-            best_n = nr;
-            best_g = g;
-          }
-        }
+      for (int wv : {4, 8})
+        for (int wpc : {4, 8})
+          if (!err) err = trial(er, 32, ((cus * wpc + 7) / 8) * 8, wv);
+    if (!err && rows.size() > 1) err = trial(best[0], 64, best[2], best[3]);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (err) return err;
     if (cache_path) {
       std::ofstream f(cache_path, std::ios::app);
-      f << key << " " << best_e << " " << best_n << " " << best_g << " " << best << "\n";
+      f << key << " " << best[0] << " " << best[1] << " " << best[2] << " " << best[3] << " " << best_ms << "\n";
     }
   }
-  if (xmgn_status r = xmgn_ctx_set_tiles(c, best_e, best_n, best_g)) return r;
-  if (edge_rows) *edge_rows = best_e;
-  if (node_rows) *node_rows = best_n;
-  if (grid) *grid = best_g;
-  if (step_ms) *step_ms = best;
+  if (xmgn_status r = xmgn_ctx_set_tiles(c, best[0], best[1], best[2], best[3])) return r;
+  if (edge_rows) *edge_rows = best[0];
+  if (node_rows) *node_rows = best[1];
+  if (grid) *grid = best[2];
+  if (edge_waves) *edge_waves = best[3];
+  if (step_ms) *step_ms = best_ms;
   return XMGN_OK;
   GUARD_END
 }

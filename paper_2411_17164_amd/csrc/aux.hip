@@ -110,20 +110,54 @@ __global__ __launch_bounds__(NTHR) void k_wgrad(WgradOp op, int rows_per_chunk, 
       }
 }
 
-__global__ void k_wgrad_reduce(const float* __restrict__ partial, int n_chunks, int M_valid, int N,
-                               float* __restrict__ dst, int ldd, int MN) {
+// Fixed-order column sums of a [rows][stride] partial matrix, in two
+// stages: stage 1 sums rows [s*per, (s+1)*per) of each column into
+// tmp[s][col] (grid.y = split s); stage 2 adds the splits in order.  The
+// result depends only on (rows, splits), never on scheduling.
+constexpr int RED_SPLITS = 32;
+
+__global__ void k_colsum_stage1(const float* __restrict__ src, int rows, int stride, int ncol, int per,
+                                float* __restrict__ tmp) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncol) return;
+  const int s = blockIdx.y;
+  const int r0 = s * per, r1 = min(rows, r0 + per);
+  float a0 = 0.f, a1 = 0.f;
+  int r = r0;
+  for (; r + 1 < r1; r += 2) {  // two independent loads in flight, fixed pairing
+    a0 += src[(size_t)r * stride + j];
+    a1 += src[(size_t)(r + 1) * stride + j];
+  }
+  if (r < r1) a0 += src[(size_t)r * stride + j];
+  tmp[(size_t)s * ncol + j] = a0 + a1;
+}
+
+__global__ void k_wgrad_reduce(const float* __restrict__ tmp, int splits, int M_valid, int N,
+                               float* __restrict__ dst, int ldd, int ncol) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M_valid * N) return;
   const int m = idx / N, n = idx - m * N;
   float s = 0.f;
-  for (int c = 0; c < n_chunks; ++c) s += partial[(size_t)c * MN + idx];
+  for (int k = 0; k < splits; ++k) s += tmp[(size_t)k * ncol + idx];
   dst[(size_t)m * ldd + n] = s;
 }
 
+size_t reduce_tmp_floats(int max_cols) { return (size_t)RED_SPLITS * (size_t)max_cols; }
+
+// dst[m * ldd + n] = sum over r < rows of src[r * stride + m * N + n], m < M_valid.
+// tmp: caller scratch of reduce_tmp_floats(M_valid * N) floats.
+static void colsum_to(const float* src, int rows, int stride, int M_valid, int N, float* dst, int ldd, float* tmp,
+                      hipStream_t st) {
+  const int ncol = M_valid * N;
+  const int splits = rows < RED_SPLITS ? (rows > 0 ? rows : 1) : RED_SPLITS;
+  const int per = rows > 0 ? (rows + splits - 1) / splits : 0;
+  k_colsum_stage1<<<dim3((ncol + 255) / 256, splits), 256, 0, st>>>(src, rows, stride, ncol, per, tmp);
+  k_wgrad_reduce<<<(ncol + 255) / 256, 256, 0, st>>>(tmp, splits, M_valid, N, dst, ldd, ncol);
+}
+
 void launch_wgrad_reduce(const float* partial, int n_chunks, int M_valid, int N, float* dst, int ldd, int MN,
-                         hipStream_t st) {
-  const int tot = M_valid * N;
-  k_wgrad_reduce<<<(tot + 255) / 256, 256, 0, st>>>(partial, n_chunks, M_valid, N, dst, ldd, MN);
+                         float* tmp, hipStream_t st) {
+  colsum_to(partial, n_chunks, MN, M_valid, N, dst, ldd, tmp, st);
 }
 
 static int wgrad_chunks(int R, int* rows_per_chunk) {
@@ -145,7 +179,7 @@ size_t wgrad_partial_floats(const Shape&, const WgradOp& op) {
   return (size_t)(nc > 0 ? nc : 1) * op.M * op.N;
 }
 
-void launch_wgrad(const Shape& s, const WgradOp& op, float* partial, hipStream_t st) {
+void launch_wgrad(const Shape& s, const WgradOp& op, float* partial, float* tmp, hipStream_t st) {
   int rpc;
   const int nc = wgrad_chunks(op.R, &rpc);
   const int nbm = (op.M + WG_B - 1) / WG_B, nbn = (op.N + WG_B - 1) / WG_B;
@@ -160,8 +194,7 @@ void launch_wgrad(const Shape& s, const WgradOp& op, float* partial, hipStream_t
       k_wgrad<float, float, float><<<grid, NTHR, 0, st>>>(op, rpc, nbm, partial);
     }
   }
-  const int tot = op.M_valid * op.N;
-  k_wgrad_reduce<<<(tot + 255) / 256, 256, 0, st>>>(partial, nc, op.M_valid, op.N, op.dst, op.ldd, op.M * op.N);
+  colsum_to(partial, nc, op.M * op.N, op.M_valid, op.N, op.dst, op.ldd, tmp, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -177,19 +210,28 @@ struct VecSegs {
   float* dst[16];
 };
 
-__global__ void k_vec_reduce(const float* __restrict__ partial, int G, int row, VecSegs s) {
+__global__ void k_vec_reduce(const float* __restrict__ tmp, int splits, int row, VecSegs s) {
   const int seg = blockIdx.y;
   if (seg >= s.n) return;
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < s.len[seg]; j += gridDim.x * blockDim.x) {
     const int run = j / s.inner[seg], k = j - run * s.inner[seg];
     const int src = s.src[seg] + run * s.src_stride[seg] + k;
     float acc = 0.f;
-    for (int g = 0; g < G; ++g) acc += partial[(size_t)g * row + src];
+    for (int g = 0; g < splits; ++g) acc += tmp[(size_t)g * row + src];
     s.dst[seg][run * s.dst_stride[seg] + k] = acc;
   }
 }
 
-void launch_vec_reduce(const float* partial, int G, int row, const VecSeg* segs, int n_seg, hipStream_t st) {
+// stage 1 of the vector reductions: column sums of [G][row] in RED_SPLITS groups
+static const float* vec_stage1(const float* partial, int G, int row, int* splits, float* tmp, hipStream_t st) {
+  *splits = G < RED_SPLITS ? G : RED_SPLITS;
+  const int per = (G + *splits - 1) / *splits;
+  k_colsum_stage1<<<dim3((row + 255) / 256, *splits), 256, 0, st>>>(partial, G, row, row, per, tmp);
+  return tmp;
+}
+
+void launch_vec_reduce(const float* partial, int G, int row, const VecSeg* segs, int n_seg, float* tmp,
+                       hipStream_t st) {
   VecSegs s{};
   s.n = n_seg;
   int maxlen = 1;
@@ -202,13 +244,15 @@ void launch_vec_reduce(const float* partial, int G, int row, const VecSeg* segs,
     s.dst[i] = segs[i].dst;
     if (segs[i].len > maxlen) maxlen = segs[i].len;
   }
-  k_vec_reduce<<<dim3((maxlen + 255) / 256, n_seg), 256, 0, st>>>(partial, G, row, s);
+  int splits;
+  const float* t1 = vec_stage1(partial, G, row, &splits, tmp, st);
+  k_vec_reduce<<<dim3((maxlen + 255) / 256, n_seg), 256, 0, st>>>(t1, splits, row, s);
 }
 
 // Strided variant: dst[c * dst_stride + k] = sum_g partial[g][src + c * src_stride + k],
 // c < runs, k < inner.
 void launch_vec_reduce_strided(const float* partial, int G, int row, int src, int runs, int inner, int src_stride,
-                               float* dst, int dst_stride, hipStream_t st) {
+                               float* dst, int dst_stride, float* tmp, hipStream_t st) {
   VecSegs s{};
   s.n = 1;
   s.src[0] = src;
@@ -217,7 +261,9 @@ void launch_vec_reduce_strided(const float* partial, int G, int row, int src, in
   s.src_stride[0] = src_stride;
   s.dst_stride[0] = dst_stride;
   s.dst[0] = dst;
-  k_vec_reduce<<<dim3((runs * inner + 255) / 256, 1), 256, 0, st>>>(partial, G, row, s);
+  int splits;
+  const float* t1 = vec_stage1(partial, G, row, &splits, tmp, st);
+  k_vec_reduce<<<dim3((runs * inner + 255) / 256, 1), 256, 0, st>>>(t1, splits, row, s);
 }
 
 // ---------------------------------------------------------------------------

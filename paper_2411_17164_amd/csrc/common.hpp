@@ -137,10 +137,10 @@ __device__ __forceinline__ float sum_groups(float s) {
   return s;
 }
 
-// Full-row sums of x over all columns of all 4 waves.  red: LDS float
-// [NWAVE][MT].  Returns out[mb][r] = sum over the row acc_row(mb, r).
-// Contains two barriers.
-template <int MB, int NB, int MT>
+// Full-row sums of x over all columns of all NW waves.  red: LDS float
+// [NW][MT].  Returns out[mb][r] = sum over the row acc_row(mb, r), the wave
+// partials added in wave order.  Contains two barriers.
+template <int MB, int NB, int MT, int NW = NWAVE>
 __device__ __forceinline__ void row_sum(const f32x4 (&x)[MB][NB], float* red, float (&out)[MB][4]) {
   const int w = wave_id(), l = lane_id();
 #pragma unroll
@@ -159,18 +159,21 @@ __device__ __forceinline__ void row_sum(const f32x4 (&x)[MB][NB], float* red, fl
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = acc_row(mb, r);
-      out[mb][r] = (red[row] + red[MT + row]) + (red[2 * MT + row] + red[3 * MT + row]);
+      float t = 0.f;
+#pragma unroll
+      for (int k = 0; k < NW; k += 2) t += red[k * MT + row] + red[(k + 1) * MT + row];
+      out[mb][r] = t;
     }
   __syncthreads();
 }
 
 // LayerNorm of the rows of u (in place -> xhat), returning inv std per row.
 // Statistics in FP32, two passes (mean, then mean of squared deviations).
-template <int MB, int NB, int MT, int H>
+template <int MB, int NB, int MT, int H, int NW = NWAVE>
 __device__ __forceinline__ void ln_normalize(f32x4 (&u)[MB][NB], float* red, float eps,
                                              float (&inv)[MB][4]) {
   float s[MB][4];
-  row_sum<MB, NB, MT>(u, red, s);
+  row_sum<MB, NB, MT, NW>(u, red, s);
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -184,7 +187,7 @@ __device__ __forceinline__ void ln_normalize(f32x4 (&u)[MB][NB], float* red, flo
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) sq[mb][nb][r] = u[mb][nb][r] * u[mb][nb][r];
-  row_sum<MB, NB, MT>(sq, red, s);
+  row_sum<MB, NB, MT, NW>(sq, red, s);
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -228,7 +231,7 @@ __device__ __forceinline__ void lds_rows_to_global(const T* src, int rows, int w
                                                    size_t ld_dst, RowFn row_index) {
   constexpr int E = 16 / sizeof(T);
   const int cpr = width / E;
-  for (int c = threadIdx.x; c < rows * cpr; c += NTHR) {
+  for (int c = threadIdx.x; c < rows * cpr; c += blockDim.x) {
     const int i = c / cpr, q = c - i * cpr;
     *(uint4*)(dst + (size_t)row_index(i) * ld_dst + q * E) = *(const uint4*)(src + i * LD + q * E);
   }
@@ -240,7 +243,7 @@ template <typename T, int LD, int MT, typename SrcFn>
 __device__ __forceinline__ void global_rows_to_lds(T* dst, int rows, int width, int col0, SrcFn src_row) {
   constexpr int E = 16 / sizeof(T);
   const int cpr = width / E;
-  for (int c = threadIdx.x; c < MT * cpr; c += NTHR) {
+  for (int c = threadIdx.x; c < MT * cpr; c += blockDim.x) {
     const int i = c / cpr, q = c - i * cpr;
     uint4 v = {0u, 0u, 0u, 0u};
     if (i < rows) v = *(const uint4*)(src_row(i) + q * E);
@@ -252,7 +255,7 @@ __device__ __forceinline__ void global_rows_to_lds(T* dst, int rows, int width, 
 template <typename T, int LD, int MT, typename SrcFn>
 __device__ __forceinline__ void global_f32_rows_to_lds(T* dst, int rows, int width, int col0, SrcFn src_row) {
   const int cpr = width / 4;
-  for (int c = threadIdx.x; c < MT * cpr; c += NTHR) {
+  for (int c = threadIdx.x; c < MT * cpr; c += blockDim.x) {
     const int i = c / cpr, q = c - i * cpr;
     float4 v = {0.f, 0.f, 0.f, 0.f};
     if (i < rows) v = *(const float4*)(src_row(i) + q * 4);

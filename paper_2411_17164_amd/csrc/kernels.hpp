@@ -53,6 +53,7 @@ struct Shape {
   int mt_edge;  // rows per edge tile
   int mt_node;  // rows per node tile
   int grid;     // persistent grid (workgroups)
+  int nw_edge;  // waves per workgroup of the edge kernels (4 or 8)
   float eps;
 };
 
@@ -86,8 +87,11 @@ struct EdgeBwdOut {
 // True when the edge adjoint accumulates dW2 and the e-block of dW1 itself
 // (then du and z are not written and wpart must be given).
 bool edge_bwd_fuses_wgrad(const Shape& s);
+// Fixed-order sums over the rows of partial matrices use a two-stage
+// reduction with caller scratch of reduce_tmp_floats(columns) floats.
+size_t reduce_tmp_floats(int max_cols);
 void launch_wgrad_reduce(const float* partial, int n_chunks, int M_valid, int N, float* dst, int ldd, int MN,
-                         hipStream_t st);
+                         float* tmp, hipStream_t st);
 void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
                      const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st);
 
@@ -147,7 +151,7 @@ struct WgradOp {
   int ldd;
 };
 size_t wgrad_partial_floats(const Shape& s, const WgradOp& op);
-void launch_wgrad(const Shape& s, const WgradOp& op, float* partial, hipStream_t st);
+void launch_wgrad(const Shape& s, const WgradOp& op, float* partial, float* tmp, hipStream_t st);
 
 struct VecSeg {
   int src;  // offset in the partial row
@@ -155,8 +159,10 @@ struct VecSeg {
   float* dst;
 };
 // dst[j] = sum over g < G of partial[g * row + src + j] for every segment.
-void launch_vec_reduce(const float* partial, int G, int row, const VecSeg* segs, int n_seg,
+void launch_vec_reduce(const float* partial, int G, int row, const VecSeg* segs, int n_seg, float* tmp,
                        hipStream_t st);
+void launch_vec_reduce_strided(const float* partial, int G, int row, int src, int runs, int inner, int src_stride,
+                               float* dst, int dst_stride, float* tmp, hipStream_t st);
 
 struct PrepJob {
   int64_t src_off;   // element offset in the FP32 params

@@ -21,21 +21,21 @@
 
 namespace xmgn {
 
-template <typename T, int H>
+template <typename T, int H, int NW = NWAVE>
 struct BD {
   static constexpr int PAD = 16 / sizeof(T);
   static constexpr int LDH = H + PAD;
   static constexpr int LD2 = 2 * H + PAD;
   static constexpr int LD3 = 3 * H + PAD;
   static constexpr int LDF = H + 4;
-  static constexpr int NB = H / 64;
-  static constexpr int CPW = H / 4;
+  static constexpr int NB = H / (16 * NW);
+  static constexpr int CPW = H / NW;
 };
 
 // Copy an FP32 [rows][H] block from global into an FP32 LDS tile (zero fill).
 template <int H, int LDF, int MT, typename SrcFn>
 __device__ __forceinline__ void f32_rows_to_lds(float* dst, int rows, SrcFn src) {
-  for (int c = threadIdx.x; c < MT * (H / 4); c += NTHR) {
+  for (int c = threadIdx.x; c < MT * (H / 4); c += blockDim.x) {
     const int i = c / (H / 4), q = c - i * (H / 4);
     float4 v = {0.f, 0.f, 0.f, 0.f};
     if (i < rows) v = src(i, q);
@@ -55,7 +55,7 @@ __device__ __forceinline__ void acc_to_ldsf(const f32x4 (&x)[MB][NB], float* dst
 
 // LayerNorm adjoint in registers.  On entry xh = xhat, dv = upstream
 // gradient (C layout); on exit dv holds du.  Accumulates dgamma, dbeta.
-template <int MB, int NB, int MT, int H>
+template <int MB, int NB, int MT, int H, int NW = NWAVE>
 __device__ __forceinline__ void ln_backward(const f32x4 (&xh)[MB][NB], f32x4 (&dv)[MB][NB], const float (&inv)[MB][4],
                                             const float* gamma, int n0, float* red, float (&cg)[NB],
                                             float (&cbt)[NB]) {
@@ -75,8 +75,8 @@ __device__ __forceinline__ void ln_backward(const f32x4 (&xh)[MB][NB], f32x4 (&d
   col_accumulate(t, cg);
   col_accumulate(dv, cbt);
   float sg[MB][4], sgx[MB][4];
-  row_sum<MB, NB, MT>(g, red, sg);
-  row_sum<MB, NB, MT>(gx, red, sgx);
+  row_sum<MB, NB, MT, NW>(g, red, sg);
+  row_sum<MB, NB, MT, NW>(gx, red, sgx);
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -103,22 +103,25 @@ __device__ __forceinline__ void acc_to_lds_t(const f32x4 (&x)[MB][NB], bf16* dst
     }
 }
 
-// acc (128 x 128, this wave's 64 x 64 quarter) += A^T-tile * B-tile over the
-// MT rows of a tile, with AT[m][k], BT[n][k] transposed tiles in LDS.
-template <int MT, int LDT>
-__device__ __forceinline__ void wave_wgrad(f32x4 (&acc)[4][4], const bf16* AT, const bf16* BT) {
+// acc (this wave's 64 x (128 / (NW/2)) block of a 128 x 128 product) +=
+// A^T-tile * B-tile over the MT rows of a tile, with AT[m][k], BT[n][k]
+// transposed tiles in LDS.  Waves: wm = w % 2 picks the rows, wn = w / 2
+// the columns.
+template <int MT, int LDT, int NW>
+__device__ __forceinline__ void wave_wgrad(f32x4 (&acc)[4][8 / NW * 2], const bf16* AT, const bf16* BT) {
+  constexpr int WNB = 8 / NW * 2;  // 16-column blocks per wave (4 at NW = 4, 2 at NW = 8)
   const int w = wave_id(), wm = w & 1, wn = w >> 1;
   const int l = lane_id(), li = l & 15, lg = l >> 4;
 #pragma unroll
   for (int ks = 0; ks < MT; ks += 32) {
-    bf16x8 b[4];
+    bf16x8 b[WNB];
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) b[nb] = *(const bf16x8*)(BT + (wn * 64 + nb * 16 + li) * LDT + ks + lg * 8);
+    for (int nb = 0; nb < WNB; ++nb) b[nb] = *(const bf16x8*)(BT + (wn * WNB * 16 + nb * 16 + li) * LDT + ks + lg * 8);
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
       const bf16x8 a = *(const bf16x8*)(AT + (wm * 64 + mb * 16 + li) * LDT + ks + lg * 8);
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mma(a, b[nb], acc[mb][nb]);
+      for (int nb = 0; nb < WNB; ++nb) acc[mb][nb] = mma(a, b[nb], acc[mb][nb]);
     }
   }
 }
@@ -136,11 +139,12 @@ __device__ __forceinline__ void write_partial(float* p, int n0, const float (&v)
 // FW: also accumulate dW2 = sum du z^T and the e-block of dW1 = sum da e^T
 // per workgroup on MFMA (BF16, H = 128), from transposed tiles in LDS, so
 // that z and du never travel to HBM; partials go to o.wpart.
-template <typename T, int H, int MT, int ACT, int AGG, int FW>
-__global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T* __restrict__ h,
-                                                   const T* __restrict__ e, const float* __restrict__ de_in,
-                                                   const float* __restrict__ dm, EdgeBwdOut o, float eps) {
-  using D = BD<T, H>;
+template <typename T, int H, int MT, int ACT, int AGG, int FW, int NW>
+__global__ __launch_bounds__(64 * NW) void k_edge_bwd(BatchView b, MlpW w, const T* __restrict__ h,
+                                                      const T* __restrict__ e, const float* __restrict__ de_in,
+                                                      const float* __restrict__ dm, EdgeBwdOut o, float eps) {
+  using D = BD<T, H, NW>;
+  constexpr int WNB = 8 / NW * 2;
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
@@ -148,7 +152,7 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
   constexpr size_t TS = FW ? (size_t)H * LDT * 2 : 0;
   static_assert(!FW || (sizeof(T) == 2 && H == 128), "fused weight gradients: BF16, H = 128");
   static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
-  __shared__ __align__(16) unsigned char smem[XS + ZS + 3 * TS + NWAVE * MT * 4 + 2 * MT * 4];
+  __shared__ __align__(16) unsigned char smem[XS + ZS + 3 * TS + NW * MT * 4 + 2 * MT * 4];
   T* xs = (T*)smem;
   float* ft = (float*)smem;
   T* zs = (T*)(smem + XS);
@@ -156,14 +160,14 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
   bf16* zT = (bf16*)(smem + XS + ZS + TS);
   bf16* dT = (bf16*)(smem + XS + ZS + 2 * TS);  // du^T, then da^T
   float* red = (float*)(smem + XS + ZS + 3 * TS);
-  int* rs = (int*)(red + NWAVE * MT);
+  int* rs = (int*)(red + NW * MT);
   const T* W1 = (const T*)w.W1;
   const T* W2 = (const T*)w.W2;
   const T* W2T = (const T*)w.W2T;
   const T* W1Te = (const T*)w.W1T;
   const int n0 = wave_id() * D::CPW;
   float cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
-  f32x4 accW2[4][4], accW1[4][4];
+  f32x4 accW2[4][WNB], accW1[4][WNB];
   if constexpr (FW) {
     zero_acc(accW2);
     zero_acc(accW1);
@@ -185,7 +189,7 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
     global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, 2 * H, [&](int i) { return e + (size_t)(e0 + i) * H; });
     if constexpr (FW) {
       // e^T for the dW1 e-block: 8 columns of one row per step
-      for (int c = threadIdx.x; c < MT * (H / 8); c += NTHR) {
+      for (int c = threadIdx.x; c < MT * (H / 8); c += 64 * NW) {
         const int i = c / (H / 8), q = c - i * (H / 8);
         uint4 v = {0u, 0u, 0u, 0u};
         if (i < ne) v = *(const uint4*)(e + (size_t)(e0 + i) * H + q * 8);
@@ -226,7 +230,7 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
         for (int r = 0; r < 4; ++r) x[mb][nb][r] += bb;
       }
     float inv[MB][4];
-    ln_normalize<MB, NB, MT, H>(x, red, eps, inv);  // x = xhat
+    ln_normalize<MB, NB, MT, H, NW>(x, red, eps, inv);  // x = xhat
 
     // upstream gradient dv = dm_r + de'_k  (FP32 tile over the dead gather)
     f32_rows_to_lds<H, D::LDF, MT>(ft, ne, [&](int i, int q) {
@@ -249,13 +253,13 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) g[mb][nb][r] = ft[acc_row(mb, r) * D::LDF + acc_col(n0, nb)];
-    ln_backward<MB, NB, MT, H>(x, g, inv, w.gamma, n0, red, cg, cbt);  // g = du (barriers inside)
+    ln_backward<MB, NB, MT, H, NW>(x, g, inv, w.gamma, n0, red, cg, cbt);  // g = du (barriers inside)
     col_accumulate(g, cb2);
     acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
     if constexpr (FW) acc_to_lds_t<MB, NB, LDT>(g, dT, n0);
     __syncthreads();
     if constexpr (FW) {
-      wave_wgrad<MT, LDT>(accW2, dT, zT);  // dW2 += du^T z
+      wave_wgrad<MT, LDT, NW>(accW2, dT, zT);  // dW2 += du^T z
     } else {
       lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.du + (size_t)e0 * H, H, [](int i) { return i; });
     }
@@ -276,7 +280,7 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
     __syncthreads();
     // S_r: receiver-segment sums of da (FP32, ascending sender order)
     const int nr = r1 - r0;
-    for (int task = threadIdx.x; task < nr * (H / 4); task += NTHR) {
+    for (int task = threadIdx.x; task < nr * (H / 4); task += 64 * NW) {
       const int rl = task / (H / 4), q = task - rl * (H / 4);
       const int lo = b.row_ptr[r0 + rl] - e0, hi = b.row_ptr[r0 + rl + 1] - e0;
       float4 s = {0.f, 0.f, 0.f, 0.f};
@@ -293,11 +297,11 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
     // de = de' (+ dm_r) + (W1^T da)[2H:3H]
     zero_acc(g);
     wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1Te, H, n0);
-    if constexpr (FW) wave_wgrad<MT, LDT>(accW1, dT, eT);  // dW1[:, 2H:3H] += da^T e
+    if constexpr (FW) wave_wgrad<MT, LDT, NW>(accW1, dT, eT);  // dW1[:, 2H:3H] += da^T e
     __syncthreads();
     acc_to_ldsf<MB, NB, D::LDF>(g, ft, n0);
     __syncthreads();
-    for (int c = threadIdx.x; c < ne * (H / 4); c += NTHR) {
+    for (int c = threadIdx.x; c < ne * (H / 4); c += 64 * NW) {
       const int i = c / (H / 4), q = c - i * (H / 4);
       float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
       if (de_in) {
@@ -331,10 +335,10 @@ __global__ __launch_bounds__(NTHR) void k_edge_bwd(BatchView b, MlpW w, const T*
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
+      for (int nb = 0; nb < WNB; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int m = wm * 64 + mb * 16 + lg * 4 + r, n = wn * 64 + nb * 16 + li;
+          const int m = wm * 64 + mb * 16 + lg * 4 + r, n = wn * WNB * 16 + nb * 16 + li;
           q2[m * H + n] = accW2[mb][nb][r];
           q1[m * H + n] = accW1[mb][nb][r];
         }
@@ -498,31 +502,37 @@ __global__ __launch_bounds__(NTHR) void k_node_dh(int n, const T* __restrict__ B
 }
 
 // S_s[s] = sum over the out-edges of s (CSC order: ascending receiver) of da.
-// One wave per sender; each lane owns H/64 consecutive columns.
+// A sender's row is covered by LPR lanes holding 16 bytes each; a wave takes
+// 64 / LPR senders at once, and the edge loop is unrolled so several row
+// loads are in flight.  Every lane adds its columns in CSC order.
 template <typename T, int H>
 __global__ __launch_bounds__(NTHR) void k_sender_sum(int n, const int* __restrict__ csc_ptr, const int* __restrict__ csc_edge,
                                                      const T* __restrict__ da, float* __restrict__ S_s) {
-  constexpr int C = H / 64;
+  constexpr int E = 16 / sizeof(T);   // elements per lane
+  constexpr int LPR = H / E;          // lanes per row
+  constexpr int SPW = 64 / LPR;       // senders per wave
+  static_assert(LPR <= 64 && 64 % LPR == 0, "row must map onto a wave");
   const int l = lane_id();
+  const int sub = l / LPR, q = l - sub * LPR;
   const int nw = gridDim.x * NWAVE;
-  for (int s = blockIdx.x * NWAVE + wave_id(); s < n; s += nw) {
-    const int lo = csc_ptr[s], hi = csc_ptr[s + 1];
-    float acc[C];
+  for (int s0 = (blockIdx.x * NWAVE + wave_id()) * SPW; s0 < n; s0 += nw * SPW) {
+    const int s = s0 + sub;
+    float acc[E];
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = 0.f;
-    for (int j = lo; j < hi; ++j) {
-      const T* row = da + (size_t)csc_edge[j] * H + l * C;
-      if constexpr (sizeof(T) == 2 && C == 2) {
-        const bf16x2 v = *(const bf16x2*)row;
-        acc[0] += (float)v[0];
-        acc[1] += (float)v[1];
-      } else {
+    for (int c = 0; c < E; ++c) acc[c] = 0.f;
+    if (s < n) {
+      const int lo = csc_ptr[s], hi = csc_ptr[s + 1];
+#pragma unroll 4
+      for (int j = lo; j < hi; ++j) {
+        const uint4 v = *(const uint4*)(da + (size_t)csc_edge[j] * H + q * E);
+        const T* pv = (const T*)&v;
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] += to_f(row[c]);
+        for (int c = 0; c < E; ++c) acc[c] += to_f(pv[c]);
       }
-    }
+      float* dst = S_s + (size_t)s * H + q * E;
 #pragma unroll
-    for (int c = 0; c < C; ++c) S_s[(size_t)s * H + l * C + c] = acc[c];
+      for (int c = 0; c < E; c += 4) *(float4*)(dst + c) = make_float4(acc[c], acc[c + 1], acc[c + 2], acc[c + 3]);
+    }
   }
 }
 
@@ -851,19 +861,30 @@ constexpr bool node_fits() {
 
 bool edge_bwd_fuses_wgrad(const Shape& s) { return s.prec == 1 && s.H == 128; }
 
-void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
-                     const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st) {
+template <int NW>
+static void edge_bwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
+                        const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st) {
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
     constexpr int FW = (sizeof(T) == 2 && H == 128) ? 1 : 0;
     if constexpr (edge_bwd_fits<T, H, MT>()) {
       if (s.agg)
-        k_edge_bwd<T, H, MT, ACT, 1, FW><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, de_in, dm, o, s.eps);
+        k_edge_bwd<T, H, MT, ACT, 1, FW, NW><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, de_in, dm, o,
+                                                                         s.eps);
       else
-        k_edge_bwd<T, H, MT, ACT, 0, FW><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, de_in, dm, o, s.eps);
+        k_edge_bwd<T, H, MT, ACT, 0, FW, NW><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, de_in, dm, o,
+                                                                         s.eps);
     } else {
       g_config_error = 1;
     }
   }))));
+}
+
+void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
+                     const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st) {
+  if (s.nw_edge == 8)
+    edge_bwd_nw<8>(s, b, w, h, e, de_in, dm, o, st);
+  else
+    edge_bwd_nw<4>(s, b, w, h, e, de_in, dm, o, st);
 }
 
 void launch_node_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const float* m,

@@ -8,15 +8,15 @@
 
 namespace xmgn {
 
-template <typename T, int H>
+template <typename T, int H, int NW = NWAVE>
 struct Dims {
   static constexpr int PAD = 16 / sizeof(T);
   static constexpr int LDH = H + PAD;          // one H-wide tile
   static constexpr int LD2 = 2 * H + PAD;      // [h | m]
   static constexpr int LD3 = 3 * H + PAD;      // [h_r | h_s | e]
   static constexpr int LDF = H + 4;            // FP32 tile
-  static constexpr int NB = H / 64;            // 16-column blocks per wave
-  static constexpr int CPW = H / 4;            // columns per wave
+  static constexpr int NB = H / (16 * NW);     // 16-column blocks per wave
+  static constexpr int CPW = H / NW;           // columns per wave
 };
 
 // ---------------------------------------------------------------------------
@@ -26,21 +26,22 @@ struct Dims {
 // A tile holds whole receiver segments, so m_r is summed in one workgroup in
 // ascending sender order (the CSR order) -- deterministic, no atomics.
 // ---------------------------------------------------------------------------
-template <typename T, int H, int MT, int ACT, int AGG>
-__global__ __launch_bounds__(NTHR) void k_edge_fwd(BatchView b, MlpW w, const T* __restrict__ h,
-                                                   const T* __restrict__ e, T* __restrict__ e_out,
-                                                   float* __restrict__ m, float eps) {
-  using D = Dims<T, H>;
+// NW waves per workgroup; each wave owns H / NW output columns of every GEMM.
+template <typename T, int H, int MT, int ACT, int AGG, int NW>
+__global__ __launch_bounds__(64 * NW) void k_edge_fwd(BatchView b, MlpW w, const T* __restrict__ h,
+                                                      const T* __restrict__ e, T* __restrict__ e_out,
+                                                      float* __restrict__ m, float eps) {
+  using D = Dims<T, H, NW>;
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
   static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
-  __shared__ __align__(16) unsigned char smem[XS + ZS + NWAVE * MT * 4 + 2 * MT * 4];
+  __shared__ __align__(16) unsigned char smem[XS + ZS + NW * MT * 4 + 2 * MT * 4];
   T* xs = (T*)smem;
   float* ft = (float*)smem;  // aliases xs once the gathered tile is dead
   T* zs = (T*)(smem + XS);
   float* red = (float*)(smem + XS + ZS);
-  int* rs = (int*)(red + NWAVE * MT);
+  int* rs = (int*)(red + NW * MT);
   int* ss = rs + MT;
   const T* W1 = (const T*)w.W1;
   const T* W2 = (const T*)w.W2;
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(NTHR) void k_edge_fwd(BatchView b, MlpW w, const T*
         for (int r = 0; r < 4; ++r) acc[mb][nb][r] += bb;
       }
     float inv[MB][4];
-    ln_normalize<MB, NB, MT, H>(acc, red, eps, inv);  // barriers: GEMM2 done everywhere
+    ln_normalize<MB, NB, MT, H, NW>(acc, red, eps, inv);  // barriers: GEMM2 done everywhere
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(NTHR) void k_edge_fwd(BatchView b, MlpW w, const T*
 
     // m_r: sequential sum over the receiver's edges (ascending sender id)
     const int nr = r1 - r0;
-    for (int task = threadIdx.x; task < nr * (H / 4); task += NTHR) {
+    for (int task = threadIdx.x; task < nr * (H / 4); task += 64 * NW) {
       const int rl = task / (H / 4), q = task - rl * (H / 4);
       const int lo = b.row_ptr[r0 + rl] - e0, hi = b.row_ptr[r0 + rl + 1] - e0;
       float4 s = {0.f, 0.f, 0.f, 0.f};
@@ -414,19 +415,30 @@ constexpr bool edge_fits() {
              (size_t)MT * 4 * 8 <= 160 * 1024;
 }
 
-void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
-                     void* e_out, float* m, hipStream_t st) {
-  if (b.n_etiles == 0) return;
+template <int NW>
+static void edge_fwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e, void* e_out,
+                        float* m, hipStream_t st) {
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
     if constexpr (edge_fits<T, H, MT>()) {
       if (s.agg)
-        k_edge_fwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m, s.eps);
+        k_edge_fwd<T, H, MT, ACT, 1, NW><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m,
+                                                                     s.eps);
       else
-        k_edge_fwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m, s.eps);
+        k_edge_fwd<T, H, MT, ACT, 0, NW><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m,
+                                                                     s.eps);
     } else {
       g_config_error = 1;
     }
   }))));
+}
+
+void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
+                     void* e_out, float* m, hipStream_t st) {
+  if (b.n_etiles == 0) return;
+  if (s.nw_edge == 8)
+    edge_fwd_nw<8>(s, b, w, h, e, e_out, m, st);
+  else
+    edge_fwd_nw<4>(s, b, w, h, e, e_out, m, st);
 }
 
 void launch_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const float* m,

@@ -36,11 +36,27 @@ def short(name: str) -> str:
 
 
 def stats(d: str):
+    """[(kernel, calls, total ms, avg us, %)] from the --stats CSV, or from
+    the kernel trace (rocpd2csv export) when no stats file exists."""
     rows = []
-    with open(_find(d, "kernel_stats.csv")) as f:
-        for r in csv.DictReader(f):
-            rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6,
-                         float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    try:
+        path = _find(d, "kernel_stats.csv")
+    except FileNotFoundError:
+        path = None
+    if path:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6,
+                             float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    else:
+        acc = defaultdict(lambda: [0, 0.0])
+        with open(_find(d, "kernel_trace.csv")) as f:
+            for r in csv.DictReader(f):
+                a = acc[r["Kernel_Name"]]
+                a[0] += 1
+                a[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        tot = sum(v[1] for v in acc.values()) or 1.0
+        rows = [(k, c, t, t / c * 1e3, 100.0 * t / tot) for k, (c, t) in acc.items()]
     rows.sort(key=lambda x: -x[2])
     return rows
 
@@ -48,7 +64,11 @@ def stats(d: str):
 def counters(d: str, counter: str):
     """{kernel name: [value per dispatch]} for one counter."""
     out = defaultdict(list)
-    with open(_find(d, "counter_collection.csv")) as f:
+    try:
+        path = _find(d, "counter_collection.csv")
+    except FileNotFoundError:
+        path = _find(d, "counter_collection_trace.csv")
+    with open(path) as f:
         for r in csv.DictReader(f):
             if r.get("Counter_Name") == counter:
                 out[r["Kernel_Name"]].append(float(r["Counter_Value"]))

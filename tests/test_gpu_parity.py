@@ -144,6 +144,25 @@ def test_fwd_bwd_15_layers(api, ctx, precision, tol):
     assert worst[0][1] <= tol, worst
 
 
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 2e-2)])
+@pytest.mark.parametrize("edge_rows,edge_waves", [(32, 8), (64, 8), (32, 4)])
+def test_tile_configs(api, precision, tol, edge_rows, edge_waves):
+    """Every tile / wave configuration the autotuner may pick gives the same
+    results within the bound (and the same outputs as the default tiles)."""
+    c = api.Context(0)
+    c.set_tiles(edge_rows, 32, 256, edge_waves)
+    case = Case(3, levels=(500, 2000, 6000), layers=3, precision=precision)
+    g = gpu_graph(api, c, case)
+    ps = api.Partset.halo(g, case.inp.pos, None, case.L)
+    out, loss, grad = gpu_step(api, c, case, ps, [0])
+    loss_r, y_r, g_r = om.step_full(case.desc, case.params.astype(np.float64), case.oracle_graph(),
+                                    case.inp.node_in, case.inp.pos, case.inp.edge_norm, case.inp.targets)
+    errs = per_tensor_errors(case, grad, g_r)
+    log(f"  tiles {edge_rows}x{edge_waves} {precision}: out {rel_l2(out, y_r):.2e} worst {max(errs.values()):.2e}")
+    assert rel_l2(out, y_r) <= tol
+    assert max(errs.values()) <= tol
+
+
 def test_fwd_bwd_silu_fp32(api, ctx):
     case = Case(2, levels=(3000,), layers=3, activation="silu")
     log("fwd+bwd silu fp32")
