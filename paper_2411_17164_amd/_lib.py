@@ -10,7 +10,8 @@ import os
 import re
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libxmgn.so")
+# XMGN_LIB selects another build of the library (e.g. an instrumented one)
+LIB_PATH = os.environ.get("XMGN_LIB") or os.path.join(_HERE, "libxmgn.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "xmgn.h")
 
 XMGN_OK = 0

@@ -122,12 +122,20 @@ __device__ __forceinline__ void zero_acc(f32x4 (&acc)[MB][NB]) {
 __device__ __forceinline__ int acc_row(int mb, int r) { return mb * 16 + (lane_id() >> 4) * 4 + r; }
 __device__ __forceinline__ int acc_col(int n0, int nb) { return n0 + nb * 16 + (lane_id() & 15); }
 
-// Sum over the 16 lanes that share a lane group (same rows, 16 columns).
+// Sum over the 16 lanes of a DPP row (same rows, 16 columns), with DPP lane
+// moves (no LDS traffic): pairs (quad_perm 1,0,3,2), quads (2,3,0,1),
+// halves (row_half_mirror) and the two halves of the row (row_mirror).  Each
+// step adds a lane to its partner, so every lane ends with the same sum.
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float s) {
+  const int v = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, s), CTRL, 0xF, 0xF, false);
+  return s + __builtin_bit_cast(float, v);
+}
 __device__ __forceinline__ float sum16(float s) {
-  s += __shfl_xor(s, 1);
-  s += __shfl_xor(s, 2);
-  s += __shfl_xor(s, 4);
-  s += __shfl_xor(s, 8);
+  s = dpp_add<0xB1>(s);   // quad_perm [1,0,3,2]
+  s = dpp_add<0x4E>(s);   // quad_perm [2,3,0,1]
+  s = dpp_add<0x141>(s);  // row_half_mirror
+  s = dpp_add<0x140>(s);  // row_mirror
   return s;
 }
 // Sum over the 4 lane groups (same column, 4 x 4 rows).
@@ -167,49 +175,112 @@ __device__ __forceinline__ void row_sum(const f32x4 (&x)[MB][NB], float* red, fl
   __syncthreads();
 }
 
+// Two row sums (of x and of y) exchanged across the NW waves in one barrier
+// round.  red: LDS float [2][NW][MT].
+template <int MB, int NB, int MT, int NW = NWAVE>
+__device__ __forceinline__ void row_sum2(const f32x4 (&x)[MB][NB], const f32x4 (&y)[MB][NB], float* red,
+                                         float (&ox)[MB][4], float (&oy)[MB][4]) {
+  const int w = wave_id(), l = lane_id();
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float a = 0.f, c = 0.f;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        a += x[mb][nb][r];
+        c += y[mb][nb][r];
+      }
+      a = sum16(a);
+      c = sum16(c);
+      if ((l & 15) == 0) {
+        red[w * MT + acc_row(mb, r)] = a;
+        red[(NW + w) * MT + acc_row(mb, r)] = c;
+      }
+    }
+  __syncthreads();
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = acc_row(mb, r);
+      float a = 0.f, c = 0.f;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        a += red[k * MT + row];
+        c += red[(NW + k) * MT + row];
+      }
+      ox[mb][r] = a;
+      oy[mb][r] = c;
+    }
+  __syncthreads();
+}
+
 // LayerNorm of the rows of u (in place -> xhat), returning inv std per row.
-// Statistics in FP32, two passes (mean, then mean of squared deviations).
+// Statistics in FP32.  Each wave takes the mean and the sum of squared
+// deviations (M2) over its own H / NW columns; the waves' (mean, M2) pairs
+// are merged in one barrier round with the pairwise-variance formula
+// M2 = sum_w [M2_w + n_w (mean_w - mean)^2].  red: LDS float [2][NW][MT].
 template <int MB, int NB, int MT, int H, int NW = NWAVE>
 __device__ __forceinline__ void ln_normalize(f32x4 (&u)[MB][NB], float* red, float eps,
                                              float (&inv)[MB][4]) {
-  float s[MB][4];
-  row_sum<MB, NB, MT, NW>(u, red, s);
+  constexpr float CPW = (float)(H / NW);
+  const int w = wave_id(), l = lane_id();
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+    for (int r = 0; r < 4; ++r) {
+      float a = 0.f;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) u[mb][nb][r] -= s[mb][r] * (1.f / H);
-  f32x4 sq[MB][NB];
+      for (int nb = 0; nb < NB; ++nb) a += u[mb][nb][r];
+      const float mw = sum16(a) * (1.f / CPW);
+      float q = 0.f;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float d = u[mb][nb][r] - mw;
+        q += d * d;
+      }
+      q = sum16(q);
+      if ((l & 15) == 0) {
+        red[w * MT + acc_row(mb, r)] = mw;
+        red[(NW + w) * MT + acc_row(mb, r)] = q;
+      }
+    }
+  __syncthreads();
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+    for (int r = 0; r < 4; ++r) {
+      const int row = acc_row(mb, r);
+      float mean = 0.f;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sq[mb][nb][r] = u[mb][nb][r] * u[mb][nb][r];
-  row_sum<MB, NB, MT, NW>(sq, red, s);
+      for (int k = 0; k < NW; ++k) mean += red[k * MT + row];
+      mean *= 1.f / NW;
+      float m2 = 0.f;
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
+      for (int k = 0; k < NW; ++k) {
+        const float dm = red[k * MT + row] - mean;
+        m2 += red[(NW + k) * MT + row] + CPW * dm * dm;
+      }
+      inv[mb][r] = rsqrtf(m2 * (1.f / H) + eps);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) inv[mb][r] = rsqrtf(s[mb][r] * (1.f / H) + eps);
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) u[mb][nb][r] *= inv[mb][r];
+      for (int nb = 0; nb < NB; ++nb) u[mb][nb][r] = (u[mb][nb][r] - mean) * inv[mb][r];
+    }
+  __syncthreads();
 }
 
 // Column sums of x over all rows held by the wave, accumulated into acc[nb]
-// (every lane of a column ends with the same total).
+// (every lane of a column ends with the same total).  The per-workgroup
+// running sums over many tiles are FP64: they add up long, cancelling
+// series of tile sums (bias and LayerNorm gradients).
 template <int MB, int NB>
-__device__ __forceinline__ void col_accumulate(const f32x4 (&x)[MB][NB], float (&acc)[NB]) {
+__device__ __forceinline__ void col_accumulate(const f32x4 (&x)[MB][NB], double (&acc)[NB]) {
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     float s = 0.f;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) s += (x[mb][nb][0] + x[mb][nb][1]) + (x[mb][nb][2] + x[mb][nb][3]);
-    acc[nb] += sum_groups(s);
+    acc[nb] += (double)sum_groups(s);
   }
 }
 

@@ -57,9 +57,21 @@ __device__ __forceinline__ void acc_to_ldsf(const f32x4 (&x)[MB][NB], float* dst
 // gradient (C layout); on exit dv holds du.  Accumulates dgamma, dbeta.
 template <int MB, int NB, int MT, int H, int NW = NWAVE>
 __device__ __forceinline__ void ln_backward(const f32x4 (&xh)[MB][NB], f32x4 (&dv)[MB][NB], const float (&inv)[MB][4],
-                                            const float* gamma, int n0, float* red, float (&cg)[NB],
-                                            float (&cbt)[NB]) {
-  f32x4 g[MB][NB], gx[MB][NB], t[MB][NB];
+                                            const float* gamma, int n0, float* red, double (&cg)[NB],
+                                            double (&cbt)[NB]) {
+  f32x4 gx[MB][NB];
+  {
+    f32x4 t[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t[mb][nb][r] = dv[mb][nb][r] * xh[mb][nb][r];
+    col_accumulate(t, cg);
+  }
+  col_accumulate(dv, cbt);
+  // dv := g = dv * gamma ; gx = g * xhat
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -67,23 +79,19 @@ __device__ __forceinline__ void ln_backward(const f32x4 (&xh)[MB][NB], f32x4 (&d
       const float gm = gamma[acc_col(n0, nb)];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        t[mb][nb][r] = dv[mb][nb][r] * xh[mb][nb][r];
-        g[mb][nb][r] = dv[mb][nb][r] * gm;
-        gx[mb][nb][r] = g[mb][nb][r] * xh[mb][nb][r];
+        dv[mb][nb][r] *= gm;
+        gx[mb][nb][r] = dv[mb][nb][r] * xh[mb][nb][r];
       }
     }
-  col_accumulate(t, cg);
-  col_accumulate(dv, cbt);
   float sg[MB][4], sgx[MB][4];
-  row_sum<MB, NB, MT, NW>(g, red, sg);
-  row_sum<MB, NB, MT, NW>(gx, red, sgx);
+  row_sum2<MB, NB, MT, NW>(dv, gx, red, sg, sgx);
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        dv[mb][nb][r] = (g[mb][nb][r] - sg[mb][r] * (1.f / H) - xh[mb][nb][r] * (sgx[mb][r] * (1.f / H))) * inv[mb][r];
+        dv[mb][nb][r] = (dv[mb][nb][r] - sg[mb][r] * (1.f / H) - xh[mb][nb][r] * (sgx[mb][r] * (1.f / H))) * inv[mb][r];
 }
 
 // Store the accumulator transposed ([col][row], row stride LDT) -- the four
@@ -127,10 +135,10 @@ __device__ __forceinline__ void wave_wgrad(f32x4 (&acc)[4][8 / NW * 2], const bf
 }
 
 template <int NB>
-__device__ __forceinline__ void write_partial(float* p, int n0, const float (&v)[NB]) {
+__device__ __forceinline__ void write_partial(float* p, int n0, const double (&v)[NB]) {
   if ((lane_id() >> 4) == 0)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) p[acc_col(n0, nb)] = v[nb];
+    for (int nb = 0; nb < NB; ++nb) p[acc_col(n0, nb)] = (float)v[nb];
 }
 
 // ---------------------------------------------------------------------------
@@ -152,7 +160,7 @@ __global__ __launch_bounds__(64 * NW) void k_edge_bwd(BatchView b, MlpW w, const
   constexpr size_t TS = FW ? (size_t)H * LDT * 2 : 0;
   static_assert(!FW || (sizeof(T) == 2 && H == 128), "fused weight gradients: BF16, H = 128");
   static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
-  __shared__ __align__(16) unsigned char smem[XS + ZS + 3 * TS + NW * MT * 4 + 2 * MT * 4];
+  __shared__ __align__(16) unsigned char smem[XS + ZS + 3 * TS + 2 * NW * MT * 4 + 2 * MT * 4];
   T* xs = (T*)smem;
   float* ft = (float*)smem;
   T* zs = (T*)(smem + XS);
@@ -160,13 +168,13 @@ __global__ __launch_bounds__(64 * NW) void k_edge_bwd(BatchView b, MlpW w, const
   bf16* zT = (bf16*)(smem + XS + ZS + TS);
   bf16* dT = (bf16*)(smem + XS + ZS + 2 * TS);  // du^T, then da^T
   float* red = (float*)(smem + XS + ZS + 3 * TS);
-  int* rs = (int*)(red + NW * MT);
+  int* rs = (int*)(red + 2 * NW * MT);
   const T* W1 = (const T*)w.W1;
   const T* W2 = (const T*)w.W2;
   const T* W2T = (const T*)w.W2T;
   const T* W1Te = (const T*)w.W1T;
   const int n0 = wave_id() * D::CPW;
-  float cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
+  double cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
   f32x4 accW2[4][WNB], accW1[4][WNB];
   if constexpr (FW) {
     zero_acc(accW2);
@@ -356,7 +364,7 @@ __global__ __launch_bounds__(NTHR) void k_node_bwd(int n, MlpW w, const T* __res
   constexpr size_t XS = (size_t)MT * D::LD2 * sizeof(T);
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
   static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
-  __shared__ __align__(16) unsigned char smem[XS + ZS + NWAVE * MT * 4];
+  __shared__ __align__(16) unsigned char smem[XS + ZS + 2 * NWAVE * MT * 4];
   T* xs = (T*)smem;
   float* ft = (float*)smem;
   T* zs = (T*)(smem + XS);
@@ -366,7 +374,7 @@ __global__ __launch_bounds__(NTHR) void k_node_bwd(int n, MlpW w, const T* __res
   const T* W2T = (const T*)w.W2T;
   const T* W1T = (const T*)w.W1T;
   const int n0 = wave_id() * D::CPW;
-  float cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
+  double cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
   const int n_tiles = (n + MT - 1) / MT;
 
   TileSched sch(n_tiles);
@@ -559,8 +567,8 @@ __global__ __launch_bounds__(NTHR) void k_dec_bwd(BatchView b, MlpW w, const T* 
   const T* W2T = (const T*)w.W2T;
   const float* W3 = w.W1f;
   const int n0 = wave_id() * D::CPW;
-  float cb1[NB] = {}, cb2[NB] = {};
-  float cb3 = 0.f;
+  double cb1[NB] = {}, cb2[NB] = {};
+  double cb3 = 0.0;
   const int n_tiles = (b.n_inner + MT - 1) / MT;
 
   TileSched sch(n_tiles);
@@ -644,7 +652,7 @@ __global__ __launch_bounds__(NTHR) void k_dec_bwd(BatchView b, MlpW w, const T* 
   float* p = o.partial + (size_t)blockIdx.x * (2 * H + 16);
   write_partial<NB>(p, n0, cb1);
   write_partial<NB>(p + H, n0, cb2);
-  if (threadIdx.x < 16) p[2 * H + threadIdx.x] = (int)threadIdx.x < out_dim ? cb3 : 0.f;
+  if (threadIdx.x < 16) p[2 * H + threadIdx.x] = (int)threadIdx.x < out_dim ? (float)cb3 : 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -659,19 +667,19 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
   constexpr size_t FS = (size_t)MT * D::LDF * 4;
-  __shared__ __align__(16) unsigned char smem[2 * ZS + FS + MT * 8 * 4 + NWAVE * MT * 4];
+  __shared__ __align__(16) unsigned char smem[2 * ZS + FS + MT * 8 * 4 + 2 * NWAVE * MT * 4];
   T* zs = (T*)smem;
   T* z2s = (T*)(smem + ZS);
   float* ft = (float*)(smem + 2 * ZS);
   float* xin = (float*)(smem + 2 * ZS + FS);
-  float* red = xin + MT * 8;
+  float* red = xin + MT * 8;  // [2][NWAVE][MT]
   const T* W2 = (const T*)w.W2;
   const T* W3 = (const T*)w.W3;
   const T* W2T = (const T*)w.W2T;
   const T* W3T = (const T*)w.W3T;
   const int n0 = wave_id() * D::CPW;
-  float cb1[NB] = {}, cb2[NB] = {}, cb3[NB] = {}, cg[NB] = {}, cbt[NB] = {};
-  float cw1[NB][8] = {};
+  double cb1[NB] = {}, cb2[NB] = {}, cb3[NB] = {}, cg[NB] = {}, cbt[NB] = {};
+  double cw1[NB][8] = {};
   const int n_tiles = (rows + MT - 1) / MT;
 
   TileSched sch(n_tiles);
@@ -796,7 +804,7 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
           for (int r = 0; r < 4; ++r) s += x[mb][nb][r] * xin[acc_row(mb, r) * 8 + k];
-        cw1[nb][k] += sum_groups(s);
+        cw1[nb][k] += (double)sum_groups(s);
       }
     __syncthreads();
   }
@@ -810,7 +818,7 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) p[5 * H + acc_col(n0, nb) * 8 + k] = cw1[nb][k];
+      for (int k = 0; k < 8; ++k) p[5 * H + acc_col(n0, nb) * 8 + k] = (float)cw1[nb][k];
 }
 
 // ---------------------------------------------------------------------------

@@ -36,12 +36,12 @@ __global__ __launch_bounds__(64 * NW) void k_edge_fwd(BatchView b, MlpW w, const
   constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
   static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
-  __shared__ __align__(16) unsigned char smem[XS + ZS + NW * MT * 4 + 2 * MT * 4];
+  __shared__ __align__(16) unsigned char smem[XS + ZS + 2 * NW * MT * 4 + 2 * MT * 4];
   T* xs = (T*)smem;
   float* ft = (float*)smem;  // aliases xs once the gathered tile is dead
   T* zs = (T*)(smem + XS);
   float* red = (float*)(smem + XS + ZS);
-  int* rs = (int*)(red + NW * MT);
+  int* rs = (int*)(red + 2 * NW * MT);
   int* ss = rs + MT;
   const T* W1 = (const T*)w.W1;
   const T* W2 = (const T*)w.W2;
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(NTHR) void k_node_fwd(int n, MlpW w, const T* __res
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t XS = (size_t)MT * D::LD2 * sizeof(T);
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
-  __shared__ __align__(16) unsigned char smem[XS + ZS + NWAVE * MT * 4];
+  __shared__ __align__(16) unsigned char smem[XS + ZS + 2 * NWAVE * MT * 4];
   T* xs = (T*)smem;
   T* zs = (T*)(smem + XS);
   float* red = (float*)(smem + XS + ZS);
@@ -216,11 +216,11 @@ __global__ __launch_bounds__(NTHR) void k_enc_fwd(int rows, BatchView b, MlpW w,
   using D = Dims<T, H>;
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
-  __shared__ __align__(16) unsigned char smem[2 * ZS + MT * 8 * 4 + NWAVE * MT * 4];
+  __shared__ __align__(16) unsigned char smem[2 * ZS + MT * 8 * 4 + 2 * NWAVE * MT * 4];
   T* zs = (T*)smem;
   T* z2 = (T*)(smem + ZS);
   float* xin = (float*)(smem + 2 * ZS);
-  float* red = xin + MT * 8;
+  float* red = xin + MT * 8;  // [2][NWAVE][MT]
   const T* W2 = (const T*)w.W2;
   const T* W3 = (const T*)w.W3;
   const int n0 = wave_id() * D::CPW;
