@@ -43,17 +43,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(name: str, n: int, E: int, H: int, s: int) -> float | None:
-    """Algorithmic HBM bytes of one launch of a processor kernel (minimal
-    traffic for its inputs and outputs; s = bytes per stored latent)."""
+def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: bool = False, de_in: float = 1.0) -> float | None:
+    """Algorithmic HBM bytes of one launch of a processor kernel: each input
+    read once, each output written once (s = bytes per stored latent; FP32
+    adjoints are 4 bytes).  `fused`: the edge adjoint accumulates dW2 and the
+    e-block of dW1 itself, so z and du are not written.  `de_in`: fraction of
+    launches that read an incoming edge adjoint de' (all but the last layer)."""
     if name == "edge_fwd":
         # per edge: e and the gathered h_s read, e' written; per receiver:
         # h_r read, m (FP32) written
         return E * 3 * H * s + n * (H * s + 4 * H)
     if name == "edge_bwd":
-        # per edge: h_s, e, de' (FP32) read; de (FP32), z, du, da written;
-        # per receiver: h_r, dm (FP32) read, S_r (FP32) written
-        return E * (5 * H * s + 8 * H) + n * (H * s + 8 * H)
+        # per edge: h_s, e, de' (FP32) read; de (FP32), da written (+ z, du
+        # when not fused); per receiver: h_r, dm (FP32) read, S_r (FP32) written
+        per_edge = (2 + 1 + (0 if fused else 2)) * H * s + 4 * H * (1 + de_in)
+        return E * per_edge + n * (H * s + 8 * H)
     if name == "node_fwd":
         return n * (2 * H * s + 4 * H)
     if name == "node_bwd":
@@ -61,11 +65,13 @@ def kernel_bytes(name: str, n: int, E: int, H: int, s: int) -> float | None:
     return None
 
 
-def kernel_flops(name: str, n: int, E: int, H: int) -> float | None:
+def kernel_flops(name: str, n: int, E: int, H: int, fused: bool = False) -> float | None:
+    """Dense multiply-add flops of one launch (2 per MAC)."""
     if name == "edge_fwd":
         return E * 8.0 * H * H
     if name == "edge_bwd":
-        return E * 12.0 * H * H
+        # recompute (3H x H, H x H), W2^T du, W1e^T da; fused: du^T z, da^T e
+        return E * (16.0 if fused else 12.0) * H * H
     if name == "node_fwd":
         return n * 6.0 * H * H
     if name == "node_bwd":
@@ -99,7 +105,7 @@ def measured_traffic(workload: str, kernel: str):
 
 def cpu_baseline(cfg_idx: int, layers: int, hidden: int):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
-    the same geometry / multi-scale recipe at 1/200 of the points (1/800 at
+    the same geometry / multi-scale recipe at 1/40 of the points (1/160 at
     H = 256, to keep the same amount of work), full depth and width, one
     forward + backward."""
     from oracle import graph as og
@@ -111,7 +117,7 @@ def cpu_baseline(cfg_idx: int, layers: int, hidden: int):
     except Exception:  # noqa: BLE001
         cores = os.cpu_count() or 1
     cfg = CONFIGS[cfg_idx]
-    div = 200 * (hidden // 128) ** 2
+    div = 40 * (hidden // 128) ** 2
     levels = tuple(max(200, lv // div) for lv in cfg.levels)
     inp = make_inputs(cfg, levels=levels)
     G = og.build_graph(inp.pos, levels, cfg.k_intra, cfg.k_cross if len(levels) > 1 else 0)
@@ -255,12 +261,15 @@ def main():
     value = E * L / bf["wall"]
     # dominant kernel of the BF16 step and its roofline
     kern = bf["kernels"]
-    dom = max((k for k in kern if kernel_bytes(k, N, E, H, 2) is not None), key=lambda k: kern[k][0])
+    fused = H == 128  # the BF16 edge adjoint fuses its weight gradients at H = 128
+    de_in = (L - 1) / L
+    kb = lambda k, n_w, e_w: kernel_bytes(k, n_w, e_w, H, 2, fused, de_in)  # noqa: E731
+    dom = max((k for k in kern if kb(k, N, E) is not None), key=lambda k: kern[k][0])
     avg_ms = kern[dom][0] / kern[dom][1]
     # launches of a processor kernel per step: L per wave (edge/node kernels)
     per_step = kern[dom][1]
-    tot_bytes = sum(kernel_bytes(dom, n_w, e_w, H, 2) for n_w, e_w in wave_sizes) * per_step / len(waves)
-    tot_flops = sum(kernel_flops(dom, n_w, e_w, H) for n_w, e_w in wave_sizes) * per_step / len(waves)
+    tot_bytes = sum(kb(dom, n_w, e_w) for n_w, e_w in wave_sizes) * per_step / len(waves)
+    tot_flops = sum(kernel_flops(dom, n_w, e_w, H, fused) for n_w, e_w in wave_sizes) * per_step / len(waves)
     by = tot_bytes / per_step
     fl = tot_flops / per_step
     achieved = by / (avg_ms * 1e-3) / 1e9

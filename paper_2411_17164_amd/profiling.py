@@ -27,9 +27,40 @@ def _find(d: str, suffix: str) -> str:
     return hits[-1]
 
 
+def demangle(name: str) -> str:
+    """Readable name for this library's kernels, whose template arguments
+    are only bf16, float and integer literals: _ZN4xmgn<len><name>I...E."""
+    import re
+    m = re.match(r"_ZN4xmgn(\d+)", name)
+    if not m:
+        return name
+    i = m.end()
+    kname = name[i:i + int(m.group(1))]
+    i += int(m.group(1))
+    if i >= len(name) or name[i] != "I":
+        return kname
+    i += 1
+    args = []
+    while i < len(name) and name[i] != "E":
+        if name.startswith("DF16b", i):
+            args.append("bf16")
+            i += 5
+        elif name[i] == "f":
+            args.append("float")
+            i += 1
+        elif name[i] == "L":
+            j = name.index("E", i)
+            args.append(name[i + 2:j].replace("n", "-"))
+            i = j + 1
+        else:
+            return name
+    return f"{kname}<{', '.join(args)}>"
+
+
 def short(name: str) -> str:
-    """Kernel name without template arguments and parameter lists."""
-    n = name
+    """Demangled kernel name with its template arguments, without the
+    namespace and the parameter list."""
+    n = demangle(name)
     for tok in ("void ", "xmgn::"):
         n = n.replace(tok, "")
     return n.split("(")[0]
@@ -61,25 +92,43 @@ def stats(d: str):
     return rows
 
 
-def counters(d: str, counter: str):
-    """{kernel name: [value per dispatch]} for one counter."""
-    out = defaultdict(list)
+def _counter_rows(d: str):
     try:
         path = _find(d, "counter_collection.csv")
     except FileNotFoundError:
         path = _find(d, "counter_collection_trace.csv")
     with open(path) as f:
-        for r in csv.DictReader(f):
-            if r.get("Counter_Name") == counter:
-                out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        yield from csv.DictReader(f)
+
+
+def counters(d: str, counter: str):
+    """{kernel name: [value per dispatch]} for one counter."""
+    out = defaultdict(list)
+    for r in _counter_rows(d):
+        if r.get("Counter_Name") == counter:
+            out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
     return out
 
 
-def _match(table, sub):
+def resources(d: str):
+    """{kernel name: (VGPRs, AGPRs, SGPRs, LDS bytes, scratch bytes, workgroup size)}."""
+    out = {}
+    for r in _counter_rows(d):
+        out[r["Kernel_Name"]] = tuple(int(float(r.get(k) or 0)) for k in (
+            "VGPR_Count", "Accum_VGPR_Count", "SGPR_Count", "LDS_Block_Size", "Scratch_Size", "Workgroup_Size"))
+    return out
+
+
+def _match(table, sub, largest=False):
+    """Mean counter value over the dispatches of kernels whose name contains
+    `sub` (or the largest one: a runtime copy kernel also serves small
+    copies, and the calibration copy is the biggest of the run)."""
     names = [k for k in table if sub in k]
     if not names:
         raise KeyError(f"no kernel matching {sub!r}")
     vals = [v for k in names for v in table[k]]
+    if largest:
+        return max(vals), 1, names
     return sum(vals) / len(vals), len(vals), names
 
 
@@ -89,6 +138,7 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("dir")
     s.add_argument("--top", type=int, default=25)
+    s.add_argument("--resources", default=None, help="a --pmc output dir: add register/LDS columns")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -101,15 +151,19 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         rows = stats(a.dir)
-        print("| kernel | calls | total ms | avg us | % |")
-        print("|---|---|---|---|---|")
+        res = resources(a.resources) if a.resources else {}
+        extra = " VGPR | AGPR | LDS B | scratch B | WG |" if res else ""
+        print("| kernel | calls | total ms | avg us | % |" + extra)
+        print("|---|---|---|---|---|" + ("---|" * 5 if res else ""))
         for name, calls, tot, avg, pct in rows[: a.top]:
-            print(f"| {short(name)[:90]} | {calls} | {tot:.3f} | {avg:.1f} | {pct:.2f} |")
+            r = res.get(name)
+            tail = (" " + " | ".join(str(r[i]) for i in (0, 1, 3, 4, 5)) + " |") if r else (" | | | | |" if res else "")
+            print(f"| {short(name)[:100]} | {calls} | {tot:.3f} | {avg:.1f} | {pct:.2f} |{tail}")
         return 0
     fetch = counters(a.fetch, "FETCH_SIZE")
     write = counters(a.write, "WRITE_SIZE")
-    cf, _, _ = _match(fetch, a.calib)
-    cw, _, _ = _match(write, a.calib)
+    cf, _, _ = _match(fetch, a.calib, largest=True)
+    cw, _, _ = _match(write, a.calib, largest=True)
     kf, nf, names = _match(fetch, a.kernel)
     kw, nw, _ = _match(write, a.kernel)
     sf = a.calib_bytes / (cf * 1024.0)
