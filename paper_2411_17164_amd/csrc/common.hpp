@@ -81,33 +81,81 @@ __device__ __forceinline__ float act_d(float a) {
   }
 }
 
+// The B operand B[k][n] = W[n][k] of a wave's product, for its output
+// columns [n0, n0 + 16 NB) and k in [0, K), W in global memory (row stride
+// ldw).  For BF16 every fragment is loaded into registers by load(), in one
+// batch (K / KC x NB x 4 registers), so that the loads can be issued ahead of
+// the product -- weights are the same for every tile, and their round trip
+// then overlaps other work.  For FP32 (twice the registers) the fragments
+// are loaded inside the product's k loop instead.
+template <typename T, int NB, int K>
+struct WFrag {
+  using V = typename TT<T>::V;
+  static constexpr int E = TT<T>::E, KC = 4 * E;
+  static constexpr bool PRE = sizeof(T) == 2;
+  static_assert(K % KC == 0, "K must be a multiple of the MFMA k chunk");
+  V b[PRE ? K / KC : 1][NB];
+  const T* wrow[NB];
+  __device__ __forceinline__ void load(const T* __restrict__ W, int ldw, int n0) {
+    const int l = lane_id(), li = l & 15, lg = l >> 4;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) wrow[nb] = W + (size_t)(n0 + nb * 16 + li) * ldw + lg * E;
+    if constexpr (PRE) {
+#pragma unroll
+      for (int kk = 0; kk < K / KC; ++kk)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) b[kk][nb] = *(const V*)(wrow[nb] + kk * KC);
+    }
+  }
+};
+
 // acc[MB][NB] += A * B over k in [0, K):  A rows [0, 16 MB) from LDS (row
-// stride LDA elements), B[k][n] = W[n][k] with W in global memory (row stride
-// ldw elements); the wave's output columns are [n0, n0 + 16 NB).
+// stride LDA elements), B from a loaded WFrag.
+template <typename T, int MB, int NB, int K, int LDA>
+__device__ __forceinline__ void wave_gemm(f32x4 (&acc)[MB][NB], const T* A, const WFrag<T, NB, K>& f) {
+  using V = typename TT<T>::V;
+  constexpr int KC = WFrag<T, NB, K>::KC, E = WFrag<T, NB, K>::E;
+  const int l = lane_id(), li = l & 15, lg = l >> 4;
+  const T* arow = A + li * LDA + lg * E;
+  if constexpr (WFrag<T, NB, K>::PRE) {
+    // A fragments (LDS) are read at most two k steps ahead of their MFMAs:
+    // hoisting all of them would cost K / KC x MB x 4 registers
+#pragma unroll
+    for (int kk = 0; kk < K / KC; kk += 2) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k2 = kk; k2 < kk + 2 && k2 < K / KC; ++k2)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          V a = *(const V*)(arow + mb * 16 * LDA + k2 * KC);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mma(a, f.b[k2][nb], acc[mb][nb]);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  } else {
+#pragma unroll 4
+    for (int k = 0; k < K; k += KC) {
+      V b[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) b[nb] = *(const V*)(f.wrow[nb] + k);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        V a = *(const V*)(arow + mb * 16 * LDA + k);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mma(a, b[nb], acc[mb][nb]);
+      }
+    }
+  }
+}
+
+// acc[MB][NB] += A * W^T with the weight fragments loaded on the spot.
 template <typename T, int MB, int NB, int K, int LDA>
 __device__ __forceinline__ void wave_gemm(f32x4 (&acc)[MB][NB], const T* A,
                                           const T* __restrict__ W, int ldw, int n0) {
-  using V = typename TT<T>::V;
-  constexpr int E = TT<T>::E;
-  constexpr int KC = 4 * E;
-  static_assert(K % KC == 0, "K must be a multiple of the MFMA k chunk");
-  const int l = lane_id(), li = l & 15, lg = l >> 4;
-  const T* wrow[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) wrow[nb] = W + (size_t)(n0 + nb * 16 + li) * ldw + lg * E;
-  const T* arow = A + li * LDA + lg * E;
-#pragma unroll 4
-  for (int k = 0; k < K; k += KC) {
-    V b[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) b[nb] = *(const V*)(wrow[nb] + k);
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      V a = *(const V*)(arow + mb * 16 * LDA + k);
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mma(a, b[nb], acc[mb][nb]);
-    }
-  }
+  WFrag<T, NB, K> f;
+  f.load(W, ldw, n0);
+  wave_gemm<T, MB, NB, K, LDA>(acc, A, f);
 }
 
 template <int MB, int NB>
@@ -322,6 +370,65 @@ __device__ __forceinline__ void global_rows_to_lds(T* dst, int rows, int width, 
   }
 }
 
+// Gather a tile of MT rows x NP parts of H elements (part p of row i from
+// src(p, i)) into LDS at columns p H, zero-filling rows >= rows.  The trip
+// count is a compile-time constant, so every load of the tile is issued
+// before the first one is waited on (one memory round trip per tile).
+// hook(p, i, q, v) sees each 16-byte chunk q of part p of row i after it is
+// stored.
+template <typename T, int LD, int MT, int NP, int H, int NTHR, typename SrcFn, typename Hook>
+__device__ __forceinline__ void gather_tile(T* dst, int rows, SrcFn src, Hook hook) {
+  constexpr int E = 16 / sizeof(T), CPR = H / E, TOT = MT * NP * CPR;
+  static_assert(TOT % NTHR == 0, "whole steps of the workgroup");
+  constexpr int IT = TOT / NTHR;
+  uint4 v[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int c = (int)threadIdx.x + k * NTHR;
+    const int p = c / (MT * CPR), rem = c - p * (MT * CPR), i = rem / CPR, q = rem - i * CPR;
+    v[k] = uint4{0u, 0u, 0u, 0u};
+    if (i < rows) v[k] = *(const uint4*)(src(p, i) + q * E);
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int c = (int)threadIdx.x + k * NTHR;
+    const int p = c / (MT * CPR), rem = c - p * (MT * CPR), i = rem / CPR, q = rem - i * CPR;
+    *(uint4*)(dst + i * LD + p * H + q * E) = v[k];
+    hook(p, i, q, v[k]);
+  }
+}
+
+// FP32 tile of MT rows x H: row i, float4 q = a(i, q) (+ b(i, q) when
+// with_b), zero for rows >= rows, one batch of loads; the result goes to
+// LDS (row stride LD) through put(i, q, value).
+template <int MT, int H, int NTHR, typename AFn, typename BFn, typename PutFn>
+__device__ __forceinline__ void f32_tile(int rows, bool with_b, AFn a, BFn b, PutFn put) {
+  constexpr int CPR = H / 4, TOT = MT * CPR;
+  static_assert(TOT % NTHR == 0, "whole steps of the workgroup");
+  constexpr int IT = TOT / NTHR;
+  float4 va[IT], vb[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int c = (int)threadIdx.x + k * NTHR, i = c / CPR, q = c - i * CPR;
+    va[k] = float4{0.f, 0.f, 0.f, 0.f};
+    vb[k] = float4{0.f, 0.f, 0.f, 0.f};
+    if (i < rows) {
+      va[k] = a(i, q);
+      if (with_b) vb[k] = b(i, q);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int c = (int)threadIdx.x + k * NTHR, i = c / CPR, q = c - i * CPR;
+    float4 v = va[k];
+    v.x += vb[k].x;
+    v.y += vb[k].y;
+    v.z += vb[k].z;
+    v.w += vb[k].w;
+    put(i, q, v);
+  }
+}
+
 // FP32 global rows converted into a T tile in LDS (8 floats per step).
 template <typename T, int LD, int MT, typename SrcFn>
 __device__ __forceinline__ void global_f32_rows_to_lds(T* dst, int rows, int width, int col0, SrcFn src_row) {
@@ -336,6 +443,15 @@ __device__ __forceinline__ void global_f32_rows_to_lds(T* dst, int rows, int wid
     d[2] = from_f<T>(v.z);
     d[3] = from_f<T>(v.w);
   }
+}
+
+// Waves per SIMD that the LDS footprint of a workgroup of NW waves allows
+// (160 KiB of LDS per CU, 4 SIMDs), as a register budget for the compiler:
+// it may then use 512 / waves registers per lane and no more.
+__host__ __device__ constexpr int waves_per_simd(size_t lds_bytes, int nw) {
+  const int wg = (int)((160u * 1024u) / (lds_bytes ? lds_bytes : 1));
+  const int w = wg * nw / 4;
+  return w < 1 ? 1 : (w > 2 ? 2 : w);
 }
 
 // Persistent-grid tile schedule.  The workgroups of the grid are dealt

@@ -111,25 +111,36 @@ __device__ __forceinline__ void acc_to_lds_t(const f32x4 (&x)[MB][NB], bf16* dst
     }
 }
 
-// acc (this wave's 64 x (128 / (NW/2)) block of a 128 x 128 product) +=
-// A^T-tile * B-tile over the MT rows of a tile, with AT[m][k], BT[n][k]
-// transposed tiles in LDS.  Waves: wm = w % 2 picks the rows, wn = w / 2
-// the columns.
-template <int MT, int LDT, int NW>
-__device__ __forceinline__ void wave_wgrad(f32x4 (&acc)[4][8 / NW * 2], const bf16* AT, const bf16* BT) {
-  constexpr int WNB = 8 / NW * 2;  // 16-column blocks per wave (4 at NW = 4, 2 at NW = 8)
-  const int w = wave_id(), wm = w & 1, wn = w >> 1;
+// acc[nb][jb] += sum over the MT rows of a tile of
+//   G[row][n0 + 16 nb + i] * B[row][16 jb + j],
+// the rows n0 + 16 nb (this wave's columns of G) of a H x H weight gradient
+// G^T B.  The A operand is the wave's own FP32 accumulator tile G, rounded
+// to BF16: in the MFMA accumulator layout, lane group q holds rows
+// 4q + r and 16 + 4q + r (r < 4) of each 32-row k chunk, and since the order
+// of k inside one MFMA is free, B is read from its transposed LDS tile
+// BT[col][row] in that same row order.
+template <int MB, int NB, int H, int LDT>
+__device__ __forceinline__ void wave_wgrad(f32x4 (&acc)[NB][H / 16], const f32x4 (&g)[MB][NB], const bf16* BT) {
+  static_assert(MB % 2 == 0, "k chunks of 32 rows");
   const int l = lane_id(), li = l & 15, lg = l >> 4;
 #pragma unroll
-  for (int ks = 0; ks < MT; ks += 32) {
-    bf16x8 b[WNB];
+  for (int c = 0; c < MB / 2; ++c) {
+    bf16x8 a[NB];
 #pragma unroll
-    for (int nb = 0; nb < WNB; ++nb) b[nb] = *(const bf16x8*)(BT + (wn * WNB * 16 + nb * 16 + li) * LDT + ks + lg * 8);
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-      const bf16x8 a = *(const bf16x8*)(AT + (wm * 64 + mb * 16 + li) * LDT + ks + lg * 8);
+      for (int r = 0; r < 4; ++r) {
+        a[nb][r] = (bf16)g[2 * c][nb][r];
+        a[nb][4 + r] = (bf16)g[2 * c + 1][nb][r];
+      }
 #pragma unroll
-      for (int nb = 0; nb < WNB; ++nb) acc[mb][nb] = mma(a, b[nb], acc[mb][nb]);
+    for (int jb = 0; jb < H / 16; ++jb) {
+      const bf16* p = BT + (jb * 16 + li) * LDT + 32 * c + 4 * lg;
+      const uint2 lo = *(const uint2*)p, hi = *(const uint2*)(p + 16);
+      const uint4 v = {lo.x, lo.y, hi.x, hi.y};
+      const bf16x8 b = *(const bf16x8*)&v;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb][jb] = mma(a[nb], b, acc[nb][jb]);
     }
   }
 }
@@ -145,29 +156,37 @@ __device__ __forceinline__ void write_partial(float* p, int n0, const double (&v
 // Edge adjoint (with recompute).
 // ---------------------------------------------------------------------------
 // FW: also accumulate dW2 = sum du z^T and the e-block of dW1 = sum da e^T
-// per workgroup on MFMA (BF16, H = 128), from transposed tiles in LDS, so
-// that z and du never travel to HBM; partials go to o.wpart.
-template <typename T, int H, int MT, int ACT, int AGG, int FW, int NW>
-__global__ __launch_bounds__(64 * NW) void k_edge_bwd(BatchView b, MlpW w, const T* __restrict__ h,
-                                                      const T* __restrict__ e, const float* __restrict__ de_in,
-                                                      const float* __restrict__ dm, EdgeBwdOut o, float eps) {
+// per workgroup on MFMA (BF16, H = 128): du and da straight from the
+// accumulators, z and e from transposed tiles in LDS, so that z and du never
+// travel to HBM; partials go to o.wpart.
+template <typename T, int H, int MT, int FW, int NW>
+struct EdgeBwdLds {
   using D = BD<T, H, NW>;
-  constexpr int WNB = 8 / NW * 2;
+  static constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
+  static constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  static constexpr int LDT = MT + 8;  // transposed tiles (BF16)
+  static constexpr size_t TS = FW ? (size_t)H * LDT * 2 : 0;
+  static constexpr size_t bytes = XS + ZS + 2 * TS + 2 * NW * MT * 4 + 2 * MT * 4;
+};
+
+template <typename T, int H, int MT, int ACT, int AGG, int FW, int NW>
+__global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW>::bytes, NW)) void k_edge_bwd(
+    BatchView b, MlpW w, const T* __restrict__ h, const T* __restrict__ e, const float* __restrict__ de_in,
+    const float* __restrict__ dm, EdgeBwdOut o, float eps) {
+  using D = BD<T, H, NW>;
+  using L = EdgeBwdLds<T, H, MT, FW, NW>;
   constexpr int MB = MT / 16, NB = D::NB;
-  constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
-  constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
-  constexpr int LDT = MT + 8;                              // transposed tiles (BF16)
-  constexpr size_t TS = FW ? (size_t)H * LDT * 2 : 0;
+  constexpr size_t XS = L::XS, ZS = L::ZS, TS = L::TS;
+  constexpr int LDT = L::LDT;
   static_assert(!FW || (sizeof(T) == 2 && H == 128), "fused weight gradients: BF16, H = 128");
   static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
-  __shared__ __align__(16) unsigned char smem[XS + ZS + 3 * TS + 2 * NW * MT * 4 + 2 * MT * 4];
+  __shared__ __align__(16) unsigned char smem[L::bytes];
   T* xs = (T*)smem;
   float* ft = (float*)smem;
   T* zs = (T*)(smem + XS);
   bf16* eT = (bf16*)(smem + XS + ZS);
   bf16* zT = (bf16*)(smem + XS + ZS + TS);
-  bf16* dT = (bf16*)(smem + XS + ZS + 2 * TS);  // du^T, then da^T
-  float* red = (float*)(smem + XS + ZS + 3 * TS);
+  float* red = (float*)(smem + XS + ZS + 2 * TS);
   int* rs = (int*)(red + 2 * NW * MT);
   const T* W1 = (const T*)w.W1;
   const T* W2 = (const T*)w.W2;
@@ -175,7 +194,7 @@ __global__ __launch_bounds__(64 * NW) void k_edge_bwd(BatchView b, MlpW w, const
   const T* W1Te = (const T*)w.W1T;
   const int n0 = wave_id() * D::CPW;
   double cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
-  f32x4 accW2[4][WNB], accW1[4][WNB];
+  f32x4 accW2[NB][H / 16], accW1[NB][H / 16];
   if constexpr (FW) {
     zero_acc(accW2);
     zero_acc(accW1);
@@ -192,20 +211,18 @@ __global__ __launch_bounds__(64 * NW) void k_edge_bwd(BatchView b, MlpW w, const
       ss[threadIdx.x] = ok ? b.col[e0 + threadIdx.x] : 0;
     }
     __syncthreads();
-    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, 0, [&](int i) { return h + (size_t)rs[i] * H; });
-    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, H, [&](int i) { return h + (size_t)ss[i] * H; });
-    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, 2 * H, [&](int i) { return e + (size_t)(e0 + i) * H; });
-    if constexpr (FW) {
-      // e^T for the dW1 e-block: 8 columns of one row per step
-      for (int c = threadIdx.x; c < MT * (H / 8); c += 64 * NW) {
-        const int i = c / (H / 8), q = c - i * (H / 8);
-        uint4 v = {0u, 0u, 0u, 0u};
-        if (i < ne) v = *(const uint4*)(e + (size_t)(e0 + i) * H + q * 8);
-        const bf16* pv = (const bf16*)&v;
+    gather_tile<T, D::LD3, MT, 3, H, 64 * NW>(
+        xs, ne,
+        [&](int p, int i) { return p == 0 ? h + (size_t)rs[i] * H : p == 1 ? h + (size_t)ss[i] * H : e + (size_t)(e0 + i) * H; },
+        [&](int p, int i, int q, const uint4& v) {
+          if constexpr (FW) {
+            if (p == 2) {  // e^T for the dW1 e-block
+              const bf16* pv = (const bf16*)&v;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) eT[(q * 8 + t) * LDT + i] = pv[t];
-      }
-    }
+              for (int t = 0; t < 8; ++t) eT[(q * 8 + t) * LDT + i] = pv[t];
+            }
+          }
+        });
     __syncthreads();
 
     // recompute: a, z, u, xhat
@@ -241,17 +258,10 @@ __global__ __launch_bounds__(64 * NW) void k_edge_bwd(BatchView b, MlpW w, const
     ln_normalize<MB, NB, MT, H, NW>(x, red, eps, inv);  // x = xhat
 
     // upstream gradient dv = dm_r + de'_k  (FP32 tile over the dead gather)
-    f32_rows_to_lds<H, D::LDF, MT>(ft, ne, [&](int i, int q) {
-      float4 v = *(const float4*)(dm + (size_t)rs[i] * H + 4 * q);
-      if (de_in) {
-        const float4 d = *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q);
-        v.x += d.x;
-        v.y += d.y;
-        v.z += d.z;
-        v.w += d.w;
-      }
-      return v;
-    });
+    f32_tile<MT, H, 64 * NW>(
+        ne, de_in != nullptr, [&](int i, int q) { return *(const float4*)(dm + (size_t)rs[i] * H + 4 * q); },
+        [&](int i, int q) { return *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q); },
+        [&](int i, int q, const float4& v) { *(float4*)(ft + i * D::LDF + 4 * q) = v; });
     if constexpr (!FW) lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.z + (size_t)e0 * H, H, [](int i) { return i; });
     __syncthreads();
     f32x4 g[MB][NB];
@@ -263,14 +273,10 @@ __global__ __launch_bounds__(64 * NW) void k_edge_bwd(BatchView b, MlpW w, const
         for (int r = 0; r < 4; ++r) g[mb][nb][r] = ft[acc_row(mb, r) * D::LDF + acc_col(n0, nb)];
     ln_backward<MB, NB, MT, H, NW>(x, g, inv, w.gamma, n0, red, cg, cbt);  // g = du (barriers inside)
     col_accumulate(g, cb2);
+    if constexpr (FW) wave_wgrad<MB, NB, H, LDT>(accW2, g, zT);  // dW2 += du^T z
     acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
-    if constexpr (FW) acc_to_lds_t<MB, NB, LDT>(g, dT, n0);
     __syncthreads();
-    if constexpr (FW) {
-      wave_wgrad<MT, LDT, NW>(accW2, dT, zT);  // dW2 += du^T z
-    } else {
-      lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.du + (size_t)e0 * H, H, [](int i) { return i; });
-    }
+    if constexpr (!FW) lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.du + (size_t)e0 * H, H, [](int i) { return i; });
     // dz = W2^T du ; da = dz * act'(a)
     zero_acc(x);
     wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2T, H, n0);
@@ -281,10 +287,10 @@ __global__ __launch_bounds__(64 * NW) void k_edge_bwd(BatchView b, MlpW w, const
 #pragma unroll
         for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a[mb][nb][r]);
     col_accumulate(x, cb1);
+    if constexpr (FW) wave_wgrad<MB, NB, H, LDT>(accW1, x, eT);  // dW1[:, 2H:3H] += da^T e
     __syncthreads();
     acc_to_ldsf<MB, NB, D::LDF>(x, ft, n0);
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
-    if constexpr (FW) acc_to_lds_t<MB, NB, LDT>(x, dT, n0);
     __syncthreads();
     // S_r: receiver-segment sums of da (FP32, ascending sender order)
     const int nr = r1 - r0;
@@ -305,29 +311,18 @@ __global__ __launch_bounds__(64 * NW) void k_edge_bwd(BatchView b, MlpW w, const
     // de = de' (+ dm_r) + (W1^T da)[2H:3H]
     zero_acc(g);
     wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1Te, H, n0);
-    if constexpr (FW) wave_wgrad<MT, LDT, NW>(accW1, dT, eT);  // dW1[:, 2H:3H] += da^T e
     __syncthreads();
     acc_to_ldsf<MB, NB, D::LDF>(g, ft, n0);
     __syncthreads();
-    for (int c = threadIdx.x; c < ne * (H / 4); c += 64 * NW) {
-      const int i = c / (H / 4), q = c - i * (H / 4);
-      float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
-      if (de_in) {
-        const float4 d = *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q);
-        v.x += d.x;
-        v.y += d.y;
-        v.z += d.z;
-        v.w += d.w;
-      }
-      if (AGG) {
-        const float4 d = *(const float4*)(dm + (size_t)rs[i] * H + 4 * q);
-        v.x += d.x;
-        v.y += d.y;
-        v.z += d.z;
-        v.w += d.w;
-      }
-      *(float4*)(o.de_out + (size_t)(e0 + i) * H + 4 * q) = v;
-    }
+    f32_tile<MT, H, 64 * NW>(
+        ne, AGG != 0, [&](int i, int q) { return de_in ? *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q) : float4{0.f, 0.f, 0.f, 0.f}; },
+        [&](int i, int q) { return *(const float4*)(dm + (size_t)rs[i] * H + 4 * q); },
+        [&](int i, int q, const float4& v) {
+          if (i < ne) {
+            const float4 d = *(const float4*)(ft + i * D::LDF + 4 * q);
+            *(float4*)(o.de_out + (size_t)(e0 + i) * H + 4 * q) = float4{d.x + v.x, d.y + v.y, d.z + v.z, d.w + v.w};
+          }
+        });
     __syncthreads();
   }
   float* p = o.partial + (size_t)blockIdx.x * 4 * H;
@@ -336,19 +331,18 @@ __global__ __launch_bounds__(64 * NW) void k_edge_bwd(BatchView b, MlpW w, const
   write_partial<NB>(p + 2 * H, n0, cg);
   write_partial<NB>(p + 3 * H, n0, cbt);
   if constexpr (FW) {
-    const int wv = wave_id(), wm = wv & 1, wn = wv >> 1;
     const int li = lane_id() & 15, lg = lane_id() >> 4;
     float* q2 = o.wpart + (size_t)blockIdx.x * 2 * H * H;
     float* q1 = q2 + H * H;
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int nb = 0; nb < WNB; ++nb)
+      for (int jb = 0; jb < H / 16; ++jb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int m = wm * 64 + mb * 16 + lg * 4 + r, n = wn * WNB * 16 + nb * 16 + li;
-          q2[m * H + n] = accW2[mb][nb][r];
-          q1[m * H + n] = accW1[mb][nb][r];
+          const int m = n0 + nb * 16 + lg * 4 + r, n = jb * 16 + li;
+          q2[m * H + n] = accW2[nb][jb][r];
+          q1[m * H + n] = accW1[nb][jb][r];
         }
   }
 }

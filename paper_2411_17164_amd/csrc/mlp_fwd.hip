@@ -27,16 +27,24 @@ struct Dims {
 // ascending sender order (the CSR order) -- deterministic, no atomics.
 // ---------------------------------------------------------------------------
 // NW waves per workgroup; each wave owns H / NW output columns of every GEMM.
-template <typename T, int H, int MT, int ACT, int AGG, int NW>
-__global__ __launch_bounds__(64 * NW) void k_edge_fwd(BatchView b, MlpW w, const T* __restrict__ h,
-                                                      const T* __restrict__ e, T* __restrict__ e_out,
-                                                      float* __restrict__ m, float eps) {
+template <typename T, int H, int MT, int NW>
+struct EdgeFwdLds {
   using D = Dims<T, H, NW>;
+  static constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
+  static constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  static constexpr size_t bytes = XS + ZS + 2 * NW * MT * 4 + 2 * MT * 4;
+};
+
+template <typename T, int H, int MT, int ACT, int AGG, int NW>
+__global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::bytes, NW)) void k_edge_fwd(
+    BatchView b, MlpW w, const T* __restrict__ h, const T* __restrict__ e, T* __restrict__ e_out,
+    float* __restrict__ m, float eps) {
+  using D = Dims<T, H, NW>;
+  using L = EdgeFwdLds<T, H, MT, NW>;
   constexpr int MB = MT / 16, NB = D::NB;
-  constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
-  constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  constexpr size_t XS = L::XS, ZS = L::ZS;
   static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
-  __shared__ __align__(16) unsigned char smem[XS + ZS + 2 * NW * MT * 4 + 2 * MT * 4];
+  __shared__ __align__(16) unsigned char smem[L::bytes];
   T* xs = (T*)smem;
   float* ft = (float*)smem;  // aliases xs once the gathered tile is dead
   T* zs = (T*)(smem + XS);
@@ -57,9 +65,10 @@ __global__ __launch_bounds__(64 * NW) void k_edge_fwd(BatchView b, MlpW w, const
       ss[threadIdx.x] = ok ? b.col[e0 + threadIdx.x] : 0;
     }
     __syncthreads();
-    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, 0, [&](int i) { return h + (size_t)rs[i] * H; });
-    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, H, [&](int i) { return h + (size_t)ss[i] * H; });
-    global_rows_to_lds<T, D::LD3, MT>(xs, ne, H, 2 * H, [&](int i) { return e + (size_t)(e0 + i) * H; });
+    gather_tile<T, D::LD3, MT, 3, H, 64 * NW>(
+        xs, ne,
+        [&](int p, int i) { return p == 0 ? h + (size_t)rs[i] * H : p == 1 ? h + (size_t)ss[i] * H : e + (size_t)(e0 + i) * H; },
+        [](int, int, int, const uint4&) {});
     __syncthreads();
 
     f32x4 acc[MB][NB];
