@@ -2,6 +2,8 @@
 // (split over row chunks, reduced in a fixed order), fixed-order reductions
 // of per-workgroup partial vectors, weight preparation (cast / transpose into
 // the compute type), the masked MSE and gradient accumulation.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -11,61 +13,67 @@ int g_config_error = 0;
 
 // ---------------------------------------------------------------------------
 // wgrad: C[m][n] = sum_r A[r][a0 + m] * B[r][b0 + n].  A workgroup owns one
-// chunk of rows and one 128x128 output block; rows are staged 64 at a time,
-// transposed into LDS so that the row index is the MFMA k dimension.
+// chunk of rows and one 128x128 output block.  Rows go through LDS 128 at a
+// time, transposed so that the row index is the MFMA k dimension; the loads
+// of the next stage are issued before the products of the current one, so
+// their round trip overlaps the MFMAs.
 // ---------------------------------------------------------------------------
 constexpr int WG_B = 128;  // output block edge
-constexpr int WG_RC = 64;  // rows per LDS stage
+constexpr int WG_K = 128;  // rows per stage
 
 template <typename T>
 struct WgLds {
   static constexpr int PAD = 16 / sizeof(T);
-  static constexpr int LD = WG_RC + PAD;
+  static constexpr int LD = WG_K + PAD;
 };
 
-template <typename T, typename S>
-__device__ __forceinline__ void load4(const S* p, float (&v)[4]) {
-  if constexpr (sizeof(S) == 4) {
-    const float4 x = *(const float4*)p;
-    v[0] = x.x;
-    v[1] = x.y;
-    v[2] = x.z;
-    v[3] = x.w;
-  } else {
-    const uint2 x = *(const uint2*)p;
-    const S* s = (const S*)&x;
-    v[0] = to_f(s[0]);
-    v[1] = to_f(s[1]);
-    v[2] = to_f(s[2]);
-    v[3] = to_f(s[3]);
-  }
-}
-
-template <typename T, typename S>
-__device__ __forceinline__ void stage_t(T* dst, const S* base, int ld, int col0, const int* idx, int r0, int r_end,
-                                        int c0, int C) {
-  constexpr int LD = WgLds<T>::LD;
-  // unit: (row pair, 4-column chunk), columns fastest for coalesced loads
-  for (int u = threadIdx.x; u < (WG_RC / 2) * (WG_B / 4); u += NTHR) {
-    const int mc = u % (WG_B / 4), rp = u / (WG_B / 4);
-    const int c = c0 + 4 * mc;
-    float v0[4] = {0.f, 0.f, 0.f, 0.f}, v1[4] = {0.f, 0.f, 0.f, 0.f};
-    const int ra = r0 + 2 * rp, rb = ra + 1;
-    if (c < C) {
-      if (ra < r_end) load4<T, S>(base + (size_t)(idx ? idx[ra] : ra) * ld + col0 + c, v0);
-      if (rb < r_end) load4<T, S>(base + (size_t)(idx ? idx[rb] : rb) * ld + col0 + c, v1);
-    }
+// One thread's share of a stage: 4 columns (4 (t % 32)) of 16 rows
+// (16 (t / 32)) of one operand, loaded as 8 (BF16) or 16 (FP32) bytes per row.
+template <typename S>
+struct Slab {
+  using L = typename std::conditional<sizeof(S) == 4, float4, uint2>::type;
+  L v[16];
+  __device__ __forceinline__ void load(const S* base, int ld, int col0, const int* idx, int r0, int r_end, int c0,
+                                       int C) {
+    const int c = c0 + 4 * ((int)threadIdx.x & 31), rr = r0 + 16 * ((int)threadIdx.x >> 5);
+    const S* p = base + col0 + c;
+    // uniform branch: a gathered operand loads its 16 row indices first, so
+    // that neither path waits between its data loads
+    if (idx) {
+      int ri[16];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      T* d = dst + (4 * mc + t) * LD + 2 * rp;
-      d[0] = from_f<T>(v0[t]);
-      d[1] = from_f<T>(v1[t]);
+      for (int j = 0; j < 16; ++j) ri[j] = (c < C && rr + j < r_end) ? idx[rr + j] : -1;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = ri[j] >= 0 ? *(const L*)(p + (size_t)ri[j] * ld) : L{};
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = (c < C && rr + j < r_end) ? *(const L*)(p + (size_t)(rr + j) * ld) : L{};
     }
   }
-}
+  // column q of the 4, as 16 consecutive k values
+  template <typename T>
+  __device__ __forceinline__ void store(T* dst) const {
+    constexpr int LD = WgLds<T>::LD;
+    T* d0 = dst + (4 * ((int)threadIdx.x & 31)) * LD + 16 * ((int)threadIdx.x >> 5);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T col[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if constexpr (sizeof(S) == 4) {
+          col[j] = from_f<T>(((const float*)&v[j])[q]);
+        } else {
+          col[j] = from_f<T>(to_f(((const S*)&v[j])[q]));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; j += 16 / (int)sizeof(T)) *(uint4*)(d0 + q * LD + j) = *(const uint4*)&col[j];
+    }
+  }
+};
 
 template <typename T, typename SA, typename SB>
-__global__ __launch_bounds__(NTHR) void k_wgrad(WgradOp op, int rows_per_chunk, int nbm, float* __restrict__ partial) {
+__global__ __launch_bounds__(NTHR, 2) void k_wgrad(WgradOp op, int rows_per_chunk, int nbm, float* __restrict__ partial) {
   using V = typename TT<T>::V;
   constexpr int E = TT<T>::E, KC = 4 * E, LD = WgLds<T>::LD;
   __shared__ __align__(16) T At[WG_B * LD];
@@ -79,12 +87,21 @@ __global__ __launch_bounds__(NTHR) void k_wgrad(WgradOp op, int rows_per_chunk, 
   const int l = lane_id(), li = l & 15, lg = l >> 4;
   f32x4 acc[4][4];
   zero_acc(acc);
-  for (int r0 = r_begin; r0 < r_end; r0 += WG_RC) {
-    stage_t<T, SA>(At, (const SA*)op.A, op.lda, op.a0, op.ia, r0, r_end, m0, op.M);
-    stage_t<T, SB>(Bt, (const SB*)op.B, op.ldb, op.b0, op.ib, r0, r_end, nn0, op.N);
+  Slab<SA> sa;
+  Slab<SB> sb;
+  sa.load((const SA*)op.A, op.lda, op.a0, op.ia, r_begin, r_end, m0, op.M);
+  sb.load((const SB*)op.B, op.ldb, op.b0, op.ib, r_begin, r_end, nn0, op.N);
+  for (int r0 = r_begin; r0 < r_end; r0 += WG_K) {
+    __syncthreads();  // the previous stage's products are done with At, Bt
+    sa.template store<T>(At);
+    sb.template store<T>(Bt);
     __syncthreads();
+    if (r0 + WG_K < r_end) {  // next stage in flight during this stage's MFMAs
+      sa.load((const SA*)op.A, op.lda, op.a0, op.ia, r0 + WG_K, r_end, m0, op.M);
+      sb.load((const SB*)op.B, op.ldb, op.b0, op.ib, r0 + WG_K, r_end, nn0, op.N);
+    }
 #pragma unroll
-    for (int k = 0; k < WG_RC; k += KC) {
+    for (int k = 0; k < WG_K; k += KC) {
       V bfr[4];
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) bfr[nb] = *(const V*)(Bt + (wn * 64 + nb * 16 + li) * LD + k + lg * E);
@@ -95,7 +112,6 @@ __global__ __launch_bounds__(NTHR) void k_wgrad(WgradOp op, int rows_per_chunk, 
         for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mma(a, bfr[nb], acc[mb][nb]);
       }
     }
-    __syncthreads();
   }
   float* out = partial + (size_t)chunk * op.M * op.N;
 #pragma unroll
@@ -160,28 +176,31 @@ void launch_wgrad_reduce(const float* partial, int n_chunks, int M_valid, int N,
   colsum_to(partial, n_chunks, MN, M_valid, N, dst, ldd, tmp, st);
 }
 
-static int wgrad_chunks(int R, int* rows_per_chunk) {
-  if (R <= 0) {
-    *rows_per_chunk = WG_RC;
-    return 0;
-  }
-  int target = (R + 1023) / 1024;
-  if (target > 512) target = 512;
-  int rpc = (R + target - 1) / target;
-  rpc = (rpc + WG_RC - 1) / WG_RC * WG_RC;
+// Row chunks of a weight gradient: about 512 workgroups in all (two per CU),
+// whole 128-row stages per chunk.
+static int wgrad_chunks(const WgradOp& op, int* rows_per_chunk) {
+  *rows_per_chunk = WG_K;
+  if (op.R <= 0) return 0;
+  const int blocks = ((op.M + WG_B - 1) / WG_B) * ((op.N + WG_B - 1) / WG_B);
+  int target = 512 / blocks;
+  const int max_chunks = (op.R + WG_K - 1) / WG_K;
+  if (target > max_chunks) target = max_chunks;
+  if (target < 1) target = 1;
+  int rpc = (op.R + target - 1) / target;
+  rpc = (rpc + WG_K - 1) / WG_K * WG_K;
   *rows_per_chunk = rpc;
-  return (R + rpc - 1) / rpc;
+  return (op.R + rpc - 1) / rpc;
 }
 
 size_t wgrad_partial_floats(const Shape&, const WgradOp& op) {
   int rpc;
-  const int nc = wgrad_chunks(op.R, &rpc);
+  const int nc = wgrad_chunks(op, &rpc);
   return (size_t)(nc > 0 ? nc : 1) * op.M * op.N;
 }
 
 void launch_wgrad(const Shape& s, const WgradOp& op, float* partial, float* tmp, hipStream_t st) {
   int rpc;
-  const int nc = wgrad_chunks(op.R, &rpc);
+  const int nc = wgrad_chunks(op, &rpc);
   const int nbm = (op.M + WG_B - 1) / WG_B, nbn = (op.N + WG_B - 1) / WG_B;
   if (nc > 0) {
     dim3 grid(nc, nbm * nbn);

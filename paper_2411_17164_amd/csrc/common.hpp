@@ -356,17 +356,23 @@ __device__ __forceinline__ void lds_rows_to_global(const T* src, int rows, int w
   }
 }
 
-// Copy rows from global into an LDS tile (16-byte steps), zero-filling rows
-// >= rows up to MT.
-template <typename T, int LD, int MT, typename SrcFn>
-__device__ __forceinline__ void global_rows_to_lds(T* dst, int rows, int width, int col0, SrcFn src_row) {
-  constexpr int E = 16 / sizeof(T);
-  const int cpr = width / E;
-  for (int c = threadIdx.x; c < MT * cpr; c += blockDim.x) {
-    const int i = c / cpr, q = c - i * cpr;
-    uint4 v = {0u, 0u, 0u, 0u};
-    if (i < rows) v = *(const uint4*)(src_row(i) + q * E);
-    *(uint4*)(dst + i * LD + col0 + q * E) = v;
+// Copy rows of W elements from global into an LDS tile (16-byte steps),
+// zero-filling rows >= rows up to MT; a workgroup of NTHR threads, all loads
+// issued before the first LDS store.
+template <typename T, int LD, int MT, int W, typename SrcFn>
+__device__ __forceinline__ void global_rows_to_lds(T* dst, int rows, int col0, SrcFn src_row) {
+  constexpr int E = 16 / sizeof(T), CPR = W / E, TOT = MT * CPR, IT = (TOT + NTHR - 1) / NTHR;
+  uint4 v[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int c = (int)threadIdx.x + k * NTHR, i = c / CPR, q = c - i * CPR;
+    v[k] = uint4{0u, 0u, 0u, 0u};
+    if (c < TOT && i < rows) v[k] = *(const uint4*)(src_row(i) + q * E);
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int c = (int)threadIdx.x + k * NTHR, i = c / CPR, q = c - i * CPR;
+    if (c < TOT) *(uint4*)(dst + i * LD + col0 + q * E) = v[k];
   }
 }
 
@@ -429,19 +435,28 @@ __device__ __forceinline__ void f32_tile(int rows, bool with_b, AFn a, BFn b, Pu
   }
 }
 
-// FP32 global rows converted into a T tile in LDS (8 floats per step).
-template <typename T, int LD, int MT, typename SrcFn>
-__device__ __forceinline__ void global_f32_rows_to_lds(T* dst, int rows, int width, int col0, SrcFn src_row) {
-  const int cpr = width / 4;
-  for (int c = threadIdx.x; c < MT * cpr; c += blockDim.x) {
-    const int i = c / cpr, q = c - i * cpr;
-    float4 v = {0.f, 0.f, 0.f, 0.f};
-    if (i < rows) v = *(const float4*)(src_row(i) + q * 4);
-    T* d = dst + i * LD + col0 + q * 4;
-    d[0] = from_f<T>(v.x);
-    d[1] = from_f<T>(v.y);
-    d[2] = from_f<T>(v.z);
-    d[3] = from_f<T>(v.w);
+// FP32 global rows of W floats converted into a T tile in LDS, zero-filling
+// rows >= rows up to MT; NTHR threads, all loads issued before the stores.
+template <typename T, int LD, int MT, int W, typename SrcFn>
+__device__ __forceinline__ void global_f32_rows_to_lds(T* dst, int rows, int col0, SrcFn src_row) {
+  constexpr int CPR = W / 4, TOT = MT * CPR, IT = (TOT + NTHR - 1) / NTHR;
+  float4 v[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int c = (int)threadIdx.x + k * NTHR, i = c / CPR, q = c - i * CPR;
+    v[k] = float4{0.f, 0.f, 0.f, 0.f};
+    if (c < TOT && i < rows) v[k] = *(const float4*)(src_row(i) + q * 4);
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int c = (int)threadIdx.x + k * NTHR, i = c / CPR, q = c - i * CPR;
+    if (c < TOT) {
+      T* d = dst + i * LD + col0 + q * 4;
+      d[0] = from_f<T>(v[k].x);
+      d[1] = from_f<T>(v[k].y);
+      d[2] = from_f<T>(v[k].z);
+      d[3] = from_f<T>(v[k].w);
+    }
   }
 }
 

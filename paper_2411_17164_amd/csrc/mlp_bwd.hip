@@ -32,15 +32,13 @@ struct BD {
   static constexpr int CPW = H / NW;
 };
 
-// Copy an FP32 [rows][H] block from global into an FP32 LDS tile (zero fill).
+// Copy an FP32 [rows][H] block from global into an FP32 LDS tile (zero
+// fill); NTHR threads, all loads issued before the stores.
 template <int H, int LDF, int MT, typename SrcFn>
 __device__ __forceinline__ void f32_rows_to_lds(float* dst, int rows, SrcFn src) {
-  for (int c = threadIdx.x; c < MT * (H / 4); c += blockDim.x) {
-    const int i = c / (H / 4), q = c - i * (H / 4);
-    float4 v = {0.f, 0.f, 0.f, 0.f};
-    if (i < rows) v = src(i, q);
-    *(float4*)(dst + i * LDF + 4 * q) = v;
-  }
+  f32_tile<MT, H, NTHR>(
+      rows, false, src, [](int, int) { return float4{0.f, 0.f, 0.f, 0.f}; },
+      [&](int i, int q, const float4& v) { *(float4*)(dst + i * LDF + 4 * q) = v; });
 }
 
 template <int MB, int NB, int LDF>
@@ -351,7 +349,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
 // Node adjoint (with recompute).  dh_mid = dh' + (W1^T da)[0:H], dm = (W1^T da)[H:2H].
 // ---------------------------------------------------------------------------
 template <typename T, int H, int MT, int ACT>
-__global__ __launch_bounds__(NTHR) void k_node_bwd(int n, MlpW w, const T* __restrict__ h, const float* __restrict__ m,
+__global__ __launch_bounds__(NTHR, MT == 32 ? 2 : 1) void k_node_bwd(int n, MlpW w, const T* __restrict__ h, const float* __restrict__ m,
                                                    const float* __restrict__ dh_in, NodeBwdOut o, float eps) {
   using D = BD<T, H>;
   constexpr int MB = MT / 16, NB = D::NB;
@@ -374,8 +372,8 @@ __global__ __launch_bounds__(NTHR) void k_node_bwd(int n, MlpW w, const T* __res
   TileSched sch(n_tiles);
   for (int t = sch.begin; t < sch.end; t += sch.step) {
     const int row0 = t * MT, nr = min(MT, n - row0);
-    global_rows_to_lds<T, D::LD2, MT>(xs, nr, H, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
-    global_f32_rows_to_lds<T, D::LD2, MT>(xs, nr, H, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
+    global_rows_to_lds<T, D::LD2, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
+    global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
     __syncthreads();
     f32x4 a[MB][NB], x[MB][NB];
     zero_acc(a);
@@ -439,16 +437,15 @@ __global__ __launch_bounds__(NTHR) void k_node_bwd(int n, MlpW w, const T* __res
     wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W1T + (size_t)H * H, H, n0);  // -> dm
     acc_to_ldsf<MB, NB, D::LDF>(g, ft, n0);
     __syncthreads();
-    for (int c = threadIdx.x; c < nr * (H / 4); c += NTHR) {
-      const int i = c / (H / 4), q = c - i * (H / 4);
-      float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
-      const float4 d = *(const float4*)(dh_in + (size_t)(row0 + i) * H + 4 * q);
-      v.x += d.x;
-      v.y += d.y;
-      v.z += d.z;
-      v.w += d.w;
-      *(float4*)(o.dh_mid + (size_t)(row0 + i) * H + 4 * q) = v;
-    }
+    f32_tile<MT, H, NTHR>(
+        nr, false, [&](int i, int q) { return *(const float4*)(dh_in + (size_t)(row0 + i) * H + 4 * q); },
+        [](int, int) { return float4{0.f, 0.f, 0.f, 0.f}; },
+        [&](int i, int q, const float4& d) {
+          if (i < nr) {
+            const float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
+            *(float4*)(o.dh_mid + (size_t)(row0 + i) * H + 4 * q) = float4{v.x + d.x, v.y + d.y, v.z + d.z, v.w + d.w};
+          }
+        });
     __syncthreads();
     acc_to_ldsf<MB, NB, D::LDF>(x, ft, n0);
     __syncthreads();
@@ -467,7 +464,7 @@ __global__ __launch_bounds__(NTHR) void k_node_bwd(int n, MlpW w, const T* __res
 
 // dh_out = dh_mid + [S_r | S_s] B_rs^T, B_rs = [W1_r^T | W1_s^T] ([H][2H]).
 template <typename T, int H, int MT>
-__global__ __launch_bounds__(NTHR) void k_node_dh(int n, const T* __restrict__ Brs, const float* __restrict__ dh_mid,
+__global__ __launch_bounds__(NTHR, 2) void k_node_dh(int n, const T* __restrict__ Brs, const float* __restrict__ dh_mid,
                                                   const float* __restrict__ S_r, const float* __restrict__ S_s,
                                                   float* __restrict__ dh_out) {
   using D = BD<T, H>;
@@ -481,24 +478,23 @@ __global__ __launch_bounds__(NTHR) void k_node_dh(int n, const T* __restrict__ B
   TileSched sch(n_tiles);
   for (int t = sch.begin; t < sch.end; t += sch.step) {
     const int row0 = t * MT, nr = min(MT, n - row0);
-    global_f32_rows_to_lds<T, D::LD2, MT>(xs, nr, H, 0, [&](int i) { return S_r + (size_t)(row0 + i) * H; });
-    global_f32_rows_to_lds<T, D::LD2, MT>(xs, nr, H, H, [&](int i) { return S_s + (size_t)(row0 + i) * H; });
+    global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, 0, [&](int i) { return S_r + (size_t)(row0 + i) * H; });
+    global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, H, [&](int i) { return S_s + (size_t)(row0 + i) * H; });
     __syncthreads();
     f32x4 acc[MB][NB];
     zero_acc(acc);
     wave_gemm<T, MB, NB, 2 * H, D::LD2>(acc, xs, Brs, 2 * H, n0);
     acc_to_ldsf<MB, NB, D::LDF>(acc, ft, n0);
     __syncthreads();
-    for (int c = threadIdx.x; c < nr * (H / 4); c += NTHR) {
-      const int i = c / (H / 4), q = c - i * (H / 4);
-      float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
-      const float4 d = *(const float4*)(dh_mid + (size_t)(row0 + i) * H + 4 * q);
-      v.x += d.x;
-      v.y += d.y;
-      v.z += d.z;
-      v.w += d.w;
-      *(float4*)(dh_out + (size_t)(row0 + i) * H + 4 * q) = v;
-    }
+    f32_tile<MT, H, NTHR>(
+        nr, false, [&](int i, int q) { return *(const float4*)(dh_mid + (size_t)(row0 + i) * H + 4 * q); },
+        [](int, int) { return float4{0.f, 0.f, 0.f, 0.f}; },
+        [&](int i, int q, const float4& d) {
+          if (i < nr) {
+            const float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
+            *(float4*)(dh_out + (size_t)(row0 + i) * H + 4 * q) = float4{v.x + d.x, v.y + d.y, v.z + d.z, v.w + d.w};
+          }
+        });
     __syncthreads();
   }
 }
@@ -543,7 +539,7 @@ __global__ __launch_bounds__(NTHR) void k_sender_sum(int n, const int* __restric
 // da1, dh = W1^T da1.  Writes the factors of the weight gradients.
 // ---------------------------------------------------------------------------
 template <typename T, int H, int MT, int ACT>
-__global__ __launch_bounds__(NTHR) void k_dec_bwd(BatchView b, MlpW w, const T* __restrict__ h,
+__global__ __launch_bounds__(NTHR, 2) void k_dec_bwd(BatchView b, MlpW w, const T* __restrict__ h,
                                                   const float* __restrict__ d_out, int out_dim, DecBwdOut o) {
   using D = BD<T, H>;
   constexpr int MB = MT / 16, NB = D::NB;
@@ -568,7 +564,7 @@ __global__ __launch_bounds__(NTHR) void k_dec_bwd(BatchView b, MlpW w, const T* 
   TileSched sch(n_tiles);
   for (int t = sch.begin; t < sch.end; t += sch.step) {
     const int row0 = t * MT, nr = min(MT, b.n_inner - row0);
-    global_rows_to_lds<T, D::LDH, MT>(xs, nr, H, 0, [&](int i) { return h + (size_t)b.inner[row0 + i] * H; });
+    global_rows_to_lds<T, D::LDH, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)b.inner[row0 + i] * H; });
     for (int c = threadIdx.x; c < MT * 16; c += NTHR) {
       const int i = c >> 4, oo = c & 15;
       dys[c] = (i < nr && oo < out_dim) ? d_out[(size_t)b.gid[b.inner[row0 + i]] * out_dim + oo] : 0.f;

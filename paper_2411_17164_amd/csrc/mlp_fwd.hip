@@ -143,7 +143,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
 // Node processor, forward (Eq. 3): h' = h + LN(W2 act(W1 [h ; m] + b1) + b2)
 // ---------------------------------------------------------------------------
 template <typename T, int H, int MT, int ACT>
-__global__ __launch_bounds__(NTHR) void k_node_fwd(int n, MlpW w, const T* __restrict__ h,
+__global__ __launch_bounds__(NTHR, 2) void k_node_fwd(int n, MlpW w, const T* __restrict__ h,
                                                    const float* __restrict__ m, T* __restrict__ h_out,
                                                    float eps) {
   using D = Dims<T, H>;
@@ -162,8 +162,8 @@ __global__ __launch_bounds__(NTHR) void k_node_fwd(int n, MlpW w, const T* __res
   TileSched sch(n_tiles);
   for (int t = sch.begin; t < sch.end; t += sch.step) {
     const int row0 = t * MT, nr = min(MT, n - row0);
-    global_rows_to_lds<T, D::LD2, MT>(xs, nr, H, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
-    global_f32_rows_to_lds<T, D::LD2, MT>(xs, nr, H, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
+    global_rows_to_lds<T, D::LD2, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
+    global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
     __syncthreads();
     f32x4 acc[MB][NB];
     zero_acc(acc);
@@ -220,7 +220,7 @@ template <int KIND>
 struct EncIn;
 
 template <typename T, int H, int MT, int ACT, int KIND>
-__global__ __launch_bounds__(NTHR) void k_enc_fwd(int rows, BatchView b, MlpW w, const float* __restrict__ src,
+__global__ __launch_bounds__(NTHR, 2) void k_enc_fwd(int rows, BatchView b, MlpW w, const float* __restrict__ src,
                                                   int in_dim, EdgeNorm en, T* __restrict__ out, float eps) {
   using D = Dims<T, H>;
   constexpr int MB = MT / 16, NB = D::NB;
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(NTHR) void k_enc_fwd(int rows, BatchView b, MlpW w,
 // written to out[gid][0:out_dim].  The last layer (out_dim <= 16) is FMA.
 // ---------------------------------------------------------------------------
 template <typename T, int H, int MT, int ACT>
-__global__ __launch_bounds__(NTHR) void k_dec_fwd(BatchView b, MlpW w, const T* __restrict__ h,
+__global__ __launch_bounds__(NTHR, 2) void k_dec_fwd(BatchView b, MlpW w, const T* __restrict__ h,
                                                   float* __restrict__ out, int out_dim) {
   using D = Dims<T, H>;
   constexpr int MB = MT / 16, NB = D::NB;
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(NTHR) void k_dec_fwd(BatchView b, MlpW w, const T* 
   TileSched sch(n_tiles);
   for (int t = sch.begin; t < sch.end; t += sch.step) {
     const int row0 = t * MT, nr = min(MT, b.n_inner - row0);
-    global_rows_to_lds<T, D::LDH, MT>(xs, nr, H, 0, [&](int i) { return h + (size_t)b.inner[row0 + i] * H; });
+    global_rows_to_lds<T, D::LDH, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)b.inner[row0 + i] * H; });
     __syncthreads();
     f32x4 acc[MB][NB];
     zero_acc(acc);
