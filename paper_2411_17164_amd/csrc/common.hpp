@@ -158,6 +158,49 @@ __device__ __forceinline__ void wave_gemm(f32x4 (&acc)[MB][NB], const T* A,
   wave_gemm<T, MB, NB, K, LDA>(acc, A, f);
 }
 
+// Transposing LDS read (ds_read_b64_tr_b16, gfx950).  In each group of 16
+// lanes, lane L reads four 16-bit values at its own address, and lane 4a + b
+// receives value b of lanes a, a + 4, a + 8 and a + 12.  So if lane L points
+// at row r0 + L / 4, columns c0 + 4 (L % 4) .. + 3 of a row-major tile, lane
+// j of the group gets column c0 + j of rows r0 .. r0 + 3: a k-major MFMA
+// operand read from an n-major tile.
+typedef __bf16 bf16x4_lds __attribute__((__vector_size__(4 * sizeof(__bf16))));
+__device__ __forceinline__ bf16x4_lds lds_read_tr4(const bf16* p) {
+  return __builtin_amdgcn_ds_read_tr16_b64_v4bf16((__attribute__((address_space(3))) bf16x4_lds*)(p));
+}
+
+// MFMA B fragment B[k][n] = M[k][n] (M row-major in LDS, row stride LD) for
+// k in [k0 + 8 g, k0 + 8 g + 8) of lane group g and n = c0 + lane % 16.
+// rows_hi is the row distance of the second half of the 8 k values (4 for
+// consecutive k; any other value gives a permuted k order that the A operand
+// must share).
+__device__ __forceinline__ bf16x8 lds_bfrag_tr(const bf16* M, int LD, int r0, int c0, int rows_hi) {
+  const int l = lane_id(), L = l & 15;
+  const bf16* p = M + (size_t)(r0 + (L >> 2)) * LD + c0 + 4 * (L & 3);
+  const bf16x4_lds lo = lds_read_tr4(p), hi = lds_read_tr4(p + (size_t)rows_hi * LD);
+  return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+// acc[MB][NB] += A * B over k in [0, K) for BF16, A rows from LDS (stride
+// LDA), B fragments from bfrag(k, nb) (LDS-resident weights).
+template <int MB, int NB, int K, int LDA, typename BFrag>
+__device__ __forceinline__ void wave_gemm_lds(f32x4 (&acc)[MB][NB], const bf16* A, BFrag bfrag) {
+  const int l = lane_id(), li = l & 15, lg = l >> 4;
+  const bf16* arow = A + li * LDA + lg * 8;
+#pragma unroll
+  for (int k = 0; k < K; k += 32) {
+    bf16x8 b[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) b[nb] = bfrag(k, nb);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const bf16x8 a = *(const bf16x8*)(arow + mb * 16 * LDA + k);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mma(a, b[nb], acc[mb][nb]);
+    }
+  }
+}
+
 template <int MB, int NB>
 __device__ __forceinline__ void zero_acc(f32x4 (&acc)[MB][NB]) {
 #pragma unroll

@@ -92,35 +92,18 @@ __device__ __forceinline__ void ln_backward(const f32x4 (&xh)[MB][NB], f32x4 (&d
         dv[mb][nb][r] = (dv[mb][nb][r] - sg[mb][r] * (1.f / H) - xh[mb][nb][r] * (sgx[mb][r] * (1.f / H))) * inv[mb][r];
 }
 
-// Store the accumulator transposed ([col][row], row stride LDT) -- the four
-// values of a lane are consecutive rows of one column: one 8-byte store.
-template <int MB, int NB, int LDT>
-__device__ __forceinline__ void acc_to_lds_t(const f32x4 (&x)[MB][NB], bf16* dst, int n0) {
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      bf16x2 lo = {(bf16)x[mb][nb][0], (bf16)x[mb][nb][1]};
-      bf16x2 hi = {(bf16)x[mb][nb][2], (bf16)x[mb][nb][3]};
-      uint2 v;
-      v.x = *(const uint32_t*)&lo;
-      v.y = *(const uint32_t*)&hi;
-      *(uint2*)(dst + acc_col(n0, nb) * LDT + acc_row(mb, 0)) = v;
-    }
-}
-
 // acc[nb][jb] += sum over the MT rows of a tile of
 //   G[row][n0 + 16 nb + i] * B[row][16 jb + j],
 // the rows n0 + 16 nb (this wave's columns of G) of a H x H weight gradient
 // G^T B.  The A operand is the wave's own FP32 accumulator tile G, rounded
 // to BF16: in the MFMA accumulator layout, lane group q holds rows
-// 4q + r and 16 + 4q + r (r < 4) of each 32-row k chunk, and since the order
-// of k inside one MFMA is free, B is read from its transposed LDS tile
-// BT[col][row] in that same row order.
-template <int MB, int NB, int H, int LDT>
-__device__ __forceinline__ void wave_wgrad(f32x4 (&acc)[NB][H / 16], const f32x4 (&g)[MB][NB], const bf16* BT) {
+// 4q + r and 16 + 4q + r (r < 4) of each 32-row k chunk.  The order of k
+// inside one MFMA is free, so B is read in that same row order from its
+// row-major LDS tile (row stride LDB) with transposing reads.
+template <int MB, int NB, int H, int LDB>
+__device__ __forceinline__ void wave_wgrad(f32x4 (&acc)[NB][H / 16], const f32x4 (&g)[MB][NB], const bf16* B) {
   static_assert(MB % 2 == 0, "k chunks of 32 rows");
-  const int l = lane_id(), li = l & 15, lg = l >> 4;
+  const int lg = lane_id() >> 4;
 #pragma unroll
   for (int c = 0; c < MB / 2; ++c) {
     bf16x8 a[NB];
@@ -133,10 +116,7 @@ __device__ __forceinline__ void wave_wgrad(f32x4 (&acc)[NB][H / 16], const f32x4
       }
 #pragma unroll
     for (int jb = 0; jb < H / 16; ++jb) {
-      const bf16* p = BT + (jb * 16 + li) * LDT + 32 * c + 4 * lg;
-      const uint2 lo = *(const uint2*)p, hi = *(const uint2*)(p + 16);
-      const uint4 v = {lo.x, lo.y, hi.x, hi.y};
-      const bf16x8 b = *(const bf16x8*)&v;
+      const bf16x8 b = lds_bfrag_tr(B, LDB, 32 * c + 4 * lg, jb * 16, 16);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[nb][jb] = mma(a[nb], b, acc[nb][jb]);
     }
@@ -153,18 +133,23 @@ __device__ __forceinline__ void write_partial(float* p, int n0, const double (&v
 // ---------------------------------------------------------------------------
 // Edge adjoint (with recompute).
 // ---------------------------------------------------------------------------
-// FW: also accumulate dW2 = sum du z^T and the e-block of dW1 = sum da e^T
-// per workgroup on MFMA (BF16, H = 128): du and da straight from the
-// accumulators, z and e from transposed tiles in LDS, so that z and du never
-// travel to HBM; partials go to o.wpart.
+// FW (BF16, H = 128): also accumulate dW2 = sum du z^T and the e-block of
+// dW1 = sum da e^T per workgroup on MFMA -- du and da straight from the
+// accumulators, z and e read transposed from their LDS tiles -- so that z
+// and du never travel to HBM; partials go to o.wpart.  W2 and the e-block of
+// W1 then live in LDS for the whole kernel and serve both their products and
+// (read transposed) the adjoint products dz = du W2 and de = da W1e; the FP32
+// staging tile takes the first 2H columns of the gathered tile's rows so that
+// its e columns stay intact.
 template <typename T, int H, int MT, int FW, int NW>
 struct EdgeBwdLds {
   using D = BD<T, H, NW>;
   static constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
   static constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
-  static constexpr int LDT = MT + 8;  // transposed tiles (BF16)
-  static constexpr size_t TS = FW ? (size_t)H * LDT * 2 : 0;
-  static constexpr size_t bytes = XS + ZS + 2 * TS + 2 * NW * MT * 4 + 2 * MT * 4;
+  static constexpr int LDW = H + 8;  // LDS-resident weights (BF16)
+  static constexpr size_t WS = FW ? (size_t)H * LDW * 2 : 0;
+  static constexpr int LDF = FW ? D::LD3 * (int)sizeof(T) / 4 : D::LDF;  // FP32 staging row stride
+  static constexpr size_t bytes = XS + ZS + 2 * WS + 2 * NW * MT * 4 + 2 * MT * 4;
 };
 
 template <typename T, int H, int MT, int ACT, int AGG, int FW, int NW>
@@ -174,28 +159,36 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
   using D = BD<T, H, NW>;
   using L = EdgeBwdLds<T, H, MT, FW, NW>;
   constexpr int MB = MT / 16, NB = D::NB;
-  constexpr size_t XS = L::XS, ZS = L::ZS, TS = L::TS;
-  constexpr int LDT = L::LDT;
+  constexpr size_t XS = L::XS, ZS = L::ZS, WS = L::WS;
+  constexpr int LDW = L::LDW, LDF = L::LDF;
   static_assert(!FW || (sizeof(T) == 2 && H == 128), "fused weight gradients: BF16, H = 128");
-  static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
+  static_assert((size_t)MT * LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
+  static_assert(!FW || (size_t)H * 4 <= 2 * H * sizeof(T), "FP32 rows must leave the e columns intact");
   __shared__ __align__(16) unsigned char smem[L::bytes];
   T* xs = (T*)smem;
   float* ft = (float*)smem;
   T* zs = (T*)(smem + XS);
-  bf16* eT = (bf16*)(smem + XS + ZS);
-  bf16* zT = (bf16*)(smem + XS + ZS + TS);
-  float* red = (float*)(smem + XS + ZS + 2 * TS);
+  bf16* W2s = (bf16*)(smem + XS + ZS);       // W2 [out][in]
+  bf16* W1es = (bf16*)(smem + XS + ZS + WS);  // W1[:, 2H:3H] [out][in]
+  float* red = (float*)(smem + XS + ZS + 2 * WS);
   int* rs = (int*)(red + 2 * NW * MT);
   const T* W1 = (const T*)w.W1;
   const T* W2 = (const T*)w.W2;
   const T* W2T = (const T*)w.W2T;
   const T* W1Te = (const T*)w.W1T;
   const int n0 = wave_id() * D::CPW;
+  const int li = lane_id() & 15, lg = lane_id() >> 4;
   double cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
   f32x4 accW2[NB][H / 16], accW1[NB][H / 16];
   if constexpr (FW) {
     zero_acc(accW2);
     zero_acc(accW1);
+    // weights resident in LDS (visible after the first barrier of the tile loop)
+    for (int c = threadIdx.x; c < H * (H / 8); c += 64 * NW) {
+      const int r = c / (H / 8), q = c - r * (H / 8);
+      *(uint4*)(W2s + r * LDW + 8 * q) = *(const uint4*)(W2 + (size_t)r * H + 8 * q);
+      *(uint4*)(W1es + r * LDW + 8 * q) = *(const uint4*)(W1 + (size_t)r * 3 * H + 2 * H + 8 * q);
+    }
   }
 
   TileSched sch(b.n_etiles);
@@ -212,21 +205,20 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
     gather_tile<T, D::LD3, MT, 3, H, 64 * NW>(
         xs, ne,
         [&](int p, int i) { return p == 0 ? h + (size_t)rs[i] * H : p == 1 ? h + (size_t)ss[i] * H : e + (size_t)(e0 + i) * H; },
-        [&](int p, int i, int q, const uint4& v) {
-          if constexpr (FW) {
-            if (p == 2) {  // e^T for the dW1 e-block
-              const bf16* pv = (const bf16*)&v;
-#pragma unroll
-              for (int t = 0; t < 8; ++t) eT[(q * 8 + t) * LDT + i] = pv[t];
-            }
-          }
-        });
+        [](int, int, int, const uint4&) {});
     __syncthreads();
 
     // recompute: a, z, u, xhat
     f32x4 a[MB][NB];
     zero_acc(a);
-    wave_gemm<T, MB, NB, 3 * H, D::LD3>(a, xs, W1, 3 * H, n0);
+    if constexpr (FW) {
+      wave_gemm<T, MB, NB, 2 * H, D::LD3>(a, xs, W1, 3 * H, n0);  // [h_r ; h_s] blocks from global
+      wave_gemm_lds<MB, NB, H, D::LD3>(a, (const bf16*)xs + 2 * H, [&](int k, int nb) {
+        return *(const bf16x8*)(W1es + (n0 + 16 * nb + li) * LDW + k + 8 * lg);
+      });
+    } else {
+      wave_gemm<T, MB, NB, 3 * H, D::LD3>(a, xs, W1, 3 * H, n0);
+    }
     f32x4 x[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -240,10 +232,15 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
         }
       }
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
-    if constexpr (FW) acc_to_lds_t<MB, NB, LDT>(x, zT, n0);
     __syncthreads();
     zero_acc(x);
-    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2, H, n0);
+    if constexpr (FW) {
+      wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)zs, [&](int k, int nb) {
+        return *(const bf16x8*)(W2s + (n0 + 16 * nb + li) * LDW + k + 8 * lg);
+      });
+    } else {
+      wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2, H, n0);
+    }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -259,7 +256,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
     f32_tile<MT, H, 64 * NW>(
         ne, de_in != nullptr, [&](int i, int q) { return *(const float4*)(dm + (size_t)rs[i] * H + 4 * q); },
         [&](int i, int q) { return *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q); },
-        [&](int i, int q, const float4& v) { *(float4*)(ft + i * D::LDF + 4 * q) = v; });
+        [&](int i, int q, const float4& v) { *(float4*)(ft + i * LDF + 4 * q) = v; });
     if constexpr (!FW) lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.z + (size_t)e0 * H, H, [](int i) { return i; });
     __syncthreads();
     f32x4 g[MB][NB];
@@ -268,16 +265,25 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) g[mb][nb][r] = ft[acc_row(mb, r) * D::LDF + acc_col(n0, nb)];
+        for (int r = 0; r < 4; ++r) g[mb][nb][r] = ft[acc_row(mb, r) * LDF + acc_col(n0, nb)];
     ln_backward<MB, NB, MT, H, NW>(x, g, inv, w.gamma, n0, red, cg, cbt);  // g = du (barriers inside)
     col_accumulate(g, cb2);
-    if constexpr (FW) wave_wgrad<MB, NB, H, LDT>(accW2, g, zT);  // dW2 += du^T z
+    if constexpr (FW) {
+      wave_wgrad<MB, NB, H, D::LDH>(accW2, g, (const bf16*)zs);  // dW2 += du^T z
+      __syncthreads();  // every wave is done reading z before du replaces it
+    }
     acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
     __syncthreads();
     if constexpr (!FW) lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.du + (size_t)e0 * H, H, [](int i) { return i; });
     // dz = W2^T du ; da = dz * act'(a)
     zero_acc(x);
-    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2T, H, n0);
+    if constexpr (FW) {
+      wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)zs, [&](int k, int nb) {
+        return lds_bfrag_tr(W2s, LDW, k + 8 * lg, n0 + 16 * nb, 4);
+      });
+    } else {
+      wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2T, H, n0);
+    }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -285,9 +291,9 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
 #pragma unroll
         for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a[mb][nb][r]);
     col_accumulate(x, cb1);
-    if constexpr (FW) wave_wgrad<MB, NB, H, LDT>(accW1, x, eT);  // dW1[:, 2H:3H] += da^T e
+    if constexpr (FW) wave_wgrad<MB, NB, H, D::LD3>(accW1, x, (const bf16*)xs + 2 * H);  // dW1[:, 2H:3H] += da^T e
     __syncthreads();
-    acc_to_ldsf<MB, NB, D::LDF>(x, ft, n0);
+    acc_to_ldsf<MB, NB, LDF>(x, ft, n0);
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
     __syncthreads();
     // S_r: receiver-segment sums of da (FP32, ascending sender order)
@@ -297,7 +303,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
       const int lo = b.row_ptr[r0 + rl] - e0, hi = b.row_ptr[r0 + rl + 1] - e0;
       float4 s = {0.f, 0.f, 0.f, 0.f};
       for (int i = lo; i < hi; ++i) {
-        const float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
+        const float4 v = *(const float4*)(ft + i * LDF + 4 * q);
         s.x += v.x;
         s.y += v.y;
         s.z += v.z;
@@ -308,16 +314,22 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
     lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.da + (size_t)e0 * H, H, [](int i) { return i; });
     // de = de' (+ dm_r) + (W1^T da)[2H:3H]
     zero_acc(g);
-    wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1Te, H, n0);
+    if constexpr (FW) {
+      wave_gemm_lds<MB, NB, H, D::LDH>(g, (const bf16*)zs, [&](int k, int nb) {
+        return lds_bfrag_tr(W1es, LDW, k + 8 * lg, n0 + 16 * nb, 4);
+      });
+    } else {
+      wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1Te, H, n0);
+    }
     __syncthreads();
-    acc_to_ldsf<MB, NB, D::LDF>(g, ft, n0);
+    acc_to_ldsf<MB, NB, LDF>(g, ft, n0);
     __syncthreads();
     f32_tile<MT, H, 64 * NW>(
         ne, AGG != 0, [&](int i, int q) { return de_in ? *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q) : float4{0.f, 0.f, 0.f, 0.f}; },
         [&](int i, int q) { return *(const float4*)(dm + (size_t)rs[i] * H + 4 * q); },
         [&](int i, int q, const float4& v) {
           if (i < ne) {
-            const float4 d = *(const float4*)(ft + i * D::LDF + 4 * q);
+            const float4 d = *(const float4*)(ft + i * LDF + 4 * q);
             *(float4*)(o.de_out + (size_t)(e0 + i) * H + 4 * q) = float4{d.x + v.x, d.y + v.y, d.z + v.z, d.w + v.w};
           }
         });
@@ -329,7 +341,6 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
   write_partial<NB>(p + 2 * H, n0, cg);
   write_partial<NB>(p + 3 * H, n0, cbt);
   if constexpr (FW) {
-    const int li = lane_id() & 15, lg = lane_id() >> 4;
     float* q2 = o.wpart + (size_t)blockIdx.x * 2 * H * H;
     float* q1 = q2 + H * H;
 #pragma unroll
