@@ -177,9 +177,10 @@ void xmgn_partset_destroy(xmgn_partset* ps);
  * out:       dev FP32 [N_global][out_dim]; only the rows of the batch's inner
  *            nodes are written (halo predictions are dropped, Sec. III.D)
  * keep_tape: 1 keeps per-layer checkpoints (h^l, e^l, m^l) for backward.
- * params, node_in and pos must stay valid and unchanged until the matching
- * xmgn_backward has been enqueued: the backward re-reads them (the
- * encoders are recomputed from their inputs).
+ * params and node_in must stay valid and unchanged until the matching
+ * xmgn_backward has been enqueued: the backward re-reads them (the node
+ * encoder is recomputed from its input; the edge encoder from the edge
+ * features this call derives from pos and keeps in the context).
  */
 xmgn_status xmgn_forward(xmgn_ctx* ctx, const xmgn_model_desc* desc, const float* params,
                          const xmgn_partset* ps, const int32_t* part_ids, int32_t n_batch,

@@ -211,7 +211,7 @@ class Context:
         ids = _i32(part_ids)
         en = np.ascontiguousarray(edge_norm, dtype=np.float32).reshape(-1)
         # the backward re-reads node_in and pos: keep them alive until then
-        self._fwd_refs = (params, node_in, pos)
+        self._fwd_refs = (params, node_in)
         check(lib.xmgn_forward(self._h, C.byref(model.desc()), _dev(params), ps._h, _ptr32(ids), len(ids),
                                _dev(node_in), _dev(pos), en.ctypes.data_as(C.POINTER(C.c_float)), _dev(out),
                                1 if keep_tape else 0, _stream(stream)))
@@ -223,7 +223,7 @@ class Context:
         xmgn_autotune); returns (edge_rows, node_rows, grid, edge_waves, step_ms)."""
         ids = _i32(part_ids)
         en = np.ascontiguousarray(edge_norm, dtype=np.float32).reshape(-1)
-        self._fwd_refs = (params, node_in, pos)
+        self._fwd_refs = (params, node_in)
         er, nr, g, wv, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
         check(lib.xmgn_autotune(self._h, C.byref(model.desc()), _dev(params), ps._h, _ptr32(ids), len(ids),
                                 _dev(node_in), _dev(pos), en.ctypes.data_as(C.POINTER(C.c_float)), _dev(out),

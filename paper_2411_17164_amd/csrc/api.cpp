@@ -470,6 +470,7 @@ struct xmgn_ctx {
   bool tape_full = false;
   // backward workspace
   DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, wfused, redtmp, lossp;
+  DBuf xe;  // edge features of the forward [E][4]
   // per-kernel timing
   bool timing = false;
   std::vector<std::string> tnames;
@@ -482,8 +483,6 @@ struct xmgn_ctx {
   xmgn_model_desc fdesc{};
   const float* f_params = nullptr;
   const float* f_node_in = nullptr;
-  const float* f_pos = nullptr;
-  EdgeNorm f_en{};
 };
 
 static size_t tsize(const xmgn_model_desc* d) { return d->precision == 1 ? 2 : 4; }
@@ -629,7 +628,7 @@ extern "C" xmgn_status xmgn_ctx_memory(const xmgn_ctx* c, int64_t* bytes) {
   if (!c || !bytes) return fail(XMGN_ERR_INVALID, "NULL argument");
   const DBuf* bufs[] = {&c->batch.ints, &c->jobs_dev, &c->blob, &c->h, &c->e, &c->m, &c->dhA, &c->dhMid,
                         &c->dm, &c->Sr, &c->Ss, &c->deA, &c->deB, &c->fa, &c->fb, &c->fc, &c->fd,
-                        &c->dy, &c->part, &c->wpart, &c->wfused, &c->redtmp, &c->lossp};
+                        &c->dy, &c->part, &c->wpart, &c->wfused, &c->redtmp, &c->lossp, &c->xe};
   int64_t t = 0;
   for (const DBuf* b : bufs) t += (int64_t)b->bytes;
   *bytes = t;
@@ -889,7 +888,9 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
   g_config_error = 0;
   { KT("prep"); launch_prep(params, c->blob.p, d->precision, c->jobs_dev.as<PrepJob>(), (int)c->jobs.size(), st); }
   { KT("enc_node_fwd"); launch_enc_node_fwd(s, b, weights(c, d, params, 0, 0, 0), node_in, d->node_in, hslot(c, d, 0), st); }
-  { KT("enc_edge_fwd"); launch_enc_edge_fwd(s, b, weights(c, d, params, 1, 1, 0), pos, en, eslot(c, d, 0), st); }
+  if (xmgn_status r = c->xe.ensure((size_t)b.E * 4 * sizeof(float))) return r;
+  { KT("edge_feat"); launch_edge_feat(b, pos, en, c->xe.as<float>(), st); }
+  { KT("enc_edge_fwd"); launch_enc_edge_fwd(s, b, weights(c, d, params, 1, 1, 0), c->xe.as<float>(), eslot(c, d, 0), st); }
   for (int l = 0; l < L; ++l) {
     { KT("edge_fwd"); launch_edge_fwd(s, b, weights(c, d, params, 2 + 2 * l, 2, l), hslot(c, d, l), eslot(c, d, l),
                     l + 1 < L ? eslot(c, d, l + 1) : nullptr, mslot(c, d, l), st); }
@@ -904,8 +905,6 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
   c->fdesc = *d;
   c->f_params = params;
   c->f_node_in = node_in;
-  c->f_pos = pos;
-  c->f_en = en;
   return XMGN_OK;
   GUARD_END
 }
@@ -994,8 +993,8 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   const bool fw = edge_bwd_fuses_wgrad(s);
   Shape se = s;
   if (fw) se.grid = std::min(s.grid, 512);
-  if (fw)
-    if (xmgn_status r = c->wfused.ensure((size_t)se.grid * 2 * H * H * 4)) return r;
+  if (fw || enc_bwd_fuses_wgrad(s))
+    if (xmgn_status r = c->wfused.ensure((size_t)std::max(se.grid, std::min(s.grid, 256)) * 2 * H * H * 4)) return r;
   if (xmgn_status r = c->redtmp.ensure(reduce_tmp_floats((int)std::max<size_t>(H * H, 16 * H)) * 4)) return r;
   float* rt = c->redtmp.as<float>();
   float* part = c->part.as<float>();
@@ -1065,28 +1064,38 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     std::swap(de_out, de_other);
   }
   // encoders
+  const bool fe = enc_bwd_fuses_wgrad(s);
+  Shape sn = s;  // encoders: with fused weight gradients, at most one workgroup per CU in flight
+  if (fe) sn.grid = std::min(s.grid, 256);
   for (int blk = 1; blk >= 0; --blk) {
     const MlpW w = weights(c, d, params, blk, blk, 0);
-    EncBwdOut o{c->fa.p, c->fb.p, c->fc.p, c->fd.p, part};
+    EncBwdOut o{c->fa.p, c->fb.p, c->fc.p, c->fd.p, part, fe ? c->wfused.as<float>() : nullptr};
     int R;
     int in_dim;
     if (blk == 1) {
-      { KT("enc_edge_bwd"); launch_enc_edge_bwd(s, b, w, c->f_pos, c->f_en, de_in, o, st); }
+      { KT("enc_edge_bwd"); launch_enc_edge_bwd(sn, b, w, c->xe.as<float>(), de_in, o, st); }
       R = (int)E;
       in_dim = 4;
     } else {
-      { KT("enc_node_bwd"); launch_enc_node_bwd(s, b, w, c->f_node_in, d->node_in, c->dhA.as<float>(), o, st); }
+      { KT("enc_node_bwd"); launch_enc_node_bwd(sn, b, w, c->f_node_in, d->node_in, c->dhA.as<float>(), o, st); }
       R = (int)n;
       in_dim = d->node_in;
     }
     VecSeg vs[5] = {{0, (int)H, P(blk, 0, 1)}, {(int)H, (int)H, P(blk, 0, 3)}, {2 * (int)H, (int)H, P(blk, 0, 5)},
                     {3 * (int)H, (int)H, P(blk, 0, 6)}, {4 * (int)H, (int)H, P(blk, 0, 7)}};
-    launch_vec_reduce(part, G, 13 * (int)H, vs, 5, rt, st);
-    launch_vec_reduce_strided(part, G, 13 * (int)H, 5 * (int)H, (int)H, in_dim, 8, P(blk, 0, 0), in_dim, rt, st);
-    wgrad(s, wop(c->fd.p, 0, (int)H, 0, nullptr, c->fb.p, 0, (int)H, 0, nullptr, R, (int)H, (int)H, P(blk, 0, 4),
-                 (int)H), c->wpart, st);
-    wgrad(s, wop(c->fc.p, 0, (int)H, 0, nullptr, c->fa.p, 0, (int)H, 0, nullptr, R, (int)H, (int)H, P(blk, 0, 2),
-                 (int)H), c->wpart, st);
+    launch_vec_reduce(part, sn.grid, 13 * (int)H, vs, 5, rt, st);
+    launch_vec_reduce_strided(part, sn.grid, 13 * (int)H, 5 * (int)H, (int)H, in_dim, 8, P(blk, 0, 0), in_dim, rt, st);
+    if (fe) {
+      KT("wgrad");
+      launch_wgrad_reduce(c->wfused.as<float>(), sn.grid, (int)H, (int)H, P(blk, 0, 2), (int)H, 2 * (int)(H * H), rt, st);
+      launch_wgrad_reduce(c->wfused.as<float>() + H * H, sn.grid, (int)H, (int)H, P(blk, 0, 4), (int)H,
+                          2 * (int)(H * H), rt, st);
+    } else {
+      wgrad(s, wop(c->fd.p, 0, (int)H, 0, nullptr, c->fb.p, 0, (int)H, 0, nullptr, R, (int)H, (int)H, P(blk, 0, 4),
+                   (int)H), c->wpart, st);
+      wgrad(s, wop(c->fc.p, 0, (int)H, 0, nullptr, c->fa.p, 0, (int)H, 0, nullptr, R, (int)H, (int)H, P(blk, 0, 2),
+                   (int)H), c->wpart, st);
+    }
   }
   HIPCHK(hipGetLastError());
   if (g_config_error) return fail(XMGN_ERR_UNSUPPORTED, "tile configuration does not fit this kernel");

@@ -65,8 +65,10 @@ struct EdgeNorm {
 // ---- forward ----
 void launch_enc_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const float* node_in,
                          int in_dim, void* h0, hipStream_t st);
-void launch_enc_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const float* pos,
-                         EdgeNorm en, void* e0, hipStream_t st);
+// Edge features ([x_s - x_r, |x_s - x_r|] - mu) / sd into xe[E][4].
+void launch_edge_feat(const BatchView& b, const float* pos, EdgeNorm en, float* xe, hipStream_t st);
+void launch_enc_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const float* xe, void* e0,
+                         hipStream_t st);
 void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h,
                      const void* e, void* e_out, float* m, hipStream_t st);
 void launch_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h,
@@ -128,11 +130,15 @@ struct EncBwdOut {
   void* da2;
   void* du3;
   float* partial;  // [grid][5H + 8H]: db1 db2 db3 dgamma dbeta dW1[H][8]
+  float* wpart;    // fused weight gradients [grid][2][H][H] (dW2, dW3) or NULL
 };
+// True when the encoder adjoint accumulates dW2 and dW3 itself (then z1,
+// z2, da2 and du3 are not written and wpart must be given).
+bool enc_bwd_fuses_wgrad(const Shape& s);
 void launch_enc_node_bwd(const Shape& s, const BatchView& b, const MlpW& w, const float* node_in,
                          int in_dim, const float* dh0, const EncBwdOut& o, hipStream_t st);
-void launch_enc_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const float* pos,
-                         EdgeNorm en, const float* de0, const EncBwdOut& o, hipStream_t st);
+void launch_enc_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const float* xe, const float* de0,
+                         const EncBwdOut& o, hipStream_t st);
 
 // ---- auxiliary ----
 // C[m][n] = sum_r A[ia(r)][a0 + m] * B[ib(r)][b0 + n] over r < R; partial

@@ -657,30 +657,54 @@ __global__ __launch_bounds__(NTHR, 2) void k_dec_bwd(BatchView b, MlpW w, const 
 }
 
 // ---------------------------------------------------------------------------
-// Encoder adjoint: y = LN(W3 act(W2 act(W1 x + b1) + b2) + b3).
-// Writes du3, z2, da2, z1 for dW3, dW2; dW1 (H x in) is accumulated per
-// workgroup since in <= 8.
+// Encoder adjoint: y = LN(W3 act(W2 act(W1 x + b1) + b2) + b3).  dW1
+// (H x in) is accumulated per workgroup since in <= 8.  dW3 and dW2 are
+// either accumulated per workgroup on MFMA as well (FE: BF16, H = 128 --
+// du3 and da2 straight from the accumulators, z2 and z1 read transposed from
+// their LDS tiles, W2 and W3 resident in LDS and read transposed for the
+// adjoint products; partials go to o.wpart), or du3, z2, da2, z1 are
+// written out for separate weight-gradient products.
 // ---------------------------------------------------------------------------
+bool enc_bwd_fuses_wgrad(const Shape& s) { return s.prec == 1 && s.H == 128; }
+
 template <typename T, int H, int MT, int ACT, int KIND>
 __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w, const float* __restrict__ src, int in_dim,
-                                                  EdgeNorm en, const float* __restrict__ dout, EncBwdOut o, float eps) {
+                                                  const float* __restrict__ dout, EncBwdOut o, float eps) {
   using D = BD<T, H>;
+  constexpr bool FE = sizeof(T) == 2 && H == 128;
   constexpr int MB = MT / 16, NB = D::NB;
+  constexpr int LDW = H + 8;
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
   constexpr size_t FS = (size_t)MT * D::LDF * 4;
-  __shared__ __align__(16) unsigned char smem[2 * ZS + FS + MT * 8 * 4 + 2 * NWAVE * MT * 4];
+  constexpr size_t WS = FE ? (size_t)H * LDW * 2 : 0;
+  static_assert(!FE || (MB % 2 == 0 && ZS <= FS), "fused weight gradients: k chunks of 32 rows, du3 over the FP32 tile");
+  __shared__ __align__(16) unsigned char smem[2 * ZS + FS + MT * 8 * 4 + 2 * NWAVE * MT * 4 + 2 * WS];
   T* zs = (T*)smem;
   T* z2s = (T*)(smem + ZS);
   float* ft = (float*)(smem + 2 * ZS);
+  T* du3s = (T*)ft;  // FE: du3 once the FP32 tile is dead
   float* xin = (float*)(smem + 2 * ZS + FS);
   float* red = xin + MT * 8;  // [2][NWAVE][MT]
+  bf16* W2s = (bf16*)(red + 2 * NWAVE * MT);  // FE: W2 [out][in]
+  bf16* W3s = W2s + (FE ? H * LDW : 0);       // FE: W3 [out][in]
   const T* W2 = (const T*)w.W2;
   const T* W3 = (const T*)w.W3;
   const T* W2T = (const T*)w.W2T;
   const T* W3T = (const T*)w.W3T;
   const int n0 = wave_id() * D::CPW;
+  const int li = lane_id() & 15, lg = lane_id() >> 4;
   double cb1[NB] = {}, cb2[NB] = {}, cb3[NB] = {}, cg[NB] = {}, cbt[NB] = {};
   double cw1[NB][8] = {};
+  f32x4 accW2[NB][H / 16], accW3[NB][H / 16];
+  if constexpr (FE) {
+    zero_acc(accW2);
+    zero_acc(accW3);
+    for (int c = threadIdx.x; c < H * (H / 8); c += NTHR) {
+      const int r = c / (H / 8), q = c - r * (H / 8);
+      *(uint4*)(W2s + r * LDW + 8 * q) = *(const uint4*)(W2 + (size_t)r * H + 8 * q);
+      *(uint4*)(W3s + r * LDW + 8 * q) = *(const uint4*)(W3 + (size_t)r * H + 8 * q);
+    }
+  }
   const int n_tiles = (rows + MT - 1) / MT;
 
   TileSched sch(n_tiles);
@@ -694,15 +718,11 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
           const float* p = src + (size_t)b.gid[row0 + i] * in_dim;
           for (int k = 0; k < in_dim; ++k) v[k] = p[k];
         } else {
-          const int k = row0 + i;
-          const float* ps = src + (size_t)b.gid[b.col[k]] * 3;
-          const float* pr = src + (size_t)b.gid[b.recv[k]] * 3;
-          const float dx = ps[0] - pr[0], dy = ps[1] - pr[1], dz = ps[2] - pr[2];
-          const float d = sqrtf(dx * dx + dy * dy + dz * dz);
-          v[0] = (dx - en.mu[0]) / en.sd[0];
-          v[1] = (dy - en.mu[1]) / en.sd[1];
-          v[2] = (dz - en.mu[2]) / en.sd[2];
-          v[3] = (d - en.mu[3]) / en.sd[3];
+          const float4 f = ((const float4*)src)[row0 + i];  // edge features (k_edge_feat)
+          v[0] = f.x;
+          v[1] = f.y;
+          v[2] = f.z;
+          v[3] = f.w;
         }
       }
 #pragma unroll
@@ -732,7 +752,13 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
     __syncthreads();
     zero_acc(a2);
-    wave_gemm<T, MB, NB, H, D::LDH>(a2, zs, W2, H, n0);
+    if constexpr (FE) {
+      wave_gemm_lds<MB, NB, H, D::LDH>(a2, (const bf16*)zs, [&](int k, int nb) {
+        return *(const bf16x8*)(W2s + (n0 + 16 * nb + li) * LDW + k + 8 * lg);
+      });
+    } else {
+      wave_gemm<T, MB, NB, H, D::LDH>(a2, zs, W2, H, n0);
+    }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -747,7 +773,13 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
     acc_to_lds<T, MB, NB, D::LDH>(x, z2s, n0);
     __syncthreads();
     zero_acc(x);
-    wave_gemm<T, MB, NB, H, D::LDH>(x, z2s, W3, H, n0);
+    if constexpr (FE) {
+      wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)z2s, [&](int k, int nb) {
+        return *(const bf16x8*)(W3s + (n0 + 16 * nb + li) * LDW + k + 8 * lg);
+      });
+    } else {
+      wave_gemm<T, MB, NB, H, D::LDH>(x, z2s, W3, H, n0);
+    }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -759,8 +791,10 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
     float inv[MB][4];
     ln_normalize<MB, NB, MT, H>(x, red, eps, inv);
     f32_rows_to_lds<H, D::LDF, MT>(ft, nr, [&](int i, int q) { return *(const float4*)(dout + (size_t)(row0 + i) * H + 4 * q); });
-    lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z1 + (size_t)row0 * H, H, [](int i) { return i; });
-    lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.z2 + (size_t)row0 * H, H, [](int i) { return i; });
+    if constexpr (!FE) {
+      lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z1 + (size_t)row0 * H, H, [](int i) { return i; });
+      lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.z2 + (size_t)row0 * H, H, [](int i) { return i; });
+    }
     __syncthreads();
     f32x4 g[MB][NB];
 #pragma unroll
@@ -769,13 +803,22 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) g[mb][nb][r] = ft[acc_row(mb, r) * D::LDF + acc_col(n0, nb)];
-    ln_backward<MB, NB, MT, H>(x, g, inv, w.gamma, n0, red, cg, cbt);
+    ln_backward<MB, NB, MT, H>(x, g, inv, w.gamma, n0, red, cg, cbt);  // barriers inside: ft is dead after
     col_accumulate(g, cb3);
-    acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
-    __syncthreads();
-    lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.du3 + (size_t)row0 * H, H, [](int i) { return i; });
     zero_acc(x);
-    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W3T, H, n0);
+    if constexpr (FE) {
+      wave_wgrad<MB, NB, H, D::LDH>(accW3, g, (const bf16*)z2s);  // dW3 += du3^T z2
+      acc_to_lds<T, MB, NB, D::LDH>(g, du3s, n0);
+      __syncthreads();
+      wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)du3s, [&](int k, int nb) {
+        return lds_bfrag_tr(W3s, LDW, k + 8 * lg, n0 + 16 * nb, 4);
+      });
+    } else {
+      acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
+      __syncthreads();
+      lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.du3 + (size_t)row0 * H, H, [](int i) { return i; });
+      wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W3T, H, n0);
+    }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -783,12 +826,19 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
 #pragma unroll
         for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a2[mb][nb][r]);
     col_accumulate(x, cb2);
+    if constexpr (FE) wave_wgrad<MB, NB, H, D::LDH>(accW2, x, (const bf16*)zs);  // dW2 += da2^T z1
     __syncthreads();
     acc_to_lds<T, MB, NB, D::LDH>(x, z2s, n0);
     __syncthreads();
-    lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.da2 + (size_t)row0 * H, H, [](int i) { return i; });
     zero_acc(x);
-    wave_gemm<T, MB, NB, H, D::LDH>(x, z2s, W2T, H, n0);
+    if constexpr (FE) {
+      wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)z2s, [&](int k, int nb) {
+        return lds_bfrag_tr(W2s, LDW, k + 8 * lg, n0 + 16 * nb, 4);
+      });
+    } else {
+      lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.da2 + (size_t)row0 * H, H, [](int i) { return i; });
+      wave_gemm<T, MB, NB, H, D::LDH>(x, z2s, W2T, H, n0);
+    }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -820,6 +870,20 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int k = 0; k < 8; ++k) p[5 * H + acc_col(n0, nb) * 8 + k] = (float)cw1[nb][k];
+  if constexpr (FE) {
+    float* q2 = o.wpart + (size_t)blockIdx.x * 2 * H * H;
+    float* q3 = q2 + H * H;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int jb = 0; jb < H / 16; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = n0 + nb * 16 + lg * 4 + r, n = jb * 16 + li;
+          q2[m * H + n] = accW2[nb][jb][r];
+          q3[m * H + n] = accW3[nb][jb][r];
+        }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -936,17 +1000,17 @@ void launch_enc_node_bwd(const Shape& s, const BatchView& b, const MlpW& w, cons
                          const float* dh0, const EncBwdOut& o, hipStream_t st) {
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
     if constexpr (node_fits<T, H, MT>())
-      k_enc_bwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, EdgeNorm{}, dh0, o, s.eps);
+      k_enc_bwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, dh0, o, s.eps);
     else
       g_config_error = 1;
   }))));
 }
 
-void launch_enc_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const float* pos, EdgeNorm en,
-                         const float* de0, const EncBwdOut& o, hipStream_t st) {
-  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
+void launch_enc_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const float* xe, const float* de0,
+                         const EncBwdOut& o, hipStream_t st) {
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
     if constexpr (node_fits<T, H, MT>())
-      k_enc_bwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b.E, b, w, pos, 4, en, de0, o, s.eps);
+      k_enc_bwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b.E, b, w, xe, 4, de0, o, s.eps);
     else
       g_config_error = 1;
   }))));

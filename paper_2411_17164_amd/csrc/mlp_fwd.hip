@@ -214,14 +214,30 @@ __global__ __launch_bounds__(NTHR, 2) void k_node_fwd(int n, MlpW w, const T* __
 // ---------------------------------------------------------------------------
 // Encoders: in -> H -> H -> H, LN.  The first layer (in <= 8) is a plain FMA
 // product in the accumulator layout; the other two run on MFMA.
-// Node input: node_in[gid]; edge input: ([x_s - x_r, |x_s - x_r|] - mu) / sd.
+// Node input: node_in[gid]; edge input: the edge features of k_edge_feat.
 // ---------------------------------------------------------------------------
-template <int KIND>
-struct EncIn;
+// Edge features ([x_s - x_r, |x_s - x_r|] - mu) / sd, one float4 per edge
+// (Sec. III.B), computed once per forward and read by both edge encoders.
+__global__ __launch_bounds__(256) void k_edge_feat(int E, BatchView b, const float* __restrict__ pos, EdgeNorm en,
+                                                   float4* __restrict__ xe) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= E) return;
+  const float* ps = pos + (size_t)b.gid[b.col[k]] * 3;
+  const float* pr = pos + (size_t)b.gid[b.recv[k]] * 3;
+  const float dx = ps[0] - pr[0], dy = ps[1] - pr[1], dz = ps[2] - pr[2];
+  const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+  xe[k] = float4{(dx - en.mu[0]) / en.sd[0], (dy - en.mu[1]) / en.sd[1], (dz - en.mu[2]) / en.sd[2],
+                 (d - en.mu[3]) / en.sd[3]};
+}
+
+void launch_edge_feat(const BatchView& b, const float* pos, EdgeNorm en, float* xe, hipStream_t st) {
+  if (b.E == 0) return;
+  k_edge_feat<<<(b.E + 255) / 256, 256, 0, st>>>(b.E, b, pos, en, (float4*)xe);
+}
 
 template <typename T, int H, int MT, int ACT, int KIND>
 __global__ __launch_bounds__(NTHR, 2) void k_enc_fwd(int rows, BatchView b, MlpW w, const float* __restrict__ src,
-                                                  int in_dim, EdgeNorm en, T* __restrict__ out, float eps) {
+                                                  int in_dim, T* __restrict__ out, float eps) {
   using D = Dims<T, H>;
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
@@ -246,15 +262,11 @@ __global__ __launch_bounds__(NTHR, 2) void k_enc_fwd(int rows, BatchView b, MlpW
           const float* p = src + (size_t)b.gid[row0 + i] * in_dim;
           for (int k = 0; k < in_dim; ++k) v[k] = p[k];
         } else {
-          const int k = row0 + i;
-          const float* ps = src + (size_t)b.gid[b.col[k]] * 3;
-          const float* pr = src + (size_t)b.gid[b.recv[k]] * 3;
-          const float dx = ps[0] - pr[0], dy = ps[1] - pr[1], dz = ps[2] - pr[2];
-          const float d = sqrtf(dx * dx + dy * dy + dz * dz);
-          v[0] = (dx - en.mu[0]) / en.sd[0];
-          v[1] = (dy - en.mu[1]) / en.sd[1];
-          v[2] = (dz - en.mu[2]) / en.sd[2];
-          v[3] = (d - en.mu[3]) / en.sd[3];
+          const float4 f = ((const float4*)src)[row0 + i];  // edge features (k_edge_feat)
+          v[0] = f.x;
+          v[1] = f.y;
+          v[2] = f.z;
+          v[3] = f.w;
         }
       }
 #pragma unroll
@@ -462,15 +474,15 @@ void launch_enc_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, cons
                          void* h0, hipStream_t st) {
   if (b.n == 0) return;
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
-    k_enc_fwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, EdgeNorm{}, (T*)h0, s.eps);
+    k_enc_fwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, (T*)h0, s.eps);
   }))));
 }
 
-void launch_enc_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const float* pos, EdgeNorm en,
-                         void* e0, hipStream_t st) {
+void launch_enc_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const float* xe, void* e0,
+                         hipStream_t st) {
   if (b.E == 0) return;
-  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
-    k_enc_fwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b.E, b, w, pos, 4, en, (T*)e0, s.eps);
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
+    k_enc_fwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b.E, b, w, xe, 4, (T*)e0, s.eps);
   }))));
 }
 
