@@ -512,6 +512,27 @@ __host__ __device__ constexpr int waves_per_simd(size_t lds_bytes, int nw) {
   return w < 1 ? 1 : (w > 2 ? 2 : w);
 }
 
+// Indices of one edge tile: its receiver range [r0, r1), its edge range
+// [e0, e0 + ne), and this thread's edge (receiver rv, sender cv; threads
+// below ne).  Loaded one tile ahead so that the chain of dependent index
+// loads overlaps the previous tile's work.
+struct EdgeTileIdx {
+  int r0, r1, e0, ne, rv, cv;
+  template <typename BV>
+  __device__ __forceinline__ void load(const BV& b, int t) {
+    r0 = b.etiles[t];
+    r1 = b.etiles[t + 1];
+    e0 = b.row_ptr[r0];
+    ne = b.row_ptr[r1] - e0;
+    rv = 0;
+    cv = 0;
+    if ((int)threadIdx.x < ne) {
+      rv = b.recv[e0 + threadIdx.x];
+      cv = b.col[e0 + threadIdx.x];
+    }
+  }
+};
+
 // Persistent-grid tile schedule.  The workgroups of the grid are dealt
 // round-robin to the 8 XCDs (workgroup b runs on XCD b % 8); each XCD takes a
 // contiguous eighth of the tiles so that neighbouring tiles, which share

@@ -192,20 +192,22 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
   }
 
   TileSched sch(b.n_etiles);
+  EdgeTileIdx nx{};
+  if (sch.begin < sch.end) nx.load(b, sch.begin);
   for (int t = sch.begin; t < sch.end; t += sch.step) {
-    const int r0 = b.etiles[t], r1 = b.etiles[t + 1];
-    const int e0 = b.row_ptr[r0], ne = b.row_ptr[r1] - e0;
+    const EdgeTileIdx cur = nx;
+    const int r0 = cur.r0, r1 = cur.r1, e0 = cur.e0, ne = cur.ne;
     int* ss = rs + MT;
     if (threadIdx.x < MT) {
-      const bool ok = (int)threadIdx.x < ne;
-      rs[threadIdx.x] = ok ? b.recv[e0 + threadIdx.x] : 0;
-      ss[threadIdx.x] = ok ? b.col[e0 + threadIdx.x] : 0;
+      rs[threadIdx.x] = cur.rv;
+      ss[threadIdx.x] = cur.cv;
     }
     __syncthreads();
     gather_tile<T, D::LD3, MT, 3, H, 64 * NW>(
         xs, ne,
         [&](int p, int i) { return p == 0 ? h + (size_t)rs[i] * H : p == 1 ? h + (size_t)ss[i] * H : e + (size_t)(e0 + i) * H; },
         [](int, int, int, const uint4&) {});
+    if (t + sch.step < sch.end) nx.load(b, t + sch.step);  // next tile's indices, in flight from here
     __syncthreads();
 
     // recompute: a, z, u, xhat
