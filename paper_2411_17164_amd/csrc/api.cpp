@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <fstream>
 #include <sstream>
 #include <cmath>
@@ -182,10 +183,19 @@ struct PartHost {
   std::vector<int32_t> gid, hop, row_ptr, col;
 };
 
+// Every partition set gets a serial number of its own: a context caches the
+// plan of its last batch by it, so a set freed and another allocated at the
+// same address never match.
+static uint64_t next_partset_serial() {
+  static std::atomic<uint64_t> n{0};
+  return ++n;
+}
+
 struct xmgn_partset {
   int32_t n_global = 0;
   int32_t halo = 0;
   std::vector<PartHost> parts;
+  const uint64_t serial = next_partset_serial();
 };
 
 static xmgn_status check_csr(int32_t n, const int32_t* row_ptr, const int32_t* col) {
@@ -439,6 +449,7 @@ extern "C" void xmgn_partset_destroy(xmgn_partset* ps) { delete ps; }
 // ---------------------------------------------------------------------------
 struct Batch {
   const xmgn_partset* ps = nullptr;
+  uint64_t ps_serial = 0;
   std::vector<int32_t> part_ids;
   int mt_edge = 0;
   int n = 0, n_inner = 0;
@@ -734,12 +745,13 @@ static MlpW weights(const xmgn_ctx* c, const xmgn_model_desc* d, const float* pa
 
 static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32_t* part_ids, int32_t n_batch,
                                 int mt_edge) {
-  if (c->have_batch && c->batch.ps == ps && c->batch.mt_edge == mt_edge &&
+  if (c->have_batch && c->batch.ps == ps && c->batch.ps_serial == ps->serial && c->batch.mt_edge == mt_edge &&
       c->batch.part_ids == std::vector<int32_t>(part_ids, part_ids + n_batch))
     return XMGN_OK;
   c->have_batch = false;
   Batch& B = c->batch;
   B.ps = ps;
+  B.ps_serial = ps->serial;
   B.part_ids.assign(part_ids, part_ids + n_batch);
   B.mt_edge = mt_edge;
   int64_t n = 0, E = 0, ni = 0;
@@ -1018,22 +1030,31 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
           c->wpart, st);
   }
   // processor layers, last to first
+  const bool fnode = node_bwd_fuses_wgrad(s);
+  Shape snode = s;  // node adjoint: with LDS-resident weights, one workgroup per CU
+  if (fnode) snode.grid = std::min(s.grid, 256);
   const float* de_in = nullptr;
   DBuf* de_out = &c->deA;
   DBuf* de_other = &c->deB;
   for (int l = L - 1; l >= 0; --l) {
     const MlpW wn = weights(c, d, params, 3 + 2 * l, 3, l);
-    NodeBwdOut no{c->dhMid.as<float>(), c->dm.as<float>(), c->fa.p, c->fb.p, c->fc.p, part};
-    { KT("node_bwd"); launch_node_bwd(s, b, wn, hl(l), mslot(c, d, l), c->dhA.as<float>(), no, st); }
+    NodeBwdOut no{c->dhMid.as<float>(), c->dm.as<float>(), c->fa.p, c->fb.p, c->fc.p, part,
+                  fnode ? c->wfused.as<float>() : nullptr};
+    { KT("node_bwd"); launch_node_bwd(snode, b, wn, hl(l), mslot(c, d, l), c->dhA.as<float>(), no, st); }
     VecSeg ns[4] = {{0, (int)H, P(3, l, 1)}, {(int)H, (int)H, P(3, l, 3)}, {2 * (int)H, (int)H, P(3, l, 4)},
                     {3 * (int)H, (int)H, P(3, l, 5)}};
-    launch_vec_reduce(part, G, 4 * (int)H, ns, 4, rt, st);
+    launch_vec_reduce(part, snode.grid, 4 * (int)H, ns, 4, rt, st);
     wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 0),
                  2 * (int)H), c->wpart, st);
     wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, mslot(c, d, l), 1, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
                  P(3, l, 0) + H, 2 * (int)H), c->wpart, st);
-    wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, c->fc.p, 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 2),
-                 (int)H), c->wpart, st);
+    if (fnode) {
+      KT("wgrad");
+      launch_wgrad_reduce(c->wfused.as<float>(), snode.grid, (int)H, (int)H, P(3, l, 2), (int)H, (int)(H * H), rt, st);
+    } else {
+      wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, c->fc.p, 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
+                   P(3, l, 2), (int)H), c->wpart, st);
+    }
 
     const MlpW we = weights(c, d, params, 2 + 2 * l, 2, l);
     EdgeBwdOut eo{de_out->as<float>(), c->Sr.as<float>(), c->fa.p, c->fb.p, c->fc.p, part,

@@ -83,16 +83,15 @@ __device__ __forceinline__ float act_d(float a) {
 
 // The B operand B[k][n] = W[n][k] of a wave's product, for its output
 // columns [n0, n0 + 16 NB) and k in [0, K), W in global memory (row stride
-// ldw).  For BF16 every fragment is loaded into registers by load(), in one
-// batch (K / KC x NB x 4 registers), so that the loads can be issued ahead of
-// the product -- weights are the same for every tile, and their round trip
-// then overlaps other work.  For FP32 (twice the registers) the fragments
-// are loaded inside the product's k loop instead.
+// ldw).  When the whole operand fits in 96 registers (BF16 at H = 128),
+// load() brings every fragment in one batch, so the weights cost one round
+// trip per product.  Otherwise (FP32, H = 256) the fragments are loaded
+// inside the product's k loop instead.
 template <typename T, int NB, int K>
 struct WFrag {
   using V = typename TT<T>::V;
   static constexpr int E = TT<T>::E, KC = 4 * E;
-  static constexpr bool PRE = sizeof(T) == 2;
+  static constexpr bool PRE = sizeof(T) == 2 && (K / KC) * NB * 4 <= 96;
   static_assert(K % KC == 0, "K must be a multiple of the MFMA k chunk");
   V b[PRE ? K / KC : 1][NB];
   const T* wrow[NB];

@@ -360,26 +360,53 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
 
 // ---------------------------------------------------------------------------
 // Node adjoint (with recompute).  dh_mid = dh' + (W1^T da)[0:H], dm = (W1^T da)[H:2H].
+// FN (BF16, H = 128): W1 and W2 live in LDS for the whole kernel and serve
+// both their products and, read transposed, the adjoint products; dW2 is
+// accumulated per workgroup on MFMA (du from the accumulators, z read
+// transposed from its tile; partials to o.wpart), so z and du are not
+// written.  da is always written for the dW1 product.
 // ---------------------------------------------------------------------------
+bool node_bwd_fuses_wgrad(const Shape& s) { return s.prec == 1 && s.H == 128; }
+
 template <typename T, int H, int MT, int ACT>
-__global__ __launch_bounds__(NTHR, MT == 32 ? 2 : 1) void k_node_bwd(int n, MlpW w, const T* __restrict__ h, const float* __restrict__ m,
-                                                   const float* __restrict__ dh_in, NodeBwdOut o, float eps) {
+__global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 && H == 128 ? 2 : 1)) void k_node_bwd(
+    int n, MlpW w, const T* __restrict__ h, const float* __restrict__ m, const float* __restrict__ dh_in,
+    NodeBwdOut o, float eps) {
   using D = BD<T, H>;
+  constexpr bool FN = sizeof(T) == 2 && H == 128;
   constexpr int MB = MT / 16, NB = D::NB;
+  constexpr int LDW1 = 2 * H + 8, LDW2 = H + 8;
   constexpr size_t XS = (size_t)MT * D::LD2 * sizeof(T);
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
+  constexpr size_t W1S = FN ? (size_t)H * LDW1 * 2 : 0, W2S = FN ? (size_t)H * LDW2 * 2 : 0;
   static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
-  __shared__ __align__(16) unsigned char smem[XS + ZS + 2 * NWAVE * MT * 4];
+  static_assert(!FN || MB % 2 == 0, "fused dW2: k chunks of 32 rows");
+  __shared__ __align__(16) unsigned char smem[XS + ZS + 2 * NWAVE * MT * 4 + W1S + W2S];
   T* xs = (T*)smem;
   float* ft = (float*)smem;
   T* zs = (T*)(smem + XS);
   float* red = (float*)(smem + XS + ZS);
+  bf16* W1s = (bf16*)(red + 2 * NWAVE * MT);  // FN: W1 [out][2H in]
+  bf16* W2s = W1s + (FN ? H * LDW1 : 0);      // FN: W2 [out][in]
   const T* W1 = (const T*)w.W1;
   const T* W2 = (const T*)w.W2;
   const T* W2T = (const T*)w.W2T;
   const T* W1T = (const T*)w.W1T;
   const int n0 = wave_id() * D::CPW;
+  const int li = lane_id() & 15, lg = lane_id() >> 4;
   double cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
+  f32x4 accW2[NB][H / 16];
+  if constexpr (FN) {
+    zero_acc(accW2);
+    for (int c = threadIdx.x; c < H * (2 * H / 8); c += NTHR) {
+      const int r = c / (2 * H / 8), q = c - r * (2 * H / 8);
+      *(uint4*)(W1s + r * LDW1 + 8 * q) = *(const uint4*)(W1 + (size_t)r * 2 * H + 8 * q);
+    }
+    for (int c = threadIdx.x; c < H * (H / 8); c += NTHR) {
+      const int r = c / (H / 8), q = c - r * (H / 8);
+      *(uint4*)(W2s + r * LDW2 + 8 * q) = *(const uint4*)(W2 + (size_t)r * H + 8 * q);
+    }
+  }
   const int n_tiles = (n + MT - 1) / MT;
 
   TileSched sch(n_tiles);
@@ -390,7 +417,13 @@ __global__ __launch_bounds__(NTHR, MT == 32 ? 2 : 1) void k_node_bwd(int n, MlpW
     __syncthreads();
     f32x4 a[MB][NB], x[MB][NB];
     zero_acc(a);
-    wave_gemm<T, MB, NB, 2 * H, D::LD2>(a, xs, W1, 2 * H, n0);
+    if constexpr (FN) {
+      wave_gemm_lds<MB, NB, 2 * H, D::LD2>(a, (const bf16*)xs, [&](int k, int nb) {
+        return *(const bf16x8*)(W1s + (n0 + 16 * nb + li) * LDW1 + k + 8 * lg);
+      });
+    } else {
+      wave_gemm<T, MB, NB, 2 * H, D::LD2>(a, xs, W1, 2 * H, n0);
+    }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -405,7 +438,13 @@ __global__ __launch_bounds__(NTHR, MT == 32 ? 2 : 1) void k_node_bwd(int n, MlpW
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
     __syncthreads();
     zero_acc(x);
-    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2, H, n0);
+    if constexpr (FN) {
+      wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)zs, [&](int k, int nb) {
+        return *(const bf16x8*)(W2s + (n0 + 16 * nb + li) * LDW2 + k + 8 * lg);
+      });
+    } else {
+      wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2, H, n0);
+    }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -417,7 +456,7 @@ __global__ __launch_bounds__(NTHR, MT == 32 ? 2 : 1) void k_node_bwd(int n, MlpW
     float inv[MB][4];
     ln_normalize<MB, NB, MT, H>(x, red, eps, inv);
     f32_rows_to_lds<H, D::LDF, MT>(ft, nr, [&](int i, int q) { return *(const float4*)(dh_in + (size_t)(row0 + i) * H + 4 * q); });
-    lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z + (size_t)row0 * H, H, [](int i) { return i; });
+    if constexpr (!FN) lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z + (size_t)row0 * H, H, [](int i) { return i; });
     __syncthreads();
     f32x4 g[MB][NB];
 #pragma unroll
@@ -428,11 +467,21 @@ __global__ __launch_bounds__(NTHR, MT == 32 ? 2 : 1) void k_node_bwd(int n, MlpW
         for (int r = 0; r < 4; ++r) g[mb][nb][r] = ft[acc_row(mb, r) * D::LDF + acc_col(n0, nb)];
     ln_backward<MB, NB, MT, H>(x, g, inv, w.gamma, n0, red, cg, cbt);
     col_accumulate(g, cb2);
+    if constexpr (FN) {
+      wave_wgrad<MB, NB, H, D::LDH>(accW2, g, (const bf16*)zs);  // dW2 += du^T z
+      __syncthreads();  // every wave is done reading z before du replaces it
+    }
     acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
     __syncthreads();
-    lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.du + (size_t)row0 * H, H, [](int i) { return i; });
     zero_acc(x);
-    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2T, H, n0);
+    if constexpr (FN) {
+      wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)zs, [&](int k, int nb) {
+        return lds_bfrag_tr(W2s, LDW2, k + 8 * lg, n0 + 16 * nb, 4);
+      });
+    } else {
+      lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.du + (size_t)row0 * H, H, [](int i) { return i; });
+      wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W2T, H, n0);
+    }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -445,9 +494,18 @@ __global__ __launch_bounds__(NTHR, MT == 32 ? 2 : 1) void k_node_bwd(int n, MlpW
     __syncthreads();
     lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.da + (size_t)row0 * H, H, [](int i) { return i; });
     zero_acc(g);
-    wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1T, H, n0);            // -> dh part
     zero_acc(x);
-    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W1T + (size_t)H * H, H, n0);  // -> dm
+    if constexpr (FN) {
+      wave_gemm_lds<MB, NB, H, D::LDH>(g, (const bf16*)zs, [&](int k, int nb) {  // -> dh part
+        return lds_bfrag_tr(W1s, LDW1, k + 8 * lg, n0 + 16 * nb, 4);
+      });
+      wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)zs, [&](int k, int nb) {  // -> dm
+        return lds_bfrag_tr(W1s, LDW1, k + 8 * lg, H + n0 + 16 * nb, 4);
+      });
+    } else {
+      wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1T, H, n0);                  // -> dh part
+      wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W1T + (size_t)H * H, H, n0);  // -> dm
+    }
     acc_to_ldsf<MB, NB, D::LDF>(g, ft, n0);
     __syncthreads();
     f32_tile<MT, H, NTHR>(
@@ -473,11 +531,20 @@ __global__ __launch_bounds__(NTHR, MT == 32 ? 2 : 1) void k_node_bwd(int n, MlpW
   write_partial<NB>(p + H, n0, cb2);
   write_partial<NB>(p + 2 * H, n0, cg);
   write_partial<NB>(p + 3 * H, n0, cbt);
+  if constexpr (FN) {
+    float* q2 = o.wpart + (size_t)blockIdx.x * H * H;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int jb = 0; jb < H / 16; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) q2[(n0 + nb * 16 + lg * 4 + r) * H + jb * 16 + li] = accW2[nb][jb][r];
+  }
 }
 
 // dh_out = dh_mid + [S_r | S_s] B_rs^T, B_rs = [W1_r^T | W1_s^T] ([H][2H]).
 template <typename T, int H, int MT>
-__global__ __launch_bounds__(NTHR, 2) void k_node_dh(int n, const T* __restrict__ Brs, const float* __restrict__ dh_mid,
+__global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_node_dh(int n, const T* __restrict__ Brs, const float* __restrict__ dh_mid,
                                                   const float* __restrict__ S_r, const float* __restrict__ S_s,
                                                   float* __restrict__ dh_out) {
   using D = BD<T, H>;
@@ -552,7 +619,7 @@ __global__ __launch_bounds__(NTHR) void k_sender_sum(int n, const int* __restric
 // da1, dh = W1^T da1.  Writes the factors of the weight gradients.
 // ---------------------------------------------------------------------------
 template <typename T, int H, int MT, int ACT>
-__global__ __launch_bounds__(NTHR, 2) void k_dec_bwd(BatchView b, MlpW w, const T* __restrict__ h,
+__global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_bwd(BatchView b, MlpW w, const T* __restrict__ h,
                                                   const float* __restrict__ d_out, int out_dim, DecBwdOut o) {
   using D = BD<T, H>;
   constexpr int MB = MT / 16, NB = D::NB;

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
 // Node processor, forward (Eq. 3): h' = h + LN(W2 act(W1 [h ; m] + b1) + b2)
 // ---------------------------------------------------------------------------
 template <typename T, int H, int MT, int ACT>
-__global__ __launch_bounds__(NTHR, 2) void k_node_fwd(int n, MlpW w, const T* __restrict__ h,
+__global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_node_fwd(int n, MlpW w, const T* __restrict__ h,
                                                    const float* __restrict__ m, T* __restrict__ h_out,
                                                    float eps) {
   using D = Dims<T, H>;
@@ -238,7 +238,7 @@ void launch_edge_feat(const BatchView& b, const float* pos, EdgeNorm en, float* 
 }
 
 template <typename T, int H, int MT, int ACT, int KIND>
-__global__ __launch_bounds__(NTHR, 2) void k_enc_fwd(int rows, BatchView b, MlpW w, const float* __restrict__ src,
+__global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_enc_fwd(int rows, BatchView b, MlpW w, const float* __restrict__ src,
                                                   int in_dim, T* __restrict__ out, float eps) {
   using D = Dims<T, H>;
   constexpr int MB = MT / 16, NB = D::NB;
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(NTHR, 2) void k_enc_fwd(int rows, BatchView b, MlpW
 // written to out[gid][0:out_dim].  The last layer (out_dim <= 16) is FMA.
 // ---------------------------------------------------------------------------
 template <typename T, int H, int MT, int ACT>
-__global__ __launch_bounds__(NTHR, 2) void k_dec_fwd(BatchView b, MlpW w, const T* __restrict__ h,
+__global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_fwd(BatchView b, MlpW w, const T* __restrict__ h,
                                                   float* __restrict__ out, int out_dim) {
   using D = Dims<T, H>;
   constexpr int MB = MT / 16, NB = D::NB;

@@ -262,3 +262,22 @@ def test_deterministic(api, ctx):
     a = gpu_step(api, ctx, case, ps, [0])
     b = gpu_step(api, ctx, case, ps, [0])
     assert (a[0] == b[0]).all() and (a[2] == b[2]).all() and a[1] == b[1]
+
+
+def test_partset_freed_and_replaced(api, ctx):
+    """A context caches the plan of its last batch.  A partition set freed and
+    another one created in its place (the allocator hands back the freed
+    chunk) must not be mistaken for the old one: each forward matches the
+    oracle of its own graph."""
+    small = Case(1, levels=(800,), layers=2, precision="fp32")
+    big = Case(3, levels=(500, 2000, 6000), layers=2, precision="fp32")
+    for case in (small, big, small, big):
+        g = gpu_graph(api, ctx, case)
+        ps = api.Partset.halo(g, case.inp.pos, None, case.L)
+        out, _, _ = gpu_step(api, ctx, case, ps, [0])
+        y = om.forward(case.desc, case.params.astype(np.float64), case.oracle_graph(), case.inp.node_in,
+                       case.inp.pos, case.inp.edge_norm)
+        err = rel_l2(out, y)
+        log(f"  N={case.N}: rel-L2 {err:.2e}")
+        assert err <= 1e-4
+        del ps, g  # freed before the next set is created
