@@ -310,6 +310,7 @@ def main():
     line["tiles"] = {p: (dict(zip(["edge_rows", "node_rows", "grid", "edge_waves"], r["tiles"][:4]))
                          if r["tiles"] else None) for p, r in results.items()}
     line["kernels_ms"] = {p: {k: round(v[0], 3) for k, v in r["kernels"].items()} for p, r in results.items()}
+    line["device_workspace_gb"] = {p: round(r["mem"] / 1e9, 2) for p, r in results.items()}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(WORKLOADS[args.workload], L, H)
