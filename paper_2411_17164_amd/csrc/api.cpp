@@ -1005,8 +1005,11 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   const bool fw = edge_bwd_fuses_wgrad(s);
   Shape se = s;
   if (fw) se.grid = std::min(s.grid, 512);
-  if (fw || enc_bwd_fuses_wgrad(s))
-    if (xmgn_status r = c->wfused.ensure((size_t)std::max(se.grid, std::min(s.grid, 256)) * 2 * H * H * 4)) return r;
+  if (fw || enc_bwd_fuses_wgrad(s) || node_bwd_fuses_wgrad(s)) {
+    // edge adjoint: [se.grid][2][H][H]; encoders: [<=256][2][H][H]; node adjoint: [<=256][3][H][H]
+    const size_t mats = std::max((size_t)se.grid * 2, (size_t)std::min(s.grid, 256) * 3);
+    if (xmgn_status r = c->wfused.ensure(mats * H * H * 4)) return r;
+  }
   if (xmgn_status r = c->redtmp.ensure(reduce_tmp_floats((int)std::max<size_t>(H * H, 16 * H)) * 4)) return r;
   float* rt = c->redtmp.as<float>();
   float* part = c->part.as<float>();
@@ -1044,14 +1047,18 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     VecSeg ns[4] = {{0, (int)H, P(3, l, 1)}, {(int)H, (int)H, P(3, l, 3)}, {2 * (int)H, (int)H, P(3, l, 4)},
                     {3 * (int)H, (int)H, P(3, l, 5)}};
     launch_vec_reduce(part, snode.grid, 4 * (int)H, ns, 4, rt, st);
-    wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 0),
-                 2 * (int)H), c->wpart, st);
-    wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, mslot(c, d, l), 1, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
-                 P(3, l, 0) + H, 2 * (int)H), c->wpart, st);
     if (fnode) {
       KT("wgrad");
-      launch_wgrad_reduce(c->wfused.as<float>(), snode.grid, (int)H, (int)H, P(3, l, 2), (int)H, (int)(H * H), rt, st);
+      const int MN3 = 3 * (int)(H * H);
+      float* wf = c->wfused.as<float>();
+      launch_wgrad_reduce(wf, snode.grid, (int)H, (int)H, P(3, l, 2), (int)H, MN3, rt, st);
+      launch_wgrad_reduce(wf + H * H, snode.grid, (int)H, (int)H, P(3, l, 0), 2 * (int)H, MN3, rt, st);
+      launch_wgrad_reduce(wf + 2 * H * H, snode.grid, (int)H, (int)H, P(3, l, 0) + H, 2 * (int)H, MN3, rt, st);
     } else {
+      wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 0),
+                   2 * (int)H), c->wpart, st);
+      wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, mslot(c, d, l), 1, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
+                   P(3, l, 0) + H, 2 * (int)H), c->wpart, st);
       wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, c->fc.p, 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
                    P(3, l, 2), (int)H), c->wpart, st);
     }
