@@ -482,6 +482,8 @@ struct xmgn_ctx {
   // backward workspace
   DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, wfused, redtmp, lossp;
   DBuf xe;  // edge features of the forward [E][4]
+  DBuf zt;  // hidden activations of the edge MLPs [L][E][H] (edge_z_tape forms, full tape)
+  bool tape_z = false;
   // per-kernel timing
   bool timing = false;
   std::vector<std::string> tnames;
@@ -639,7 +641,7 @@ extern "C" xmgn_status xmgn_ctx_memory(const xmgn_ctx* c, int64_t* bytes) {
   if (!c || !bytes) return fail(XMGN_ERR_INVALID, "NULL argument");
   const DBuf* bufs[] = {&c->batch.ints, &c->jobs_dev, &c->blob, &c->h, &c->e, &c->m, &c->dhA, &c->dhMid,
                         &c->dm, &c->Sr, &c->Ss, &c->deA, &c->deB, &c->fa, &c->fb, &c->fc, &c->fd,
-                        &c->dy, &c->part, &c->wpart, &c->wfused, &c->redtmp, &c->lossp, &c->xe};
+                        &c->dy, &c->part, &c->wpart, &c->wfused, &c->redtmp, &c->lossp, &c->xe, &c->zt};
   int64_t t = 0;
   for (const DBuf* b : bufs) t += (int64_t)b->bytes;
   *bytes = t;
@@ -838,13 +840,16 @@ static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32
   return XMGN_OK;
 }
 
-static xmgn_status ensure_tape(xmgn_ctx* c, const xmgn_model_desc* d, bool full) {
+static xmgn_status ensure_tape(xmgn_ctx* c, const xmgn_model_desc* d, bool full, bool z) {
   const size_t ts = tsize(d), H = d->hidden, L = d->n_layers;
   const size_t n = c->batch.n, E = c->batch.E;
   const size_t sh = full ? L + 1 : 2, se = full ? L : 2, sm = full ? L : 1;
   if (xmgn_status s = c->h.ensure(sh * n * H * ts)) return s;
   if (xmgn_status s = c->e.ensure(se * E * H * ts)) return s;
   if (xmgn_status s = c->m.ensure(sm * n * H * 4)) return s;
+  c->tape_z = full && z;
+  if (c->tape_z)
+    if (xmgn_status s = c->zt.ensure(L * E * H * ts)) return s;
   c->tape_slots_h = (int)sh;
   c->tape_slots_e = (int)se;
   c->tape_slots_m = (int)sm;
@@ -859,6 +864,10 @@ static void* hslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
 static void* eslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   const size_t s = c->tape_full ? l : l % 2;
   return (char*)c->e.p + s * c->batch.E * d->hidden * tsize(d);
+}
+static void* zslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
+  if (!c->tape_z) return nullptr;
+  return (char*)c->zt.p + (size_t)l * c->batch.E * d->hidden * tsize(d);
 }
 static float* mslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   const size_t s = c->tape_full ? l : 0;
@@ -894,7 +903,7 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
   const Shape s = make_shape(c, d);
   if (xmgn_status r = ensure_batch(c, ps, part_ids, n_batch, s.mt_edge)) return r;
   if (xmgn_status r = ensure_wplan(c, d)) return r;
-  if (xmgn_status r = ensure_tape(c, d, keep_tape != 0)) return r;
+  if (xmgn_status r = ensure_tape(c, d, keep_tape != 0, edge_z_tape(s))) return r;
   const BatchView& b = c->batch.view;
   const int L = d->n_layers;
   g_config_error = 0;
@@ -905,7 +914,7 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
   { KT("enc_edge_fwd"); launch_enc_edge_fwd(s, b, weights(c, d, params, 1, 1, 0), c->xe.as<float>(), eslot(c, d, 0), st); }
   for (int l = 0; l < L; ++l) {
     { KT("edge_fwd"); launch_edge_fwd(s, b, weights(c, d, params, 2 + 2 * l, 2, l), hslot(c, d, l), eslot(c, d, l),
-                    l + 1 < L ? eslot(c, d, l + 1) : nullptr, mslot(c, d, l), st); }
+                    l + 1 < L ? eslot(c, d, l + 1) : nullptr, mslot(c, d, l), zslot(c, d, l), st); }
     { KT("node_fwd"); launch_node_fwd(s, b, weights(c, d, params, 3 + 2 * l, 3, l), hslot(c, d, l), mslot(c, d, l), hslot(c, d, l + 1),
                     st); }
   }
@@ -1066,7 +1075,11 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     const MlpW we = weights(c, d, params, 2 + 2 * l, 2, l);
     EdgeBwdOut eo{de_out->as<float>(), c->Sr.as<float>(), c->fa.p, c->fb.p, c->fc.p, part,
                   fw ? c->wfused.as<float>() : nullptr};
-    { KT("edge_bwd"); launch_edge_bwd(se, b, we, hl(l), eslot(c, d, l), de_in, c->dm.as<float>(), eo, st); }
+    {
+      KT("edge_bwd");
+      const void* zt = edge_z_tape(se) ? zslot(c, d, l) : nullptr;  // the forward's z, when it kept it
+      launch_edge_bwd(se, b, we, hl(l), eslot(c, d, l), zt, de_in, c->dm.as<float>(), eo, st);
+    }
     VecSeg es[4] = {{0, (int)H, P(2, l, 1)}, {(int)H, (int)H, P(2, l, 3)}, {2 * (int)H, (int)H, P(2, l, 4)},
                     {3 * (int)H, (int)H, P(2, l, 5)}};
     launch_vec_reduce(part, se.grid, 4 * (int)H, es, 4, rt, st);

@@ -35,10 +35,12 @@ struct EdgeFwdLds {
   static constexpr size_t bytes = XS + ZS + 2 * NW * MT * 4 + 2 * MT * 4;
 };
 
+// z_out (or NULL): the hidden activation z = act(W1 x + b1) of every edge,
+// kept for the adjoint.
 template <typename T, int H, int MT, int ACT, int AGG, int NW>
 __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::bytes, NW)) void k_edge_fwd(
     BatchView b, MlpW w, const T* __restrict__ h, const T* __restrict__ e, T* __restrict__ e_out,
-    float* __restrict__ m, float eps) {
+    float* __restrict__ m, T* __restrict__ z_out, float eps) {
   using D = Dims<T, H, NW>;
   using L = EdgeFwdLds<T, H, MT, NW>;
   constexpr int MB = MT / 16, NB = D::NB;
@@ -91,6 +93,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
       }
     acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
     __syncthreads();
+    if (z_out) lds_rows_to_global<T, D::LDH>(zs, ne, H, z_out + (size_t)e0 * H, H, [](int i) { return i; });
 
     zero_acc(acc);
     wave_gemm<T, MB, NB, H, D::LDH>(acc, zs, W2, H, n0);
@@ -440,15 +443,15 @@ constexpr bool edge_fits() {
 
 template <int NW>
 static void edge_fwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e, void* e_out,
-                        float* m, hipStream_t st) {
+                        float* m, void* z_out, hipStream_t st) {
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
     if constexpr (edge_fits<T, H, MT>()) {
       if (s.agg)
         k_edge_fwd<T, H, MT, ACT, 1, NW><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m,
-                                                                     s.eps);
+                                                                     (T*)z_out, s.eps);
       else
         k_edge_fwd<T, H, MT, ACT, 0, NW><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m,
-                                                                     s.eps);
+                                                                     (T*)z_out, s.eps);
     } else {
       g_config_error = 1;
     }
@@ -456,12 +459,12 @@ static void edge_fwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const
 }
 
 void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
-                     void* e_out, float* m, hipStream_t st) {
+                     void* e_out, float* m, void* z_out, hipStream_t st) {
   if (b.n_etiles == 0) return;
   if (s.nw_edge == 8)
-    edge_fwd_nw<8>(s, b, w, h, e, e_out, m, st);
+    edge_fwd_nw<8>(s, b, w, h, e, e_out, m, z_out, st);
   else
-    edge_fwd_nw<4>(s, b, w, h, e, e_out, m, st);
+    edge_fwd_nw<4>(s, b, w, h, e, e_out, m, z_out, st);
 }
 
 void launch_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const float* m,
