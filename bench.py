@@ -43,21 +43,25 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: bool = False, de_in: float = 1.0) -> float | None:
+def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: bool = False, de_in: float = 1.0,
+                 ztape: bool = False) -> float | None:
     """Algorithmic HBM bytes of one launch of a processor kernel: each input
     read once, each output written once (s = bytes per stored latent; FP32
     adjoints are 4 bytes).  `fused`: the edge adjoint accumulates dW2 and the
     e-block of dW1 itself, so z and du are not written.  `de_in`: fraction of
-    launches that read an incoming edge adjoint de' (all but the last layer)."""
+    launches that read an incoming edge adjoint de' (all but the last layer).
+    `ztape`: the forward writes z for the adjoint, which reads it instead of
+    h_s and h_r."""
     if name == "edge_fwd":
-        # per edge: e and the gathered h_s read, e' written; per receiver:
-        # h_r read, m (FP32) written
-        return E * 3 * H * s + n * (H * s + 4 * H)
+        # per edge: e and the gathered h_s read, e' (and z) written; per
+        # receiver: h_r read, m (FP32) written
+        return E * (3 + (1 if ztape else 0)) * H * s + n * (H * s + 4 * H)
     if name == "edge_bwd":
-        # per edge: h_s, e, de' (FP32) read; de (FP32), da written (+ z, du
-        # when not fused); per receiver: h_r, dm (FP32) read, S_r (FP32) written
+        # per edge: h_s (or z), e, de' (FP32) read; de (FP32), da written
+        # (+ z, du when not fused); per receiver: h_r (not with ztape), dm
+        # (FP32) read, S_r (FP32) written
         per_edge = (2 + 1 + (0 if fused else 2)) * H * s + 4 * H * (1 + de_in)
-        return E * per_edge + n * (H * s + 8 * H)
+        return E * per_edge + n * ((0 if ztape else H * s) + 8 * H)
     if name == "node_fwd":
         return n * (2 * H * s + 4 * H)
     if name == "node_bwd":
@@ -65,13 +69,14 @@ def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: bool = False,
     return None
 
 
-def kernel_flops(name: str, n: int, E: int, H: int, fused: bool = False) -> float | None:
+def kernel_flops(name: str, n: int, E: int, H: int, fused: bool = False, ztape: bool = False) -> float | None:
     """Dense multiply-add flops of one launch (2 per MAC)."""
     if name == "edge_fwd":
         return E * 8.0 * H * H
     if name == "edge_bwd":
-        # recompute (3H x H, H x H), W2^T du, W1e^T da; fused: du^T z, da^T e
-        return E * (16.0 if fused else 12.0) * H * H
+        # recompute (3H x H unless z is on the tape, H x H), W2^T du, W1e^T da;
+        # fused: du^T z, da^T e
+        return E * ((16.0 if fused else 12.0) - (6.0 if ztape else 0.0)) * H * H
     if name == "node_fwd":
         return n * 6.0 * H * H
     if name == "node_bwd":
@@ -262,14 +267,15 @@ def main():
     # dominant kernel of the BF16 step and its roofline
     kern = bf["kernels"]
     fused = H == 128  # the BF16 edge adjoint fuses its weight gradients at H = 128
+    ztape = fused  # ... and, with ReLU, reads z from the forward's tape
     de_in = (L - 1) / L
-    kb = lambda k, n_w, e_w: kernel_bytes(k, n_w, e_w, H, 2, fused, de_in)  # noqa: E731
+    kb = lambda k, n_w, e_w: kernel_bytes(k, n_w, e_w, H, 2, fused, de_in, ztape)  # noqa: E731
     dom = max((k for k in kern if kb(k, N, E) is not None), key=lambda k: kern[k][0])
     avg_ms = kern[dom][0] / kern[dom][1]
     # launches of a processor kernel per step: L per wave (edge/node kernels)
     per_step = kern[dom][1]
     tot_bytes = sum(kb(dom, n_w, e_w) for n_w, e_w in wave_sizes) * per_step / len(waves)
-    tot_flops = sum(kernel_flops(dom, n_w, e_w, H, fused) for n_w, e_w in wave_sizes) * per_step / len(waves)
+    tot_flops = sum(kernel_flops(dom, n_w, e_w, H, fused, ztape) for n_w, e_w in wave_sizes) * per_step / len(waves)
     by = tot_bytes / per_step
     fl = tot_flops / per_step
     achieved = by / (avg_ms * 1e-3) / 1e9
