@@ -162,6 +162,28 @@ def test_fwd_bwd_15_layers(api, ctx, precision, tol, act):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 2e-2)])
+@pytest.mark.parametrize("act", ["relu", "silu"])
+def test_fwd_bwd_h256_car(api, ctx, precision, tol, act):
+    """H = 256, the width of the 4M-point car recipe, on that recipe at
+    reduced size: the H = 256 kernel variants (32-row edge tiles, weight
+    gradients as separate products, weight fragments loaded inside the k
+    loop) against the FP64 oracle."""
+    case = Case(5, levels=(400, 1600, 5000), layers=3, precision=precision, activation=act)
+    assert case.H == 256
+    log(f"fwd+bwd H=256 car {precision} {act} levels={case.levels}")
+    g = gpu_graph(api, ctx, case)
+    ps = api.Partset.halo(g, case.inp.pos, None, case.L)
+    out, loss, grad = gpu_step(api, ctx, case, ps, [0])
+    loss_r, y_r, g_r = om.step_full(case.desc, case.params.astype(np.float64), case.oracle_graph(),
+                                    case.inp.node_in, case.inp.pos, case.inp.edge_norm, case.inp.targets)
+    e_out = rel_l2(out, y_r)
+    assert e_out <= tol
+    assert abs(loss - loss_r) <= tol * loss_r
+    worst, total = check_grads(case, grad, g_r, precision, act)
+    log(f"  out {e_out:.2e} loss {abs(loss - loss_r) / loss_r:.2e} grad total {total:.2e} worst {worst[:2]}")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 2e-2)])
 @pytest.mark.parametrize("edge_rows,edge_waves", [(32, 8), (64, 8), (32, 4)])
 def test_tile_configs(api, precision, tol, edge_rows, edge_waves):
     """Every tile / wave configuration the autotuner may pick meets the bound.
@@ -202,9 +224,12 @@ def test_fwd_bwd_silu_fp32(api, ctx):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_partitions_equal_full_graph(api, ctx, precision):
-    case = Case(4, levels=(500, 2000, 8000), layers=3, precision=precision)
-    log(f"partitions {precision}")
+@pytest.mark.parametrize("cfg", [4, 5])
+def test_partitions_equal_full_graph(api, ctx, precision, cfg):
+    """Halo partitions (the 1M-point ellipsoid recipe at H = 128 and the car
+    recipe at H = 256, both reduced) against the full graph."""
+    case = Case(cfg, levels=(500, 2000, 8000), layers=3, precision=precision)
+    log(f"partitions cfg={cfg} H={case.H} {precision}")
     g = gpu_graph(api, ctx, case)
     full = api.Partset.halo(g, case.inp.pos, None, case.L)
     y_full, loss_full, g_full = gpu_step(api, ctx, case, full, [0])
