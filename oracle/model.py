@@ -23,6 +23,13 @@ Loss (Sec. II.E, III.D): mean squared error over inner nodes only, with the
 global normaliser N_total * out_dim so that the partition losses add up to
 the full-graph loss; halo rows are excluded.
 
+BF16 form (training in bfloat16 with automatic mixed precision, Sec. V.D):
+the products over the hidden width take bfloat16 copies of their weights,
+and the gradient of the cast is passed through unchanged.  amp_cast gives
+the parameters such a form multiplies with; the oracle run at them is the
+exact counterpart of the BF16 form's arithmetic, while the run at the FP32
+master weights is the model itself.
+
 Parameter blob (float32 master, flat, this order; W stored [out][in]):
   node encoder  W1[H][6]  b1[H]  W2[H][H]  b2[H]  W3[H][H]  b3[H]  g[H]  be[H]
   edge encoder  W1[H][4]  b1[H]  W2[H][H]  b2[H]  W3[H][H]  b3[H]  g[H]  be[H]
@@ -105,6 +112,35 @@ def pack(d: Desc, grads: dict) -> np.ndarray:
     for b in names:
         parts.extend(x.reshape(-1) for x in grads[b])
     return np.concatenate(parts)
+
+
+def bf16_round(x) -> np.ndarray:
+    """Each value of x, taken as float32, rounded to the nearest bfloat16
+    (sign, 8 exponent bits and 7 stored significand bits: the upper half of
+    the float32 bit pattern), ties to the even significand; as float64."""
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    if not np.isfinite(f).all():
+        raise ValueError("bf16_round takes finite values")
+    u = f.view(np.uint32).astype(np.uint64)
+    odd = (u >> 16) & 1
+    r = ((u + 0x7FFF + odd) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(x))
+
+
+def amp_cast(d: Desc, blob) -> np.ndarray:
+    """The parameter blob with every hidden-to-hidden weight (both dimensions
+    at least H: the encoders' second and third layers, the processor MLPs and
+    the decoder's first two layers) rounded to bfloat16.  The encoders' input
+    layers (6 and 4 inputs), the decoder's output layer, the biases and the
+    LayerNorm affines stay float32."""
+    out = np.asarray(blob, dtype=np.float64).copy()
+    off = 0
+    for _, kind, shape in layout(d):
+        cnt = int(np.prod(shape))
+        if kind == "weight" and min(shape) >= d.hidden:
+            out[off:off + cnt] = bf16_round(out[off:off + cnt])
+        off += cnt
+    return out
 
 
 # --- elementwise pieces -----------------------------------------------------

@@ -65,3 +65,59 @@ class Case:
 def per_tensor_errors(case: Case, got, ref):
     """rel-L2 of every parameter tensor's gradient."""
     return {name: rel_l2(got[sl], ref[sl]) for name, sl in case.tensor_slices()}
+
+
+def oracle_refs(case: Case, G=None):
+    """FP64 oracle steps on the whole graph: at the FP32 master weights and,
+    for the BF16 form, also at the weights that form multiplies with
+    (hidden-to-hidden weights cast to bfloat16, as mixed-precision training
+    does).  Returns (base, amp); amp is None for FP32."""
+    G = case.oracle_graph() if G is None else G
+    args = (G, case.inp.node_in, case.inp.pos, case.inp.edge_norm, case.inp.targets)
+    base = om.step_full(case.desc, case.params.astype(np.float64), *args)
+    amp = om.step_full(case.desc, om.amp_cast(case.desc, case.params), *args) if case.precision == "bf16" else None
+    return base, amp
+
+
+def check_step(case: Case, out, loss, grad, refs) -> str:
+    """The parity bar for one forward + backward; returns a summary line.
+
+    FP32: outputs and loss <= 1e-4 relative.  Gradients: 1e-4 per tensor
+    under SiLU; under ReLU the derivative is a 0/1 decision on the sign of a
+    pre-activation and FP32-sized (1e-7) perturbations of the FP64 oracle
+    itself move single tensors by ~1e-4 (a kink flips), so there the whole
+    gradient is held to 1e-4 and each tensor to 1e-3.
+
+    BF16: against the oracle at the cast weights (the arithmetic the form
+    performs) every output and every gradient tensor <= 2e-2; against the
+    oracle at the FP32 master weights (the model) the outputs, the loss and
+    the whole gradient <= 2e-2, with the worst tensor reported.  The cast
+    alone moves the deepest gradient tensors (encoder input layers and
+    first-layer biases) by up to ~2.3e-2 at 5 layers."""
+    (loss_r, y_r, g_r), amp = refs
+    assert np.isfinite(out).all() and np.isfinite(grad).all()
+    errs = per_tensor_errors(case, grad, g_r)
+    worst = sorted(errs.items(), key=lambda kv: -kv[1])[:2]
+    total = rel_l2(grad, g_r)
+    e_out = rel_l2(out, y_r)
+    e_loss = abs(loss - loss_r) / loss_r
+    if case.precision == "fp32":
+        assert e_out <= 1e-4, e_out
+        assert e_loss <= 1e-4, e_loss
+        if case.activation == "silu":
+            assert worst[0][1] <= 1e-4, worst
+        else:
+            assert total <= 1e-4, (total, worst)
+            assert worst[0][1] <= 1e-3, worst
+        return f"out {e_out:.2e} loss {e_loss:.2e} grad {total:.2e} worst {worst}"
+    loss_a, y_a, g_a = amp
+    assert e_out <= 2e-2, e_out
+    assert e_loss <= 2e-2, e_loss
+    assert total <= 2e-2, (total, worst)
+    errs_a = per_tensor_errors(case, grad, g_a)
+    worst_a = sorted(errs_a.items(), key=lambda kv: -kv[1])[:2]
+    e_out_a = rel_l2(out, y_a)
+    assert e_out_a <= 2e-2, e_out_a
+    assert worst_a[0][1] <= 2e-2, worst_a
+    return (f"vs model: out {e_out:.2e} loss {e_loss:.2e} grad {total:.2e} worst {worst} | "
+            f"vs cast weights: out {e_out_a:.2e} grad {rel_l2(grad, g_a):.2e} worst {worst_a}")

@@ -1,6 +1,7 @@
 """GPU parity: the HIP library against the FP64 oracle on the same seeded
 inputs.  kNN graphs and partitions are compared bit for bit; outputs and every
-parameter-gradient tensor by relative L2 (FP32 <= 1e-4, BF16 <= 2e-2).
+parameter-gradient tensor by relative L2 (FP32 <= 1e-4; BF16 <= 2e-2, the
+bar spelled out in cases.check_step).
 
 Sizes follow the workload recipes at reduced point counts that still span
 many tiles and a ragged last tile; the full-size cases sample outputs through
@@ -8,7 +9,7 @@ their L-hop in-cones (see test_gpu_fullsize.py)."""
 import numpy as np
 import pytest
 
-from cases import Case, log, per_tensor_errors, rel_l2
+from cases import Case, check_step, log, oracle_refs, per_tensor_errors, rel_l2
 from oracle import model as om
 from oracle import partition as opart
 
@@ -102,31 +103,10 @@ def test_forward_fp32_sphere_2k(api, ctx):
     assert err <= 1e-4
 
 
-# Gradient bounds.  FP32: 1e-4 per parameter tensor where the problem is well
-# conditioned (SiLU).  With ReLU, the derivative is a 0/1 decision on the sign
-# of a pre-activation, and FP32-sized (1e-7) perturbations of the FP64 oracle
-# itself move single small-row-count tensors by ~1e-4 (a kink flips), so
-# under ReLU the FP32 bound applies to the outputs and to the whole gradient,
-# and single tensors are held to 1e-3.  BF16: 2e-2 per tensor for both.
-def check_grads(case, grad, g_r, precision, activation):
-    errs = per_tensor_errors(case, grad, g_r)
-    worst = sorted(errs.items(), key=lambda kv: -kv[1])[:4]
-    total = rel_l2(grad, g_r)
-    assert np.isfinite(grad).all()
-    if precision == "bf16":
-        assert worst[0][1] <= 2e-2, worst
-    elif activation == "silu":
-        assert worst[0][1] <= 1e-4, worst
-    else:
-        assert total <= 1e-4, (total, worst)
-        assert worst[0][1] <= 1e-3, worst
-    return worst, total
-
-
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 2e-2)])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("agg", ["message", "edge"])
 @pytest.mark.parametrize("act", ["relu", "silu"])
-def test_fwd_bwd_multiscale(api, ctx, precision, tol, agg, act):
+def test_fwd_bwd_multiscale(api, ctx, precision, agg, act):
     """3-level bumpy ellipsoid (reduced), H = 128, 4 layers: outputs, loss and
     every gradient tensor against the FP64 oracle."""
     case = Case(3, levels=(500, 2000, 6000), layers=4, precision=precision, aggregate=agg, activation=act)
@@ -134,19 +114,27 @@ def test_fwd_bwd_multiscale(api, ctx, precision, tol, agg, act):
     g = gpu_graph(api, ctx, case)
     ps = api.Partset.halo(g, case.inp.pos, None, case.L)
     out, loss, grad = gpu_step(api, ctx, case, ps, [0])
-    G = case.oracle_graph()
-    loss_r, y_r, g_r = om.step_full(case.desc, case.params.astype(np.float64), G, case.inp.node_in, case.inp.pos,
-                                    case.inp.edge_norm, case.inp.targets)
-    e_out = rel_l2(out, y_r)
-    assert e_out <= tol
-    assert abs(loss - loss_r) <= tol * loss_r
-    worst, total = check_grads(case, grad, g_r, precision, act)
-    log(f"  out {e_out:.2e} loss {abs(loss - loss_r) / loss_r:.2e} grad total {total:.2e} worst {worst[:2]}")
+    log("  " + check_step(case, out, loss, grad, oracle_refs(case)))
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 2e-2)])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("layers", [5, 6])
+def test_fwd_bwd_depths(api, ctx, precision, layers):
+    """Depths next to the 4-layer case, ReLU: at 5 layers the bfloat16 cast
+    of the weights alone moves the edge encoder's first-layer bias gradient
+    by 2.3e-2 from the model's, so the BF16 bar separates the form's
+    arithmetic (oracle at the cast weights) from the model."""
+    case = Case(3, levels=(500, 2000, 6000), layers=layers, precision=precision)
+    log(f"fwd+bwd {precision} L={layers}")
+    g = gpu_graph(api, ctx, case)
+    ps = api.Partset.halo(g, case.inp.pos, None, case.L)
+    out, loss, grad = gpu_step(api, ctx, case, ps, [0])
+    log("  " + check_step(case, out, loss, grad, oracle_refs(case)))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("act", ["relu", "silu"])
-def test_fwd_bwd_15_layers(api, ctx, precision, tol, act):
+def test_fwd_bwd_15_layers(api, ctx, precision, act):
     """Full depth (15 layers) on the multi-scale recipe at reduced size: the
     error budget has to hold through every layer, forward and back."""
     case = Case(3, levels=(250, 1000, 4000), layers=15, precision=precision, activation=act)
@@ -154,16 +142,12 @@ def test_fwd_bwd_15_layers(api, ctx, precision, tol, act):
     g = gpu_graph(api, ctx, case)
     ps = api.Partset.halo(g, case.inp.pos, None, case.L)
     out, loss, grad = gpu_step(api, ctx, case, ps, [0])
-    loss_r, y_r, g_r = om.step_full(case.desc, case.params.astype(np.float64), case.oracle_graph(),
-                                    case.inp.node_in, case.inp.pos, case.inp.edge_norm, case.inp.targets)
-    assert rel_l2(out, y_r) <= tol
-    worst, total = check_grads(case, grad, g_r, precision, act)
-    log(f"  out {rel_l2(out, y_r):.2e} loss {abs(loss - loss_r) / loss_r:.2e} grad total {total:.2e} worst {worst}")
+    log("  " + check_step(case, out, loss, grad, oracle_refs(case)))
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 2e-2)])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("act", ["relu", "silu"])
-def test_fwd_bwd_h256_car(api, ctx, precision, tol, act):
+def test_fwd_bwd_h256_car(api, ctx, precision, act):
     """H = 256, the width of the 4M-point car recipe, on that recipe at
     reduced size: the H = 256 kernel variants (32-row edge tiles, weight
     gradients as separate products, weight fragments loaded inside the k
@@ -174,18 +158,12 @@ def test_fwd_bwd_h256_car(api, ctx, precision, tol, act):
     g = gpu_graph(api, ctx, case)
     ps = api.Partset.halo(g, case.inp.pos, None, case.L)
     out, loss, grad = gpu_step(api, ctx, case, ps, [0])
-    loss_r, y_r, g_r = om.step_full(case.desc, case.params.astype(np.float64), case.oracle_graph(),
-                                    case.inp.node_in, case.inp.pos, case.inp.edge_norm, case.inp.targets)
-    e_out = rel_l2(out, y_r)
-    assert e_out <= tol
-    assert abs(loss - loss_r) <= tol * loss_r
-    worst, total = check_grads(case, grad, g_r, precision, act)
-    log(f"  out {e_out:.2e} loss {abs(loss - loss_r) / loss_r:.2e} grad total {total:.2e} worst {worst[:2]}")
+    log("  " + check_step(case, out, loss, grad, oracle_refs(case)))
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 2e-2)])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("edge_rows,edge_waves", [(32, 8), (64, 8), (32, 4)])
-def test_tile_configs(api, precision, tol, edge_rows, edge_waves):
+def test_tile_configs(api, precision, edge_rows, edge_waves):
     """Every tile / wave configuration the autotuner may pick meets the bound.
     SiLU keeps the comparison well conditioned: with ReLU, FP32-sized
     perturbations of the FP64 oracle itself move single gradient tensors by
@@ -197,13 +175,7 @@ def test_tile_configs(api, precision, tol, edge_rows, edge_waves):
     g = gpu_graph(api, c, case)
     ps = api.Partset.halo(g, case.inp.pos, None, case.L)
     out, loss, grad = gpu_step(api, c, case, ps, [0])
-    loss_r, y_r, g_r = om.step_full(case.desc, case.params.astype(np.float64), case.oracle_graph(),
-                                    case.inp.node_in, case.inp.pos, case.inp.edge_norm, case.inp.targets)
-    errs = per_tensor_errors(case, grad, g_r)
-    top = sorted(errs.items(), key=lambda kv: -kv[1])[:3]
-    log(f"  tiles {edge_rows}x{edge_waves} {precision}: out {rel_l2(out, y_r):.2e} worst {top}")
-    assert rel_l2(out, y_r) <= tol
-    assert max(errs.values()) <= tol
+    log(f"  tiles {edge_rows}x{edge_waves} {precision}: " + check_step(case, out, loss, grad, oracle_refs(case)))
 
 
 def test_fwd_bwd_silu_fp32(api, ctx):
@@ -212,11 +184,7 @@ def test_fwd_bwd_silu_fp32(api, ctx):
     g = gpu_graph(api, ctx, case)
     ps = api.Partset.halo(g, case.inp.pos, None, case.L)
     out, loss, grad = gpu_step(api, ctx, case, ps, [0])
-    loss_r, y_r, g_r = om.step_full(case.desc, case.params.astype(np.float64), case.oracle_graph(),
-                                    case.inp.node_in, case.inp.pos, case.inp.edge_norm, case.inp.targets)
-    errs = per_tensor_errors(case, grad, g_r)
-    assert rel_l2(out, y_r) <= 1e-4
-    assert max(errs.values()) <= 1e-4, errs
+    log("  " + check_step(case, out, loss, grad, oracle_refs(case)))
 
 
 # --------------------------------------------------------------------------

@@ -143,3 +143,45 @@ def test_loss_excludes_halo_rows():
     loss, dy = om.loss_and_grad(y, t, 2, 10)
     assert loss == pytest.approx((y[:2] ** 2).sum() / 40)
     assert (dy[2] == 0).all() and np.allclose(dy[:2], 2 * y[:2] / 40)
+
+
+def test_bf16_round_against_torch_and_hand_values():
+    """bf16_round agrees with torch's float32 -> bfloat16 conversion (round
+    to nearest, ties to even) on random values, exact ties and values next
+    to ties; and with hand-worked cases near 1."""
+    torch = pytest.importorskip("torch")
+    g = np.random.default_rng(3)
+    x = (g.standard_normal(20000) * np.exp(g.uniform(-30, 30, 20000))).astype(np.float32)
+    bits = g.integers(0, 1 << 16, 5000, dtype=np.uint32) << 16
+    ties = (bits | 0x8000).view(np.float32)           # exactly halfway between two bfloat16 values
+    near = np.concatenate([(bits | 0x7FFF).view(np.float32), (bits | 0x8001).view(np.float32)])
+    for v in (x, ties, near):
+        v = v[np.isfinite(v)]
+        ref = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+        assert (om.bf16_round(v) == ref).all()
+    one = 1.0
+    assert om.bf16_round(np.float32(one + 2.0**-8)) == 1.0                 # tie, even neighbour is 1
+    assert om.bf16_round(np.float32(one + 3 * 2.0**-8)) == one + 2.0**-6   # tie, even neighbour above
+    assert om.bf16_round(np.float32(one + 2.0**-8 + 2.0**-20)) == one + 2.0**-7
+    assert om.bf16_round(np.float32(-3.0)) == -3.0
+    assert om.bf16_round(np.float32(0.0)) == 0.0
+
+
+def test_amp_cast_rounds_only_hidden_products():
+    d = om.Desc(hidden=16, layers=2)
+    blob = init_params(om.param_entries(d), 7).astype(np.float32)
+    c = om.amp_cast(d, blob)
+    assert (om.amp_cast(d, c) == c).all()                                  # idempotent
+    off = 0
+    for b, kind, shape in om.layout(d):
+        n = int(np.prod(shape))
+        a, r = blob[off:off + n].astype(np.float64), c[off:off + n]
+        hidden = kind == "weight" and min(shape) >= d.hidden
+        if hidden:
+            assert (np.abs(r - a) <= 2.0**-8 * np.abs(a)).all()        # unit roundoff of an 8-bit significand
+            assert (r != a).any()
+        else:
+            assert (r == a).all(), (b, kind, shape)
+        off += n
+    names = [(b, s) for b, k, s in om.layout(d) if k == "weight" and min(s) < d.hidden]
+    assert names == [("enc_node", (16, 6)), ("enc_edge", (16, 4)), ("dec", (4, 16))]
