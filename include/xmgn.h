@@ -251,6 +251,30 @@ xmgn_status xmgn_ctx_timing_read(xmgn_ctx* ctx, int32_t i, char* name, int32_t n
 /* Device bytes currently held by the context (tape and workspace). */
 xmgn_status xmgn_ctx_memory(const xmgn_ctx* ctx, int64_t* bytes);
 
+/*
+ * Activation checkpoints offloaded to host memory (Sec. V.F.1).  While
+ * enabled, a forward with keep_tape = 1 keeps on the device only two
+ * rotating slots of the per-layer checkpoints (h^l, e^l, m^l) and copies
+ * each layer's checkpoint into page-locked host memory owned by the context,
+ * on a copy stream of its own, overlapped with the next layer (a layer waits
+ * only for the copies of the layer two before it).  The backward copies
+ * layer l-1's checkpoint back while layer l runs.  The hidden activations of
+ * the edge MLP are never offloaded: the edge adjoint recomputes them.  The
+ * checkpoints of the last two layers stay in their device slots and are not
+ * copied.  Results equal those of the device-resident tape up to the
+ * recomputed hidden activations (bitwise wherever the device-resident tape
+ * recomputes them too).  Enabling or disabling synchronises the device,
+ * frees the current tape (it is re-allocated at its new size by the next
+ * forward) and invalidates the last forward.  The forward completes (on its
+ * stream) only when its host copies have landed; each call's copies stay
+ * ordered with its own stream, so the usual stream rules apply.  Pinned
+ * bytes: ((L+1) n + L E) H s + 4 L n H for a batch of n nodes and E edges,
+ * s = 2 (BF16) or 4 (FP32).
+ */
+xmgn_status xmgn_ctx_set_offload(xmgn_ctx* ctx, int32_t enable);
+/* Page-locked host bytes currently held by the context (the offloaded tape). */
+xmgn_status xmgn_ctx_host_memory(const xmgn_ctx* ctx, int64_t* bytes);
+
 #ifdef __cplusplus
 }
 #endif

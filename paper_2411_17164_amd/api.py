@@ -195,9 +195,20 @@ class Context:
         return out
 
     def memory(self) -> int:
+        """Device bytes held by the context."""
         b = C.c_int64()
         check(lib.xmgn_ctx_memory(self._h, C.byref(b)))
         return b.value
+
+    def host_memory(self) -> int:
+        """Page-locked host bytes held by the context (the offloaded tape)."""
+        b = C.c_int64()
+        check(lib.xmgn_ctx_host_memory(self._h, C.byref(b)))
+        return b.value
+
+    def set_offload(self, enable: bool):
+        """Keep the training tape's checkpoints in host memory (synchronises the device)."""
+        check(lib.xmgn_ctx_set_offload(self._h, 1 if enable else 0))
 
     def build_knn(self, pos: torch.Tensor, level_end, k_intra: int, k_cross: int = 0, stream=None) -> Graph:
         le = _i32(level_end)

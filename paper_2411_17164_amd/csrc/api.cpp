@@ -86,6 +86,35 @@ struct DBuf {
   }
 };
 
+// Page-locked host memory (the offloaded activation tape): grow-only, contents
+// not preserved.
+struct HBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  HBuf() = default;
+  HBuf(const HBuf&) = delete;
+  HBuf& operator=(const HBuf&) = delete;
+  ~HBuf() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  xmgn_status ensure(size_t need) {
+    if (need <= bytes && p) return XMGN_OK;
+    release();
+    size_t b = need > 0 ? need : 16;
+    hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return fail(XMGN_ERR_OOM, "hipHostMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
+    }
+    bytes = b;
+    return XMGN_OK;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // model description and parameter layout
 // ---------------------------------------------------------------------------
@@ -475,10 +504,15 @@ struct xmgn_ctx {
   int64_t blob_elems = 0;
   std::vector<BlockW> bw;  // per block: 0 enc_node, 1 enc_edge, 2+2l edge, 3+2l node, 2+2L dec
   DBuf jobs_dev, blob;
-  // tape
+  // tape: mode 0 = two rolling slots (inference), 1 = every layer on the
+  // device, 2 = every layer in page-locked host memory with two device slots
   DBuf h, e, m;
-  int tape_slots_h = 0, tape_slots_e = 0, tape_slots_m = 0;
-  bool tape_full = false;
+  int tape_mode = 0;
+  bool offload = false;  // keep_tape forwards use mode 2
+  HBuf ht;               // host tape: h [L+1][n][H] | e [L][E][H] | m [L][n][H] FP32
+  hipStream_t cs = nullptr;          // copy stream of the offloaded tape
+  std::vector<hipEvent_t> sev;       // ordering events between st and cs
+  size_t sev_used = 0;
   // backward workspace
   DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, wfused, redtmp, lossp;
   DBuf xe;  // edge features of the forward [E][4]
@@ -580,6 +614,8 @@ extern "C" void xmgn_ctx_destroy(xmgn_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : ctx->tpool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->sev) (void)hipEventDestroy(e);
+  if (ctx->cs) (void)hipStreamDestroy(ctx->cs);
   delete ctx;
 }
 
@@ -645,6 +681,51 @@ extern "C" xmgn_status xmgn_ctx_memory(const xmgn_ctx* c, int64_t* bytes) {
   int64_t t = 0;
   for (const DBuf* b : bufs) t += (int64_t)b->bytes;
   *bytes = t;
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_ctx_host_memory(const xmgn_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return fail(XMGN_ERR_INVALID, "NULL argument");
+  *bytes = (int64_t)c->ht.bytes;
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_ctx_set_offload(xmgn_ctx* c, int32_t enable) {
+  GUARD_BEGIN
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipDeviceSynchronize());
+  if (enable && !c->cs) HIPCHK(hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking));
+  c->offload = enable != 0;
+  // the tape is re-allocated at its new size by the next forward
+  c->h.release();
+  c->e.release();
+  c->m.release();
+  c->zt.release();
+  if (!c->offload) c->ht.release();
+  c->fwd_valid = false;
+  return XMGN_OK;
+  GUARD_END
+}
+
+// Records an event (from the context's pool, one entry per use in a call) on
+// `st` after the work enqueued on it so far.
+static xmgn_status mark(xmgn_ctx* c, hipStream_t st, hipEvent_t* out) {
+  if (c->sev_used == c->sev.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->sev.push_back(e);
+  }
+  *out = c->sev[c->sev_used++];
+  HIPCHK(hipEventRecord(*out, st));
+  return XMGN_OK;
+}
+
+// Orders everything enqueued so far on `from` before what is enqueued next on `to`.
+static xmgn_status stream_order(xmgn_ctx* c, hipStream_t from, hipStream_t to) {
+  hipEvent_t e;
+  if (xmgn_status r = mark(c, from, &e)) return r;
+  HIPCHK(hipStreamWaitEvent(to, e, 0));
   return XMGN_OK;
 }
 
@@ -843,26 +924,29 @@ static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32
 static xmgn_status ensure_tape(xmgn_ctx* c, const xmgn_model_desc* d, bool full, bool z) {
   const size_t ts = tsize(d), H = d->hidden, L = d->n_layers;
   const size_t n = c->batch.n, E = c->batch.E;
-  const size_t sh = full ? L + 1 : 2, se = full ? L : 2, sm = full ? L : 1;
+  const int mode = !full ? 0 : c->offload ? 2 : 1;
+  const size_t sh = mode == 1 ? L + 1 : 2, se = mode == 1 ? L : std::min<size_t>(L, 2),
+               sm = mode == 1 ? L : mode == 2 ? std::min<size_t>(L, 2) : 1;
   if (xmgn_status s = c->h.ensure(sh * n * H * ts)) return s;
   if (xmgn_status s = c->e.ensure(se * E * H * ts)) return s;
   if (xmgn_status s = c->m.ensure(sm * n * H * 4)) return s;
-  c->tape_z = full && z;
+  // the offloaded tape keeps no z: the edge adjoint recomputes it
+  c->tape_z = mode == 1 && z;
   if (c->tape_z)
     if (xmgn_status s = c->zt.ensure(L * E * H * ts)) return s;
-  c->tape_slots_h = (int)sh;
-  c->tape_slots_e = (int)se;
-  c->tape_slots_m = (int)sm;
-  c->tape_full = full;
+  if (mode == 2)
+    if (xmgn_status s = c->ht.ensure(((L + 1) * n + L * E) * H * ts + L * n * H * 4)) return s;
+  c->tape_mode = mode;
   return XMGN_OK;
 }
 
+// Device slot of layer l's checkpoint.
 static void* hslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
-  const size_t s = c->tape_full ? l : l % 2;
+  const size_t s = c->tape_mode == 1 ? l : l % 2;
   return (char*)c->h.p + s * c->batch.n * d->hidden * tsize(d);
 }
 static void* eslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
-  const size_t s = c->tape_full ? l : l % 2;
+  const size_t s = c->tape_mode == 1 ? l : l % 2;
   return (char*)c->e.p + s * c->batch.E * d->hidden * tsize(d);
 }
 static void* zslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
@@ -870,9 +954,56 @@ static void* zslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   return (char*)c->zt.p + (size_t)l * c->batch.E * d->hidden * tsize(d);
 }
 static float* mslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
-  const size_t s = c->tape_full ? l : 0;
+  const size_t s = c->tape_mode == 1 ? l : c->tape_mode == 2 ? l % 2 : 0;
   return c->m.as<float>() + s * c->batch.n * d->hidden;
 }
+
+// Host copy of layer l's checkpoint in the offloaded tape.
+static void* host_h(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
+  return (char*)c->ht.p + (size_t)l * c->batch.n * d->hidden * tsize(d);
+}
+static void* host_e(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
+  const size_t H = d->hidden, ts = tsize(d), L = d->n_layers;
+  return (char*)c->ht.p + ((L + 1) * c->batch.n + (size_t)l * c->batch.E) * H * ts;
+}
+static void* host_m(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
+  const size_t H = d->hidden, ts = tsize(d), L = d->n_layers;
+  return (char*)c->ht.p + ((L + 1) * c->batch.n + L * c->batch.E) * H * ts + (size_t)l * c->batch.n * H * 4;
+}
+
+// Offloaded tape, forward: copy, on the copy stream, the checkpoint rows the
+// layer just made (h and e of level `lv`, m of level `lv - 1`; any may be
+// skipped) once the work enqueued on st so far has finished.
+// `done` receives an event that completes with these copies.
+static xmgn_status tape_out(xmgn_ctx* c, const xmgn_model_desc* d, hipStream_t st, int lh, int le, int lm,
+                            hipEvent_t* done) {
+  const size_t H = d->hidden, ts = tsize(d), n = c->batch.n, E = c->batch.E;
+  if (xmgn_status r = stream_order(c, st, c->cs)) return r;
+  if (lh >= 0) HIPCHK(hipMemcpyAsync(host_h(c, d, lh), hslot(c, d, lh), n * H * ts, hipMemcpyDeviceToHost, c->cs));
+  if (le >= 0) HIPCHK(hipMemcpyAsync(host_e(c, d, le), eslot(c, d, le), E * H * ts, hipMemcpyDeviceToHost, c->cs));
+  if (lm >= 0) HIPCHK(hipMemcpyAsync(host_m(c, d, lm), mslot(c, d, lm), n * H * 4, hipMemcpyDeviceToHost, c->cs));
+  return mark(c, c->cs, done);
+}
+
+// Offloaded tape, backward: bring layer l's checkpoint back into its device
+// slot on the copy stream, after the work enqueued on st so far (the last
+// reader of that slot) has finished.
+static xmgn_status tape_in(xmgn_ctx* c, const xmgn_model_desc* d, hipStream_t st, int l, bool h, bool e, bool m,
+                           hipEvent_t* done) {
+  const size_t H = d->hidden, ts = tsize(d), n = c->batch.n, E = c->batch.E;
+  if (xmgn_status r = stream_order(c, st, c->cs)) return r;
+  if (h) HIPCHK(hipMemcpyAsync(hslot(c, d, l), host_h(c, d, l), n * H * ts, hipMemcpyHostToDevice, c->cs));
+  if (e) HIPCHK(hipMemcpyAsync(eslot(c, d, l), host_e(c, d, l), E * H * ts, hipMemcpyHostToDevice, c->cs));
+  if (m) HIPCHK(hipMemcpyAsync(mslot(c, d, l), host_m(c, d, l), n * H * 4, hipMemcpyHostToDevice, c->cs));
+  return mark(c, c->cs, done);
+}
+
+// The offloaded tape leaves the last layers' checkpoints in their device
+// slots, where the backward finds them: all of layer L-1 (slot (L-1) % 2),
+// h^L, and e and m of layer L-2 (slot L % 2, whose h the forward overwrote
+// with h^L).  Only the rest travels.
+static bool tape_h_offloaded(int l, int L) { return l <= L - 2; }
+static bool tape_em_offloaded(int l, int L) { return l <= L - 3; }
 
 extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const float* params, const xmgn_partset* ps,
                                     const int32_t* part_ids, int32_t n_batch, const float* node_in, const float* pos,
@@ -912,13 +1043,30 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
   if (xmgn_status r = c->xe.ensure((size_t)b.E * 4 * sizeof(float))) return r;
   { KT("edge_feat"); launch_edge_feat(b, pos, en, c->xe.as<float>(), st); }
   { KT("enc_edge_fwd"); launch_enc_edge_fwd(s, b, weights(c, d, params, 1, 1, 0), c->xe.as<float>(), eslot(c, d, 0), st); }
+  // offloaded tape: copies[j] completes with the copies of the checkpoint rows
+  // made before layer j (j = 0: the encoders).  Layer l overwrites the device
+  // slot of layer l - 2, so it waits for copies[l - 1].
+  const bool off = c->tape_mode == 2;
+  c->sev_used = 0;
+  std::vector<hipEvent_t> copies(L + 1, nullptr);
+  if (off)
+    if (xmgn_status r = tape_out(c, d, st, tape_h_offloaded(0, L) ? 0 : -1, tape_em_offloaded(0, L) ? 0 : -1, -1,
+                                 &copies[0]))
+      return r;
   for (int l = 0; l < L; ++l) {
+    if (off && l >= 1) HIPCHK(hipStreamWaitEvent(st, copies[l - 1], 0));
     { KT("edge_fwd"); launch_edge_fwd(s, b, weights(c, d, params, 2 + 2 * l, 2, l), hslot(c, d, l), eslot(c, d, l),
                     l + 1 < L ? eslot(c, d, l + 1) : nullptr, mslot(c, d, l), zslot(c, d, l), st); }
     { KT("node_fwd"); launch_node_fwd(s, b, weights(c, d, params, 3 + 2 * l, 3, l), hslot(c, d, l), mslot(c, d, l), hslot(c, d, l + 1),
                     st); }
+    if (off)
+      if (xmgn_status r = tape_out(c, d, st, tape_h_offloaded(l + 1, L) ? l + 1 : -1,
+                                   tape_em_offloaded(l + 1, L) ? l + 1 : -1, tape_em_offloaded(l, L) ? l : -1,
+                                   &copies[l + 1]))
+        return r;
   }
   { KT("dec_fwd"); launch_dec_fwd(s, b, weights(c, d, params, 2 + 2 * L, 4, 0), hslot(c, d, L), out, d->out_dim, st); }
+  if (off) HIPCHK(hipStreamWaitEvent(st, copies[L], 0));  // the host tape is whole when the forward completes
   HIPCHK(hipGetLastError());
   if (g_config_error) return fail(XMGN_ERR_UNSUPPORTED, "tile configuration does not fit this kernel");
   c->fwd_valid = true;
@@ -1048,7 +1196,17 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   const float* de_in = nullptr;
   DBuf* de_out = &c->deA;
   DBuf* de_other = &c->deB;
+  // offloaded tape: layer l - 1's checkpoint comes back into its device slot
+  // (last read by layer l + 1, or by the decoder) while layer l runs.
+  const bool off = c->tape_mode == 2;
+  c->sev_used = 0;
+  std::vector<hipEvent_t> back(L, nullptr);
   for (int l = L - 1; l >= 0; --l) {
+    if (off && back[l]) HIPCHK(hipStreamWaitEvent(st, back[l], 0));
+    if (off && l >= 1 && tape_h_offloaded(l - 1, L)) {
+      const bool em = tape_em_offloaded(l - 1, L);
+      if (xmgn_status r = tape_in(c, d, st, l - 1, true, em, em, &back[l - 1])) return r;
+    }
     const MlpW wn = weights(c, d, params, 3 + 2 * l, 3, l);
     NodeBwdOut no{c->dhMid.as<float>(), c->dm.as<float>(), c->fa.p, c->fb.p, c->fc.p, part,
                   fnode ? c->wfused.as<float>() : nullptr};

@@ -102,3 +102,11 @@ def test_bad_graphs_and_partitions_are_rejected():
         api.Partset.halo(g, bad, [50, 50], 2)
     with pytest.raises(api.XmgnError):
         api.Partset.explicit(g, [[1, 1]], 2)
+
+
+def test_context_calls_reject_null_handles():
+    lib = _lib.lib
+    b = _lib.C.c_int64()
+    assert lib.xmgn_ctx_set_offload(None, 1) == -1
+    assert lib.xmgn_ctx_host_memory(None, _lib.C.byref(b)) == -1
+    assert lib.xmgn_ctx_memory(None, _lib.C.byref(b)) == -1

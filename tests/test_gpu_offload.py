@@ -1,0 +1,122 @@
+"""GPU: activation checkpoints offloaded to host memory (Sec. V.F.1).
+
+The offloaded tape must give the same forward bit for bit, the same
+gradients bit for bit wherever the device-resident tape recomputes the edge
+MLP's hidden activations too (FP32, SiLU), and gradients within 5e-3 of the
+resident tape's where that tape keeps them instead (BF16 ReLU); every run
+meets the parity bar against the FP64 oracle.  Depths 1, 2, 3 and 5 cover every case of which checkpoints stay in
+their device slots and which travel."""
+import numpy as np
+import pytest
+
+from cases import Case, check_step, log, oracle_refs, per_tensor_errors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2411_17164_amd import api as a
+    return a
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def step(api, ctx, case, ps, part_ids):
+    model = case.model(api)
+    p = dev(case.params)
+    node_in, pos, tgt = dev(case.inp.node_in), dev(case.inp.pos), dev(case.inp.targets)
+    out = torch.zeros(case.N, 4, device="cuda")
+    ctx.forward(model, p, ps, part_ids, node_in, pos, case.inp.edge_norm, out, keep_tape=True)
+    d_out = torch.zeros_like(out)
+    loss = torch.zeros(1, device="cuda")
+    ctx.mse_grad(out, tgt, case.N, d_out, loss)
+    d_params = torch.full_like(p, float("nan"))
+    ctx.backward(model, p, d_out, d_params)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), float(loss.item()), d_params.cpu().numpy()
+
+
+def pinned_bytes(case, n, E):
+    s = 2 if case.precision == "bf16" else 4
+    H, L = case.H, case.L
+    return ((L + 1) * n + L * E) * H * s + 4 * L * n * H
+
+
+@pytest.mark.parametrize("precision,act", [("fp32", "relu"), ("fp32", "silu"), ("bf16", "relu"), ("bf16", "silu")])
+@pytest.mark.parametrize("layers", [1, 2, 3, 5])
+def test_offload_matches_device_tape(api, precision, act, layers):
+    case = Case(3, levels=(500, 2000, 6000), layers=layers, precision=precision, activation=act)
+    log(f"offload {precision} {act} L={layers}")
+    resident, off = api.Context(0), api.Context(0)
+    off.set_offload(True)
+    g = resident.build_knn(dev(case.inp.pos), case.levels, case.k_intra, case.k_cross)
+    torch.cuda.synchronize()
+    ps = api.Partset.halo(g, case.inp.pos, None, case.L)
+    y_a, loss_a, g_a = step(api, resident, case, ps, [0])
+    y_b, loss_b, g_b = step(api, off, case, ps, [0])
+    assert (y_a == y_b).all()
+    assert loss_a == loss_b
+    assert np.isfinite(g_b).all()
+    n_inner, n_halo, E = ps.info(0)
+    assert off.host_memory() == pinned_bytes(case, n_inner + n_halo, E)
+    assert resident.host_memory() == 0
+    # one layer: two h slots, one e and one m slot either way
+    assert off.memory() < resident.memory() if layers > 1 else off.memory() <= resident.memory()
+    ztape = precision == "bf16" and act == "relu" and case.H == 128
+    if not ztape:
+        assert (g_a == g_b).all()
+    else:
+        errs = per_tensor_errors(case, g_b, g_a)
+        assert max(errs.values()) <= 5e-3, sorted(errs.items(), key=lambda kv: -kv[1])[:4]
+    log(f"  device {resident.memory() / 1e6:.1f} MB -> {off.memory() / 1e6:.1f} MB, "
+        f"pinned {off.host_memory() / 1e6:.1f} MB")
+    log("  " + check_step(case, y_b, loss_b, g_b, oracle_refs(case)))
+
+
+def test_offload_partitions_and_switching(api):
+    """Two partitions one at a time with the offloaded tape, gradients
+    accumulated, against the full graph with the resident tape; a larger
+    batch after a smaller one (the host tape grows), and switching offload
+    off and on again on the same context."""
+    case = Case(4, levels=(500, 2000, 8000), layers=4, precision="bf16", activation="silu")
+    ctx = api.Context(0)
+    g = ctx.build_knn(dev(case.inp.pos), case.levels, case.k_intra, case.k_cross)
+    torch.cuda.synchronize()
+    full = api.Partset.halo(g, case.inp.pos, None, case.L)
+    y_full, loss_full, g_full = step(api, ctx, case, full, [0])
+    ps = api.Partset.halo(g, case.inp.pos, np.array([3000, 5000]), case.L)
+    ctx.set_offload(True)
+    acc = torch.zeros(len(case.params), device="cuda")
+    y = np.zeros_like(y_full)
+    loss = 0.0
+    hm = []
+    for p in (0, 1):
+        yp, lp, gp = step(api, ctx, case, ps, [p])
+        gid = ps.export(p)["gid"][: ps.info(p)[0]]
+        y[gid] = yp[gid]
+        loss += lp
+        api.grad_accumulate(acc, dev(gp))
+        hm.append(ctx.host_memory())
+    torch.cuda.synchronize()
+    assert (y == y_full).all()
+    assert abs(loss - loss_full) <= 1e-5 * loss_full
+    errs = per_tensor_errors(case, acc.cpu().numpy(), g_full)
+    log(f"offload partitions: worst {sorted(errs.items(), key=lambda kv: -kv[1])[:3]}, pinned {hm}")
+    assert max(errs.values()) <= 5e-3
+    sizes = [sum(ps.info(p)[:2]) for p in (0, 1)]
+    edges = [ps.info(p)[2] for p in (0, 1)]
+    assert hm[1] == max(pinned_bytes(case, sizes[0], edges[0]), pinned_bytes(case, sizes[1], edges[1]))
+    ctx.set_offload(False)
+    assert ctx.host_memory() == 0
+    y2, loss2, g2 = step(api, ctx, case, full, [0])
+    assert (y2 == y_full).all() and (g2 == g_full).all()
+    ctx.set_offload(True)
+    y3, loss3, g3 = step(api, ctx, case, full, [0])
+    assert (y3 == y_full).all() and (g3 == g_full).all()
