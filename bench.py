@@ -136,6 +136,74 @@ def cpu_baseline(cfg_idx: int, layers: int, hidden: int):
                       f"({G.n_edges} edges, {layers} layers, H={hidden}); {t:.1f} s"}
 
 
+def study(args):
+    """Memory studies on one GPU, one partition per batch (Sec. V.F.1-2).
+
+    offload: the 3-level 400k-point ellipsoid in two halo partitions, with
+    the per-layer checkpoints on the device and offloaded to host memory.
+    memory: peak device memory of a training step against the partition
+    count (1 to 32, equal sizes, 15-hop halos) on the 1-level and the
+    3-level graph of the same 400k points, both tape placements.
+    Prints one JSON line per run."""
+    import torch
+
+    from paper_2411_17164_amd import api
+    from synth import CONFIGS, init_params, make_inputs
+
+    cfg = CONFIGS[3]
+    H, L = cfg.hidden, cfg.layers
+    dev = torch.device("cuda:0")
+    to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    if args.study == "offload":
+        plan = [("3-level", cfg.levels, [2])]
+    else:
+        plan = [("1-level", (cfg.levels[-1],), [1, 2, 4, 8, 16, 32]), ("3-level", cfg.levels, [1, 2, 4, 8, 16, 32])]
+    model = api.Model(H, L, precision="bf16")
+    entries = [(kind, shape) for (_, _, _, kind, shape, _) in model.param_tensors()]
+    params = to(init_params(entries, cfg.seed("weights")))
+    for gname, levels, part_counts in plan:
+        inp = make_inputs(cfg, levels=levels)
+        pos, node_in, tgt = to(inp.pos), to(inp.node_in), to(inp.targets)
+        kctx = api.Context(0)
+        g = kctx.build_knn(pos, [int(x) for x in inp.level_end], cfg.k_intra, cfg.k_cross if len(levels) > 1 else 0)
+        N, E = g.info()
+        out = torch.zeros(N, 4, device=dev)
+        d_out, loss = torch.zeros_like(out), torch.zeros(1, device=dev)
+        d_params, acc = torch.zeros_like(params), torch.zeros_like(params)
+        for P in part_counts:
+            sizes = None if P == 1 else [N // P + (1 if i < N % P else 0) for i in range(P)]
+            ps = api.Partset.halo(g, inp.pos, sizes, L)
+            infos = [ps.info(p) for p in range(P)]
+            E_proc = sum(i[2] for i in infos)
+            for offload in (False, True):
+                ctx = api.Context(0)
+                ctx.set_offload(offload)
+
+                def step():
+                    acc.zero_()
+                    for p in range(P):  # one partition at a time, gradients aggregated
+                        ctx.forward(model, params, ps, [p], node_in, pos, inp.edge_norm, out, keep_tape=True)
+                        ctx.mse_grad(out, tgt, N, d_out, loss)
+                        ctx.backward(model, params, d_out, d_params)
+                        api.grad_accumulate(acc, d_params)
+
+                step()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    step()
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) / args.steps * 1e3
+                line = {"study": args.study, "graph": gname, "nodes": N, "edges": E, "partitions": P, "halo": L,
+                        "offload": offload, "ms_per_step": round(ms, 2),
+                        "device_workspace_gb": round(ctx.memory() / 1e9, 3),
+                        "pinned_host_gb": round(ctx.host_memory() / 1e9, 3),
+                        "processed_edges": E_proc, "max_part_edges": max(i[2] for i in infos),
+                        "edge_updates_per_s": E * L / (ms * 1e-3), "dtype": "bf16", "data": "synthetic"}
+                print(json.dumps(line), flush=True)
+                del ctx
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,11 +222,17 @@ def main():
                     help="partitions per batch (wave) for partitioned workloads (0 = all in one batch)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB device copy first (to scale HBM counters)")
+    ap.add_argument("--study", choices=["offload", "memory"],
+                    help="memory studies instead of the benchmark line (one JSON line per run)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(partitions would be spread over GPUs with one gradient all-reduce)", file=sys.stderr)
         sys.exit(2)
+
+    if args.study:
+        study(args)
+        return
 
     import torch
 
