@@ -36,6 +36,7 @@ WORKLOADS = {
     "ellipsoid-ms-400k": 3,
     "ellipsoid-ms-1m-24p": 4,
     "car-ms-4m-16p": 5,
+    "car-ms-2m-21p-h512": 6,
 }
 
 
@@ -126,7 +127,7 @@ def cpu_baseline(cfg_idx: int, layers: int, hidden: int):
     levels = tuple(max(200, lv // div) for lv in cfg.levels)
     inp = make_inputs(cfg, levels=levels)
     G = og.build_graph(inp.pos, levels, cfg.k_intra, cfg.k_cross if len(levels) > 1 else 0)
-    d = om.Desc(hidden=hidden, layers=layers)
+    d = om.Desc(hidden=hidden, layers=layers, node_in=cfg.node_in, activation=cfg.activation)
     params = init_params(om.param_entries(d), cfg.seed("weights")).astype(np.float64)
     t0 = time.perf_counter()
     om.step_full(d, params, G, inp.node_in, inp.pos, inp.edge_norm, inp.targets)
@@ -273,8 +274,10 @@ def main():
         f"kNN {t_knn * 1e3:.1f} ms, plan {t_part * 1e3:.1f} ms")
 
     results = {}
-    for prec in (["bf16"] if args.no_fp32 else ["bf16", "fp32"]):
-        model = api.Model(H, L, precision=prec)
+    if H == 512 and not args.no_fp32:
+        log("[bench] H = 512 runs in the BF16 form only: no FP32 leg")
+    for prec in (["bf16"] if args.no_fp32 or H == 512 else ["bf16", "fp32"]):
+        model = api.Model(H, L, node_in=cfg.node_in, activation=cfg.activation, precision=prec)
         entries = [(kind, shape) for (_, _, _, kind, shape, _) in model.param_tensors()]
         params = to(init_params(entries, cfg.seed("weights")))
         out = torch.zeros(N, 4, device=dev)
@@ -297,7 +300,9 @@ def main():
                 api.grad_accumulate(acc, d_params)
 
         tuned = None
-        if not args.no_autotune and not (args.edge_rows or args.node_rows or args.grid or args.edge_waves):
+        if H == 512 and not args.no_autotune:
+            log("[bench] H = 512: fixed tiles (32-row edge, 16-row node), no autotuning")
+        elif not args.no_autotune and not (args.edge_rows or args.node_rows or args.grid or args.edge_waves):
             ctx.set_tiles(0, 0, 0, 0)
             tuned = ctx.autotune(model, params, ps, waves[0], node_in, pos, inp.edge_norm, out, d_out, d_params)
             log(f"[bench] {prec}: autotuned edge_rows={tuned[0]} node_rows={tuned[1]} grid={tuned[2]} "
@@ -376,7 +381,8 @@ def main():
                    "levels": levels, "k": [cfg.k_intra, cfg.k_cross], "partitions": n_parts,
                    "halo": L if n_parts > 1 else 0, "waves": len(waves), "processed_edges": E_proc,
                    "parallelism": "halo-partition batches" if n_parts > 1 else "none",
-                   "graph_replay": bool(args.graph and len(waves) == 1)},
+                   "graph_replay": bool(args.graph and len(waves) == 1), "activation": cfg.activation,
+                   "node_in": cfg.node_in},
         "processed_edge_updates_per_s": E_proc * L / bf["wall"],
         "roofline": roofline,
         "knn_build_ms": round(t_knn * 1e3, 2),

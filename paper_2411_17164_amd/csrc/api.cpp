@@ -120,9 +120,13 @@ struct HBuf {
 // ---------------------------------------------------------------------------
 static xmgn_status check_desc(const xmgn_model_desc* d) {
   if (!d) return fail(XMGN_ERR_INVALID, "desc is NULL");
-  if (d->hidden != 128 && d->hidden != 256) return fail(XMGN_ERR_UNSUPPORTED, "hidden must be 128 or 256");
+  if (d->hidden != 128 && d->hidden != 256 && d->hidden != 512)
+    return fail(XMGN_ERR_UNSUPPORTED, "hidden must be 128, 256 or 512");
+  if (d->hidden == 512 && d->precision != 1)
+    return fail(XMGN_ERR_UNSUPPORTED, "hidden 512 runs in the BF16 form only (an FP32 edge tile exceeds LDS)");
   if (d->n_layers < 1 || d->n_layers > 64) return fail(XMGN_ERR_INVALID, "n_layers must be in [1, 64]");
-  if (d->node_in < 1 || d->node_in > 8) return fail(XMGN_ERR_INVALID, "node_in must be in [1, 8]");
+  if (d->node_in < 1 || d->node_in > 32 || (d->node_in > 8 && d->node_in % 4 != 0))
+    return fail(XMGN_ERR_INVALID, "node_in must be in [1, 8], or a multiple of 4 up to 32");
   if (d->edge_in != 4) return fail(XMGN_ERR_INVALID, "edge_in must be 4");
   if (d->out_dim < 1 || d->out_dim > 16) return fail(XMGN_ERR_INVALID, "out_dim must be in [1, 16]");
   if (d->activation != 0 && d->activation != 1) return fail(XMGN_ERR_INVALID, "activation must be 0 or 1");
@@ -579,10 +583,15 @@ static Shape make_shape(const xmgn_ctx* c, const xmgn_model_desc* d) {
   s.agg = d->aggregate;
   s.eps = d->ln_eps;
   int me = c->mt_edge > 0 ? c->mt_edge : 64, mn = c->mt_node > 0 ? c->mt_node : 64;
-  // LDS budget: H = 256 runs 32-row tiles
+  // LDS budget: H = 256 runs 32-row tiles; H = 512 32-row edge tiles (a
+  // tile holds whole receiver segments) and 16-row node tiles
   if (d->hidden == 256) {
     me = 32;
     mn = 32;
+  }
+  if (d->hidden == 512) {
+    me = 32;
+    mn = 16;
   }
   s.mt_edge = me;
   s.mt_node = mn;
@@ -1268,7 +1277,11 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   if (fe) sn.grid = std::min(s.grid, 256);
   for (int blk = 1; blk >= 0; --blk) {
     const MlpW w = weights(c, d, params, blk, blk, 0);
-    EncBwdOut o{c->fa.p, c->fb.p, c->fc.p, c->fd.p, part, fe ? c->wfused.as<float>() : nullptr};
+    // more than 8 node inputs: the input layer's dW1 is a separate product
+    // over its FP32 adjoint (S_r is free once the layers are done)
+    const bool wide = blk == 0 && d->node_in > 8;
+    EncBwdOut o{c->fa.p, c->fb.p, c->fc.p, c->fd.p, part, fe ? c->wfused.as<float>() : nullptr,
+                wide ? c->Sr.as<float>() : nullptr};
     int R;
     int in_dim;
     if (blk == 1) {
@@ -1283,7 +1296,11 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     VecSeg vs[5] = {{0, (int)H, P(blk, 0, 1)}, {(int)H, (int)H, P(blk, 0, 3)}, {2 * (int)H, (int)H, P(blk, 0, 5)},
                     {3 * (int)H, (int)H, P(blk, 0, 6)}, {4 * (int)H, (int)H, P(blk, 0, 7)}};
     launch_vec_reduce(part, sn.grid, 13 * (int)H, vs, 5, rt, st);
-    launch_vec_reduce_strided(part, sn.grid, 13 * (int)H, 5 * (int)H, (int)H, in_dim, 8, P(blk, 0, 0), in_dim, rt, st);
+    if (wide)
+      wgrad(s, wop(c->Sr.p, 1, (int)H, 0, nullptr, c->f_node_in, 1, in_dim, 0, b.gid, (int)n, (int)H, in_dim,
+                   P(blk, 0, 0), in_dim), c->wpart, st);
+    else
+      launch_vec_reduce_strided(part, sn.grid, 13 * (int)H, 5 * (int)H, (int)H, in_dim, 8, P(blk, 0, 0), in_dim, rt, st);
     if (fe) {
       KT("wgrad");
       launch_wgrad_reduce(c->wfused.as<float>(), sn.grid, (int)H, (int)H, P(blk, 0, 2), (int)H, 2 * (int)(H * H), rt, st);

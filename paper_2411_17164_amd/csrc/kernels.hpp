@@ -139,7 +139,11 @@ struct EncBwdOut {
   void* du3;
   float* partial;  // [grid][5H + 8H]: db1 db2 db3 dgamma dbeta dW1[H][8]
   float* wpart;    // fused weight gradients [grid][2][H][H] (dW2, dW3) or NULL
+  float* da1;      // more than 8 inputs: adjoint of the input layer's output [rows][H] (FP32); dW1 not in partial
 };
+// Rows per tile of the edge encoder: the edge tile, except at H = 512 where
+// the encoder (no segment constraint) takes the 16-row node tile.
+inline int enc_edge_rows(const Shape& s) { return s.H == 512 ? s.mt_node : s.mt_edge; }
 // True when the encoder adjoint accumulates dW2 and dW3 itself (then z1,
 // z2, da2 and du3 are not written and wpart must be given).
 bool enc_bwd_fuses_wgrad(const Shape& s);

@@ -783,7 +783,9 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_bwd(BatchView b,
 // ---------------------------------------------------------------------------
 bool enc_bwd_fuses_wgrad(const Shape& s) { return s.prec == 1 && s.H == 128; }
 
-template <typename T, int H, int MT, int ACT, int KIND>
+// KIN as for k_enc_fwd; with 32 input slots the input layer's dW1 is left to
+// a separate product over o.da1 (its FP32 adjoint, written here).
+template <typename T, int H, int MT, int ACT, int KIND, int KIN>
 __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w, const float* __restrict__ src, int in_dim,
                                                   const float* __restrict__ dout, EncBwdOut o, float eps) {
   using D = BD<T, H>;
@@ -794,13 +796,13 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
   constexpr size_t FS = (size_t)MT * D::LDF * 4;
   constexpr size_t WS = FE ? (size_t)H * LDW * 2 : 0;
   static_assert(!FE || (MB % 2 == 0 && ZS <= FS), "fused weight gradients: k chunks of 32 rows, du3 over the FP32 tile");
-  __shared__ __align__(16) unsigned char smem[2 * ZS + FS + MT * 8 * 4 + 2 * NWAVE * MT * 4 + 2 * WS];
+  __shared__ __align__(16) unsigned char smem[2 * ZS + FS + MT * KIN * 4 + 2 * NWAVE * MT * 4 + 2 * WS];
   T* zs = (T*)smem;
   T* z2s = (T*)(smem + ZS);
   float* ft = (float*)(smem + 2 * ZS);
   T* du3s = (T*)ft;  // FE: du3 once the FP32 tile is dead
   float* xin = (float*)(smem + 2 * ZS + FS);
-  float* red = xin + MT * 8;  // [2][NWAVE][MT]
+  float* red = xin + MT * KIN;  // [2][NWAVE][MT]
   bf16* W2s = (bf16*)(red + 2 * NWAVE * MT);  // FE: W2 [out][in]
   bf16* W3s = W2s + (FE ? H * LDW : 0);       // FE: W3 [out][in]
   const T* W2 = (const T*)w.W2;
@@ -810,7 +812,7 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
   const int n0 = wave_id() * D::CPW;
   const int li = lane_id() & 15, lg = lane_id() >> 4;
   double cb1[NB] = {}, cb2[NB] = {}, cb3[NB] = {}, cg[NB] = {}, cbt[NB] = {};
-  double cw1[NB][8] = {};
+  double cw1[NB][KIN == 8 ? 8 : 1] = {};
   f32x4 accW2[NB][H / 16], accW3[NB][H / 16];
   if constexpr (FE) {
     zero_acc(accW2);
@@ -826,44 +828,68 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
   TileSched sch(n_tiles);
   for (int t = sch.begin; t < sch.end; t += sch.step) {
     const int row0 = t * MT, nr = min(MT, rows - row0);
-    if (threadIdx.x < MT) {
-      const int i = threadIdx.x;
-      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (i < nr) {
-        if constexpr (KIND == 0) {
-          const float* p = src + (size_t)b.gid[row0 + i] * in_dim;
-          for (int k = 0; k < in_dim; ++k) v[k] = p[k];
-        } else {
-          const float4 f = ((const float4*)src)[row0 + i];  // edge features (k_edge_feat)
-          v[0] = f.x;
-          v[1] = f.y;
-          v[2] = f.z;
-          v[3] = f.w;
+    if constexpr (KIN == 8) {
+      if (threadIdx.x < MT) {
+        const int i = threadIdx.x;
+        float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (i < nr) {
+          if constexpr (KIND == 0) {
+            const float* p = src + (size_t)b.gid[row0 + i] * in_dim;
+            for (int k = 0; k < in_dim; ++k) v[k] = p[k];
+          } else {
+            const float4 f = ((const float4*)src)[row0 + i];  // edge features (k_edge_feat)
+            v[0] = f.x;
+            v[1] = f.y;
+            v[2] = f.z;
+            v[3] = f.w;
+          }
         }
-      }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) xin[i * 8 + k] = v[k];
+        for (int k = 0; k < 8; ++k) xin[i * 8 + k] = v[k];
+      }
+    } else {
+      for (int task = threadIdx.x; task < MT * KIN; task += NTHR) {
+        const int i = task / KIN, k = task - i * KIN;
+        xin[task] = (i < nr && k < in_dim) ? src[(size_t)b.gid[row0 + i] * in_dim + k] : 0.f;
+      }
     }
     __syncthreads();
     f32x4 a1[MB][NB], a2[MB][NB], x[MB][NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int c = acc_col(n0, nb);
-      float wr[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) wr[k] = k < in_dim ? w.W1f[c * in_dim + k] : 0.f;
       const float bb = w.b1[c];
+      if constexpr (KIN == 8) {
+        float wr[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) wr[k] = k < in_dim ? w.W1f[c * in_dim + k] : 0.f;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float* xi = xin + acc_row(mb, r) * 8;
+            float s = bb;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += wr[k] * xi[k];
+            a1[mb][nb][r] = s;
+          }
+      } else {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a1[mb][nb][r] = bb;
+        for (int k = 0; k < in_dim; ++k) {
+          const float wk = w.W1f[c * in_dim + k];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a1[mb][nb][r] += wk * xin[acc_row(mb, r) * KIN + k];
+        }
+      }
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float* xi = xin + acc_row(mb, r) * 8;
-          float s = bb;
-#pragma unroll
-          for (int k = 0; k < 8; ++k) s += wr[k] * xi[k];
-          a1[mb][nb][r] = s;
-          x[mb][nb][r] = act_f<ACT>(s);
-        }
+        for (int r = 0; r < 4; ++r) x[mb][nb][r] = act_f<ACT>(a1[mb][nb][r]);
     }
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
     __syncthreads();
@@ -962,17 +988,29 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
 #pragma unroll
         for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a1[mb][nb][r]);
     col_accumulate(x, cb1);
+    if constexpr (KIN == 8) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        float s = 0.f;
+        for (int k = 0; k < 8; ++k) {
+          float s = 0.f;
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+          for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) s += x[mb][nb][r] * xin[acc_row(mb, r) * 8 + k];
-        cw1[nb][k] += (double)sum_groups(s);
-      }
+            for (int r = 0; r < 4; ++r) s += x[mb][nb][r] * xin[acc_row(mb, r) * 8 + k];
+          cw1[nb][k] += (double)sum_groups(s);
+        }
+    } else {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = acc_row(mb, r);
+            if (row < nr) o.da1[(size_t)(row0 + row) * H + acc_col(n0, nb)] = x[mb][nb][r];
+          }
+    }
     __syncthreads();
   }
   float* p = o.partial + (size_t)blockIdx.x * 13 * H;
@@ -981,11 +1019,12 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
   write_partial<NB>(p + 2 * H, n0, cb3);
   write_partial<NB>(p + 3 * H, n0, cg);
   write_partial<NB>(p + 4 * H, n0, cbt);
-  if ((lane_id() >> 4) == 0)
+  if constexpr (KIN == 8)
+    if ((lane_id() >> 4) == 0)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) p[5 * H + acc_col(n0, nb) * 8 + k] = (float)cw1[nb][k];
+        for (int k = 0; k < 8; ++k) p[5 * H + acc_col(n0, nb) * 8 + k] = (float)cw1[nb][k];
   if constexpr (FE) {
     float* q2 = o.wpart + (size_t)blockIdx.x * 2 * H * H;
     float* q3 = q2 + H * H;
@@ -1011,13 +1050,18 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
     using T = float;               \
     __VA_ARGS__                    \
   }
-#define XMGN_DISPATCH_H(Hv, ...) \
-  if (Hv == 128) {               \
-    constexpr int H = 128;       \
-    __VA_ARGS__                  \
-  } else {                       \
-    constexpr int H = 256;       \
-    __VA_ARGS__                  \
+#define XMGN_DISPATCH_H(Hv, ...)                \
+  if (Hv == 128) {                              \
+    constexpr int H = 128;                      \
+    __VA_ARGS__                                 \
+  } else if (Hv == 256) {                       \
+    constexpr int H = 256;                      \
+    __VA_ARGS__                                 \
+  } else if constexpr (sizeof(T) == 2) {        \
+    constexpr int H = 512; /* BF16 only */      \
+    __VA_ARGS__                                 \
+  } else {                                      \
+    g_config_error = 1;                         \
   }
 #define XMGN_DISPATCH_ACT(a, ...) \
   if (a == 0) {                   \
@@ -1027,10 +1071,14 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
     constexpr int ACT = 1;        \
     __VA_ARGS__                   \
   }
-// 64-row tiles only at H = 128; H = 256 uses 32-row tiles (LDS budget)
+// Rows per tile: 64 or 32 at H = 128, 32 at H = 256 (LDS budget); at
+// H = 512, 32 for edge tiles (whole receiver segments) and 16 for node tiles.
 #define XMGN_DISPATCH_MT(mt, ...)          \
   if (mt == 64 && H == 128) {              \
     constexpr int MT = H == 128 ? 64 : 32; \
+    __VA_ARGS__                            \
+  } else if (mt == 16 && H == 512) {       \
+    constexpr int MT = H == 512 ? 16 : 32; \
     __VA_ARGS__                            \
   } else {                                 \
     constexpr int MT = 32;                 \
@@ -1129,18 +1177,24 @@ void launch_dec_bwd(const Shape& s, const BatchView& b, const MlpW& w, const voi
 void launch_enc_node_bwd(const Shape& s, const BatchView& b, const MlpW& w, const float* node_in, int in_dim,
                          const float* dh0, const EncBwdOut& o, hipStream_t st) {
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
-    if constexpr (node_fits<T, H, MT>())
-      k_enc_bwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, dh0, o, s.eps);
-    else
+    if constexpr (node_fits<T, H, MT>()) {
+      if (in_dim <= 8)
+        k_enc_bwd<T, H, MT, ACT, 0, 8><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, dh0, o, s.eps);
+      else if (o.da1)
+        k_enc_bwd<T, H, MT, ACT, 0, 32><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, dh0, o, s.eps);
+      else
+        g_config_error = 1;
+    } else {
       g_config_error = 1;
+    }
   }))));
 }
 
 void launch_enc_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const float* xe, const float* de0,
                          const EncBwdOut& o, hipStream_t st) {
-  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(enc_edge_rows(s), {
     if constexpr (node_fits<T, H, MT>())
-      k_enc_bwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b.E, b, w, xe, 4, de0, o, s.eps);
+      k_enc_bwd<T, H, MT, ACT, 1, 8><<<s.grid, NTHR, 0, st>>>(b.E, b, w, xe, 4, de0, o, s.eps);
     else
       g_config_error = 1;
   }))));

@@ -240,17 +240,19 @@ void launch_edge_feat(const BatchView& b, const float* pos, EdgeNorm en, float* 
   k_edge_feat<<<(b.E + 255) / 256, 256, 0, st>>>(b.E, b, pos, en, (float4*)xe);
 }
 
-template <typename T, int H, int MT, int ACT, int KIND>
+// KIN: input slots per row (8, or 32 for up to 32 inputs, whose first layer
+// reads its weights from global memory inside a runtime-length loop).
+template <typename T, int H, int MT, int ACT, int KIND, int KIN>
 __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_enc_fwd(int rows, BatchView b, MlpW w, const float* __restrict__ src,
                                                   int in_dim, T* __restrict__ out, float eps) {
   using D = Dims<T, H>;
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
-  __shared__ __align__(16) unsigned char smem[2 * ZS + MT * 8 * 4 + 2 * NWAVE * MT * 4];
+  __shared__ __align__(16) unsigned char smem[2 * ZS + MT * KIN * 4 + 2 * NWAVE * MT * 4];
   T* zs = (T*)smem;
   T* z2 = (T*)(smem + ZS);
   float* xin = (float*)(smem + 2 * ZS);
-  float* red = xin + MT * 8;  // [2][NWAVE][MT]
+  float* red = xin + MT * KIN;  // [2][NWAVE][MT]
   const T* W2 = (const T*)w.W2;
   const T* W3 = (const T*)w.W3;
   const int n0 = wave_id() * D::CPW;
@@ -259,43 +261,68 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_enc_fwd(int rows, Ba
   TileSched sch(n_tiles);
   for (int t = sch.begin; t < sch.end; t += sch.step) {
     const int row0 = t * MT, nr = min(MT, rows - row0);
-    if (threadIdx.x < MT) {
-      const int i = threadIdx.x;
-      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (i < nr) {
-        if constexpr (KIND == 0) {
-          const float* p = src + (size_t)b.gid[row0 + i] * in_dim;
-          for (int k = 0; k < in_dim; ++k) v[k] = p[k];
-        } else {
-          const float4 f = ((const float4*)src)[row0 + i];  // edge features (k_edge_feat)
-          v[0] = f.x;
-          v[1] = f.y;
-          v[2] = f.z;
-          v[3] = f.w;
+    if constexpr (KIN == 8) {
+      if (threadIdx.x < MT) {
+        const int i = threadIdx.x;
+        float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (i < nr) {
+          if constexpr (KIND == 0) {
+            const float* p = src + (size_t)b.gid[row0 + i] * in_dim;
+            for (int k = 0; k < in_dim; ++k) v[k] = p[k];
+          } else {
+            const float4 f = ((const float4*)src)[row0 + i];  // edge features (k_edge_feat)
+            v[0] = f.x;
+            v[1] = f.y;
+            v[2] = f.z;
+            v[3] = f.w;
+          }
         }
-      }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) xin[i * 8 + k] = v[k];
+        for (int k = 0; k < 8; ++k) xin[i * 8 + k] = v[k];
+      }
+    } else {
+      for (int task = threadIdx.x; task < MT * KIN; task += NTHR) {
+        const int i = task / KIN, k = task - i * KIN;
+        xin[task] = (i < nr && k < in_dim) ? src[(size_t)b.gid[row0 + i] * in_dim + k] : 0.f;
+      }
     }
     __syncthreads();
     f32x4 acc[MB][NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int c = acc_col(n0, nb);
-      float wr[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) wr[k] = k < in_dim ? w.W1f[c * in_dim + k] : 0.f;
       const float bb = w.b1[c];
+      if constexpr (KIN == 8) {
+        float wr[8];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
+        for (int k = 0; k < 8; ++k) wr[k] = k < in_dim ? w.W1f[c * in_dim + k] : 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float* x = xin + acc_row(mb, r) * 8;
-          float a = bb;
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int k = 0; k < 8; ++k) a += wr[k] * x[k];
-          acc[mb][nb][r] = act_f<ACT>(a);
+          for (int r = 0; r < 4; ++r) {
+            const float* x = xin + acc_row(mb, r) * 8;
+            float a = bb;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a += wr[k] * x[k];
+            acc[mb][nb][r] = act_f<ACT>(a);
+          }
+      } else {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[mb][nb][r] = bb;
+        for (int k = 0; k < in_dim; ++k) {
+          const float wk = w.W1f[c * in_dim + k];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[mb][nb][r] += wk * xin[acc_row(mb, r) * KIN + k];
         }
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r]);
+      }
     }
     acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
     __syncthreads();
@@ -409,13 +436,18 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_fwd(BatchView b,
     using T = float;                    \
     __VA_ARGS__                         \
   }
-#define XMGN_DISPATCH_H(Hv, ...)        \
-  if (Hv == 128) {                      \
-    constexpr int H = 128;              \
-    __VA_ARGS__                         \
-  } else {                              \
-    constexpr int H = 256;              \
-    __VA_ARGS__                         \
+#define XMGN_DISPATCH_H(Hv, ...)                \
+  if (Hv == 128) {                              \
+    constexpr int H = 128;                      \
+    __VA_ARGS__                                 \
+  } else if (Hv == 256) {                       \
+    constexpr int H = 256;                      \
+    __VA_ARGS__                                 \
+  } else if constexpr (sizeof(T) == 2) {        \
+    constexpr int H = 512; /* BF16 only */      \
+    __VA_ARGS__                                 \
+  } else {                                      \
+    g_config_error = 1;                         \
   }
 #define XMGN_DISPATCH_ACT(a, ...)       \
   if (a == 0) {                         \
@@ -425,10 +457,14 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_fwd(BatchView b,
     constexpr int ACT = 1;              \
     __VA_ARGS__                         \
   }
-// 64-row tiles only at H = 128; H = 256 uses 32-row tiles (LDS budget)
+// Rows per tile: 64 or 32 at H = 128, 32 at H = 256 (LDS budget); at
+// H = 512, 32 for edge tiles (whole receiver segments) and 16 for node tiles.
 #define XMGN_DISPATCH_MT(mt, ...)          \
   if (mt == 64 && H == 128) {              \
     constexpr int MT = H == 128 ? 64 : 32; \
+    __VA_ARGS__                            \
+  } else if (mt == 16 && H == 512) {       \
+    constexpr int MT = H == 512 ? 16 : 32; \
     __VA_ARGS__                            \
   } else {                                 \
     constexpr int MT = 32;                 \
@@ -479,15 +515,18 @@ void launch_enc_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, cons
                          void* h0, hipStream_t st) {
   if (b.n == 0) return;
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_node, {
-    k_enc_fwd<T, H, MT, ACT, 0><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, (T*)h0, s.eps);
+    if (in_dim <= 8)
+      k_enc_fwd<T, H, MT, ACT, 0, 8><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, (T*)h0, s.eps);
+    else
+      k_enc_fwd<T, H, MT, ACT, 0, 32><<<s.grid, NTHR, 0, st>>>(b.n, b, w, node_in, in_dim, (T*)h0, s.eps);
   }))));
 }
 
 void launch_enc_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const float* xe, void* e0,
                          hipStream_t st) {
   if (b.E == 0) return;
-  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
-    k_enc_fwd<T, H, MT, ACT, 1><<<s.grid, NTHR, 0, st>>>(b.E, b, w, xe, 4, (T*)e0, s.eps);
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(enc_edge_rows(s), {
+    k_enc_fwd<T, H, MT, ACT, 1, 8><<<s.grid, NTHR, 0, st>>>(b.E, b, w, xe, 4, (T*)e0, s.eps);
   }))));
 }
 

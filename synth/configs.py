@@ -1,4 +1,4 @@
-"""The five synthetic workloads and their seeded inputs.
+"""The six synthetic workloads and their seeded inputs.
 
 Sizes follow the paper's workload shape (Sec. V.C: 3-level surface point
 clouds, k = 6, a halo as deep as the 15 message-passing layers; Sec. V.D:
@@ -30,10 +30,16 @@ class Config:
     part_jitter: float = 0.0      # relative spread of partition sizes
     halo: int = 0
     precision: str = "fp32"
+    activation: str = "relu"
+    fourier: tuple = ()           # frequencies f of the sin / cos(2 pi f x) input features
 
     @property
     def n_nodes(self) -> int:
         return self.levels[-1]
+
+    @property
+    def node_in(self) -> int:
+        return NODE_IN + 6 * len(self.fourier)
 
     def seed(self, what: str) -> int:
         off = {"geom": 1, "modes": 2, "weights": 3, "targets": 4, "parts": 5}[what]
@@ -49,6 +55,11 @@ CONFIGS = {
               n_parts=24, part_jitter=0.4, halo=15, precision="bf16"),
     5: Config(5, "car-ms-4m-16p", "car", (250_000, 1_000_000, 4_000_000), 6, 3, 256, 15,
               n_parts=16, part_jitter=0.0, halo=15, precision="bf16"),
+    # the paper's own training shape (Sec. V.C-D): 3 levels of 0.5M/1M/2M
+    # points, 21 partitions with 15-hop halos, H = 512, SiLU, 24 inputs
+    # (position, normal and their Fourier features at 2 pi, 4 pi, 8 pi)
+    6: Config(6, "car-ms-2m-21p-h512", "car", (500_000, 1_000_000, 2_000_000), 6, 3, 512, 15,
+              n_parts=21, part_jitter=0.0, halo=15, precision="bf16", activation="silu", fourier=(1, 2, 4)),
 }
 
 NODE_IN = 6     # position + normal
@@ -77,6 +88,16 @@ def zscore(x: np.ndarray) -> np.ndarray:
     sd = x64.std(axis=0)
     sd[sd == 0] = 1.0
     return ((x64 - mu) / sd).astype(np.float32)
+
+
+def fourier_features(pos: np.ndarray, freqs) -> np.ndarray:
+    """[sin(2 pi f x_c), cos(2 pi f x_c)] for every frequency f and coordinate
+    c, in float64 from the float32 positions: float32 [n][6 len(freqs)]."""
+    x = pos.astype(np.float64)
+    cols = []
+    for f in freqs:
+        cols += [np.sin(2.0 * np.pi * f * x), np.cos(2.0 * np.pi * f * x)]
+    return np.concatenate(cols, axis=1).astype(np.float32) if cols else np.zeros((len(pos), 0), np.float32)
 
 
 def edge_norm_for(pos: np.ndarray) -> np.ndarray:
@@ -137,7 +158,7 @@ class Inputs:
     pos: np.ndarray          # float32 [N][3]
     normal: np.ndarray       # float32 [N][3]
     level_end: np.ndarray    # int32 [levels]
-    node_in: np.ndarray      # float32 [N][6] z-scored [pos, normal]
+    node_in: np.ndarray      # float32 [N][node_in] z-scored [pos, normal, Fourier features]
     edge_norm: np.ndarray    # float32 [2][4]
     targets: np.ndarray      # float32 [N][4]
     part_sizes: np.ndarray   # int32 [n_parts]
@@ -150,7 +171,7 @@ def make_inputs(cfg: Config, n: int | None = None, levels=None, n_parts=None) ->
     levels = tuple(cfg.levels if levels is None else levels)
     n = levels[-1] if n is None else n
     pos, nrm = points(cfg, n)
-    node_in = zscore(np.concatenate([pos, nrm], axis=1))
+    node_in = zscore(np.concatenate([pos, nrm, fourier_features(pos, cfg.fourier)], axis=1))
     g = np.random.Generator(np.random.PCG64(cfg.seed("targets")))
     targets = g.standard_normal((n, OUT_DIM)).astype(np.float32)
     return Inputs(cfg, pos, nrm, np.array(levels, dtype=np.int32), node_in,

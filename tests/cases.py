@@ -38,7 +38,8 @@ class Case:
         self.precision = precision
         self.activation = activation
         self.aggregate = aggregate
-        self.desc = om.Desc(hidden=self.H, layers=self.L, activation=activation, aggregate=aggregate)
+        self.desc = om.Desc(hidden=self.H, layers=self.L, node_in=self.cfg.node_in, activation=activation,
+                            aggregate=aggregate)
         self.params = init_params(om.param_entries(self.desc), self.cfg.seed("weights"))
         self.N = self.levels[-1]
         self._graph = None
@@ -49,8 +50,8 @@ class Case:
         return self._graph
 
     def model(self, api):
-        return api.Model(self.H, self.L, activation=self.activation, precision=self.precision,
-                         aggregate=self.aggregate)
+        return api.Model(self.H, self.L, node_in=self.cfg.node_in, activation=self.activation,
+                         precision=self.precision, aggregate=self.aggregate)
 
     def tensor_slices(self):
         """(name, slice) of every parameter tensor, in blob order."""

@@ -44,6 +44,15 @@ def test_unsupported_hidden_and_bad_desc():
         api.Model(128, 0).param_count()
     with pytest.raises(api.XmgnError):
         api.Model(128, 2, edge_in=3).param_count()
+    # H = 512 runs in the BF16 form only; wide inputs come in multiples of 4
+    with pytest.raises(api.XmgnError) as e:
+        api.Model(512, 2, precision="fp32").param_count()
+    assert e.value.code == -5
+    assert api.Model(512, 2, precision="bf16", node_in=24).param_count() > 0
+    with pytest.raises(api.XmgnError):
+        api.Model(128, 2, node_in=10).param_count()
+    with pytest.raises(api.XmgnError):
+        api.Model(128, 2, node_in=36).param_count()
 
 
 def _cloud(n, seed):

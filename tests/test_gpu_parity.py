@@ -274,3 +274,39 @@ def test_partset_freed_and_replaced(api, ctx):
         log(f"  N={case.N}: rel-L2 {err:.2e}")
         assert err <= 1e-4
         del ps, g  # freed before the next set is created
+
+
+@pytest.mark.parametrize("act", ["silu", "relu"])
+def test_fwd_bwd_h512_production(api, ctx, act):
+    """The paper's training shape at reduced size: car recipe, H = 512 (BF16
+    only), 24 inputs (position, normal and their Fourier features), 3
+    layers: 32-row edge tiles, 16-row node tiles, the wide input layer."""
+    case = Case(6, levels=(200, 800, 2500), layers=3, precision="bf16", activation=act)
+    assert case.H == 512 and case.cfg.node_in == 24
+    log(f"fwd+bwd H=512 production {act} levels={case.levels}")
+    g = gpu_graph(api, ctx, case)
+    ps = api.Partset.halo(g, case.inp.pos, None, case.L)
+    out, loss, grad = gpu_step(api, ctx, case, ps, [0])
+    log("  " + check_step(case, out, loss, grad, oracle_refs(case)))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_wide_node_input(api, ctx, precision):
+    """24 node inputs at H = 128: the encoder's input layer loops over its
+    inputs and its weight gradient is a separate product over the FP32
+    adjoint, gathered through the batch's node ids."""
+    case = Case(6, levels=(400, 1600, 5000), hidden=128, layers=2, precision=precision, activation="silu")
+    log(f"fwd+bwd 24 inputs H=128 {precision}")
+    g = gpu_graph(api, ctx, case)
+    sizes = np.array([2000, 3000])
+    ps = api.Partset.halo(g, case.inp.pos, sizes, case.L)
+    full = api.Partset.halo(g, case.inp.pos, None, case.L)
+    out, loss, grad = gpu_step(api, ctx, case, full, [0])
+    log("  " + check_step(case, out, loss, grad, oracle_refs(case)))
+    # a partition's rows are not the global rows: the input gather goes through gid
+    acc = torch.zeros(len(case.params), device="cuda")
+    for p in range(2):
+        api.grad_accumulate(acc, dev(gpu_step(api, ctx, case, ps, [p])[2]))
+    torch.cuda.synchronize()
+    errs = per_tensor_errors(case, acc.cpu().numpy(), grad)
+    assert max(errs.values()) <= (1e-5 if precision == "fp32" else 5e-3), sorted(errs.items(), key=lambda kv: -kv[1])[:3]
