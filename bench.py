@@ -112,8 +112,8 @@ def measured_traffic(workload: str, kernel: str):
 def cpu_baseline(cfg_idx: int, layers: int, hidden: int):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
     the same geometry / multi-scale recipe at 1/32 of the points (1/128 at
-    H = 256, to keep the same amount of work), full depth and width, one
-    forward + backward."""
+    H = 256, 1/2048 at H = 512, to keep the same order of work), full depth
+    and width, one forward + backward."""
     from oracle import graph as og
     from oracle import model as om
     from synth import CONFIGS, init_params, make_inputs
@@ -123,7 +123,7 @@ def cpu_baseline(cfg_idx: int, layers: int, hidden: int):
     except Exception:  # noqa: BLE001
         cores = os.cpu_count() or 1
     cfg = CONFIGS[cfg_idx]
-    div = 32 * (hidden // 128) ** 2
+    div = 32 * (hidden // 128) ** (2 if hidden <= 256 else 3)
     levels = tuple(max(200, lv // div) for lv in cfg.levels)
     inp = make_inputs(cfg, levels=levels)
     G = og.build_graph(inp.pos, levels, cfg.k_intra, cfg.k_cross if len(levels) > 1 else 0)

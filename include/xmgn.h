@@ -105,8 +105,10 @@ void xmgn_ctx_destroy(xmgn_ctx* ctx);
 /* Tile configuration of the processor kernels: rows per tile of the edge and
  * node kernels (32 or 64), the persistent grid size in workgroups (a
  * multiple of 8) and the waves per workgroup of the edge kernels (4 or 8);
- * 0 selects the library default for any of them.  Changing it invalidates
- * cached batch plans. */
+ * 0 selects the library default for any of them (64, 64, 1024, 4; 8 edge
+ * waves at H = 512).  LDS fixes the rows at H = 256 (32 and 32) and at
+ * H = 512 (32-row edge tiles, 16-row node tiles) whatever is asked.
+ * Changing it invalidates cached batch plans. */
 xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int32_t node_rows,
                                int32_t grid, int32_t edge_waves);
 

@@ -596,7 +596,7 @@ static Shape make_shape(const xmgn_ctx* c, const xmgn_model_desc* d) {
   s.mt_edge = me;
   s.mt_node = mn;
   s.grid = c->grid > 0 ? c->grid : 1024;
-  s.nw_edge = c->nw_edge > 0 ? c->nw_edge : 4;
+  s.nw_edge = c->nw_edge > 0 ? c->nw_edge : d->hidden == 512 ? 8 : 4;  // H = 512: fewer spills at 8 waves
   return s;
 }
 
