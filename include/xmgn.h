@@ -237,6 +237,30 @@ xmgn_status xmgn_autotune(xmgn_ctx* ctx, const xmgn_model_desc* desc, const floa
 xmgn_status xmgn_grad_accumulate(float* acc, const float* g, int64_t n, xmgn_stream stream);
 
 /*
+ * Optimizer step of the paper's training (Sec. V.D: Adam, gradients clipped
+ * at a global L2 norm of 32, learning rate annealed on a cosine).
+ * params, m, v: dev FP32 [n], updated in place (m, v start at zero);
+ * grad: dev FP32 [n], read only.  With clip_norm > 0 the gradient is first
+ * scaled by min(1, clip_norm / (||grad||_2 + 1e-6)), the norm taken over
+ * all n entries and summed in FP64 in a fixed order; then, with t = step
+ * (1-based), m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2 and
+ * params -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * grad_norm: dev FP32 [1] receiving ||grad||_2 before clipping, or NULL.
+ * The update runs in FP32; the host scalars 1 - b1, 1 - b2, 1 - b1^t and
+ * 1 - b2^t are formed in FP64 and rounded once.  Deterministic,
+ * asynchronous on `stream`; uses a small scratch buffer of ctx, so steps on
+ * one ctx must be ordered on one stream.  Errors: XMGN_ERR_INVALID for
+ * step < 1, betas outside [0, 1), a non-finite or negative lr, eps <= 0.
+ */
+xmgn_status xmgn_adam_step(xmgn_ctx* ctx, float* params, const float* grad, float* m, float* v,
+                           int64_t n, int64_t step, double lr, double beta1, double beta2, double eps,
+                           double clip_norm, float* grad_norm, xmgn_stream stream);
+/* Cosine-annealed learning rate (Sec. V.D) at step t of T (host, no device
+ * work): lr_min + (lr_max - lr_min) (1 + cos(pi t / T)) / 2 with t clamped
+ * to [0, T]; lr_min when T <= 0. */
+double xmgn_cosine_lr(int64_t t, int64_t T, double lr_max, double lr_min);
+
+/*
  * Per-kernel timing (tracing).  While enabled, every kernel the context
  * launches is bracketed by a pair of HIP events on its stream; the totals per
  * kernel class since the last xmgn_ctx_set_timing call are read with

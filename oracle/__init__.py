@@ -9,7 +9,9 @@ Modules
   graph      multi-scale kNN point-cloud graph (Sec. III.B, III.C) -> CSR/CSC
   partition  recursive coordinate bisection + L-hop halo (Sec. III.A)
   model      encoder / processor (Eq. 1-4) / decoder, masked MSE loss,
-             hand-written adjoint, gradient aggregation over partitions
+             hand-written adjoint, gradient aggregation over partitions,
+             the bfloat16 weight cast of mixed-precision training
+  optim      Adam with global-norm clipping, cosine learning rate (Sec. V.D)
 
 Every function is float64 unless it produces integers.  Where the paper is
 silent the reading taken is stated in the function's docstring.

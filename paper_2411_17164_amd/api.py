@@ -264,6 +264,31 @@ def grad_accumulate(acc: torch.Tensor, g: torch.Tensor, stream=None):
     check(lib.xmgn_grad_accumulate(_dev(acc), _dev(g), acc.numel(), _stream(stream)))
 
 
+def cosine_lr(t: int, total: int, lr_max: float, lr_min: float) -> float:
+    return float(lib.xmgn_cosine_lr(t, total, lr_max, lr_min))
+
+
+class Adam:
+    """Optimizer state (m, v, step) for xmgn_adam_step on one parameter blob."""
+
+    def __init__(self, ctx: Context, params: torch.Tensor, betas=(0.9, 0.999), eps: float = 1e-8,
+                 clip_norm: float = 32.0):
+        self.ctx, self.params = ctx, params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.norm = torch.zeros(1, device=params.device)
+        self.betas, self.eps, self.clip_norm = betas, eps, clip_norm
+        self.t = 0
+
+    def step(self, grad: torch.Tensor, lr: float, stream=None):
+        if grad.numel() != self.params.numel():
+            raise ValueError("size mismatch")
+        self.t += 1
+        check(lib.xmgn_adam_step(self.ctx._h, _dev(self.params), _dev(grad), _dev(self.m), _dev(self.v),
+                                 self.params.numel(), self.t, lr, self.betas[0], self.betas[1], self.eps,
+                                 self.clip_norm, _dev(self.norm), _stream(stream)))
+
+
 class ProcessorFn(torch.autograd.Function):
     """out = X-MeshGraphNet(params) on a batch of partitions; backward returns
     d_params through the hand-written adjoint (xmgn_backward)."""

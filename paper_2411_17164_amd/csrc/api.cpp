@@ -519,7 +519,8 @@ struct xmgn_ctx {
   size_t sev_used = 0;
   // backward workspace
   DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, wfused, redtmp, lossp;
-  DBuf xe;  // edge features of the forward [E][4]
+  DBuf xe;    // edge features of the forward [E][4]
+  DBuf optp;  // optimizer: per-workgroup squared-norm partials (FP64)
   DBuf zt;  // hidden activations of the edge MLPs [L][E][H] (edge_z_tape forms, full tape)
   bool tape_z = false;
   // per-kernel timing
@@ -686,7 +687,8 @@ extern "C" xmgn_status xmgn_ctx_memory(const xmgn_ctx* c, int64_t* bytes) {
   if (!c || !bytes) return fail(XMGN_ERR_INVALID, "NULL argument");
   const DBuf* bufs[] = {&c->batch.ints, &c->jobs_dev, &c->blob, &c->h, &c->e, &c->m, &c->dhA, &c->dhMid,
                         &c->dm, &c->Sr, &c->Ss, &c->deA, &c->deB, &c->fa, &c->fb, &c->fc, &c->fd,
-                        &c->dy, &c->part, &c->wpart, &c->wfused, &c->redtmp, &c->lossp, &c->xe, &c->zt};
+                        &c->dy, &c->part, &c->wpart, &c->wfused, &c->redtmp, &c->lossp, &c->xe, &c->zt,
+                        &c->optp};
   int64_t t = 0;
   for (const DBuf* b : bufs) t += (int64_t)b->bytes;
   *bytes = t;
@@ -1325,6 +1327,35 @@ extern "C" xmgn_status xmgn_grad_accumulate(float* acc, const float* g, int64_t 
   launch_accumulate(acc, g, n, (hipStream_t)stream);
   HIPCHK(hipGetLastError());
   return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_adam_step(xmgn_ctx* c, float* params, const float* grad, float* m, float* v, int64_t n,
+                                      int64_t step, double lr, double beta1, double beta2, double eps,
+                                      double clip_norm, float* grad_norm, xmgn_stream stream) {
+  GUARD_BEGIN
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (n < 0) return fail(XMGN_ERR_INVALID, "n must be >= 0");
+  if (n > 0 && (!params || !grad || !m || !v)) return fail(XMGN_ERR_INVALID, "NULL argument");
+  if (step < 1) return fail(XMGN_ERR_INVALID, "step is 1-based");
+  if (!(std::isfinite(lr) && lr >= 0.0 && std::isfinite(eps) && eps > 0.0 && std::isfinite(clip_norm)))
+    return fail(XMGN_ERR_INVALID, "lr must be finite and >= 0, eps finite and > 0, clip_norm finite");
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0))
+    return fail(XMGN_ERR_INVALID, "betas must be in [0, 1)");
+  HIPCHK(hipSetDevice(c->device));
+  const int G = 256;
+  if (xmgn_status r = c->optp.ensure(G * sizeof(double))) return r;
+  AdamArgs a{(float)lr, (float)beta1, (float)beta2, (float)(1.0 - beta1), (float)(1.0 - beta2), (float)eps,
+             (float)(1.0 - std::pow(beta1, (double)step)), (float)(1.0 - std::pow(beta2, (double)step)), clip_norm};
+  launch_adam(params, grad, m, v, n, c->optp.as<double>(), G, a, grad_norm, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return XMGN_OK;
+  GUARD_END
+}
+
+extern "C" double xmgn_cosine_lr(int64_t t, int64_t T, double lr_max, double lr_min) {
+  if (T <= 0) return lr_min;
+  const double x = (double)std::min<int64_t>(std::max<int64_t>(t, 0), T) / (double)T;
+  return lr_min + 0.5 * (lr_max - lr_min) * (1.0 + std::cos(M_PI * x));
 }
 
 extern "C" xmgn_status xmgn_build_knn(xmgn_ctx* c, const float* pos, int32_t n, const int32_t* level_end,

@@ -330,6 +330,61 @@ void launch_accumulate(float* acc, const float* g, int64_t n, hipStream_t st) {
   k_accumulate<<<(unsigned)blocks, 256, 0, st>>>(acc, g, n);
 }
 
+// ---------------------------------------------------------------------------
+// Optimizer: global-norm clipping and Adam.  The squared norm is summed in
+// FP64, per workgroup over a fixed index set and then over the workgroups in
+// order, so the step is deterministic.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ g, int64_t n,
+                                               double* __restrict__ partial) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double x = g[i];
+    s += x * x;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, int64_t n,
+                                              const double* __restrict__ partial, int G, AdamArgs a,
+                                              float* __restrict__ norm_out) {
+  __shared__ float scale;
+  if (threadIdx.x == 0) {
+    double ss = 0.0;
+    for (int k = 0; k < G; ++k) ss += partial[k];
+    const double norm = sqrt(ss);
+    scale = a.clip > 0.0 ? (float)fmin(1.0, a.clip / (norm + 1e-6)) : 1.f;
+    if (blockIdx.x == 0 && norm_out) norm_out[0] = (float)norm;
+  }
+  __syncthreads();
+  const float sc = scale;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float gi = g[i] * sc;
+    const float mi = a.b1 * m[i] + a.c1 * gi;
+    const float vi = a.b2 * v[i] + a.c2 * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= a.lr * (mi / a.bc1) / (sqrtf(vi / a.bc2) + a.eps);
+  }
+}
+
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, double* partial, int G,
+                 const AdamArgs& a, float* norm_out, hipStream_t st) {
+  k_sumsq<<<G, 256, 0, st>>>(g, n, partial);
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  k_adam<<<(unsigned)blocks, 256, 0, st>>>(p, g, m, v, n, partial, G, a, norm_out);
+}
+
 // Masked MSE over the batch's inner rows: per-workgroup partial sums in a
 // fixed order, then a single-workgroup fixed-order total.
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out, const float* __restrict__ target,

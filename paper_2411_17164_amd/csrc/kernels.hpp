@@ -197,6 +197,15 @@ void launch_prep(const float* params, void* blob, int prec, const PrepJob* jobs_
 
 void launch_fill(float* p, size_t n, float v, hipStream_t st);
 void launch_accumulate(float* acc, const float* g, int64_t n, hipStream_t st);
+// Adam constants of one step, each rounded to FP32 once from its FP64 value:
+// c1 = 1 - b1, c2 = 1 - b2, bc1 = 1 - b1^t, bc2 = 1 - b2^t; clip <= 0: none.
+struct AdamArgs {
+  float lr, b1, b2, c1, c2, eps, bc1, bc2;
+  double clip;
+};
+// partial: dev double [G] scratch; norm_out: dev float [1] or NULL.
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, double* partial, int G,
+                 const AdamArgs& a, float* norm_out, hipStream_t st);
 void launch_mse(const float* out, const float* target, const int* gid, const int* inner, int n_inner,
                 int out_dim, double inv_norm, float* d_out, float* partial, int G, float* loss,
                 hipStream_t st);
