@@ -68,9 +68,10 @@ const char* xmgn_version(void);
  *   LN(u) = gamma (u - mean) / sqrt(var + ln_eps) + beta, biased variance.
  */
 typedef struct {
-  int32_t hidden;     /* H: 128 or 256 */
+  int32_t hidden;     /* H: 128, 256, or 512 (BF16 form only) */
   int32_t n_layers;   /* processor layers L >= 1 */
-  int32_t node_in;    /* node input width, 1..8 (6 = position + normal) */
+  int32_t node_in;    /* node input width: 1..8, or a multiple of 4 up to 32
+                         (6 = position + normal; 24 adds their Fourier features) */
   int32_t edge_in;    /* must be 4 */
   int32_t out_dim;    /* decoder outputs, 1..16 */
   int32_t activation; /* 0 = ReLU, 1 = SiLU */
