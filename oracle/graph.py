@@ -30,13 +30,15 @@ def sqdist(pos64: np.ndarray, q: np.ndarray, j: np.ndarray) -> np.ndarray:
     return (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
 
 
-def knn(pos: np.ndarray, queries: np.ndarray, cand_end: int, k: int) -> np.ndarray:
+def knn(pos: np.ndarray, queries: np.ndarray, cand_end: int, k: int, tree=None) -> np.ndarray:
     """The k nearest candidates j in [0, cand_end), j != q, of each query q,
     ranked by (d2, j).  Returns int32 [len(queries)][k].
 
     A k-d tree (library primitive) supplies, for each query, every candidate
     within a radius that is guaranteed to contain the k best; the exact key is
-    then computed here and sorted.
+    then computed here and sorted.  `tree`: a cKDTree over the float64
+    candidates pos[:cand_end], built here when not given (a caller querying
+    the same candidates many times builds it once).
     """
     queries = np.asarray(queries, dtype=np.int64)
     nq = len(queries)
@@ -45,7 +47,10 @@ def knn(pos: np.ndarray, queries: np.ndarray, cand_end: int, k: int) -> np.ndarr
     if k >= cand_end:
         raise ValueError("k must be smaller than the candidate count")
     pos64 = pos.astype(np.float64)
-    tree = cKDTree(pos64[:cand_end])
+    if tree is None:
+        tree = cKDTree(pos64[:cand_end])
+    elif tree.n != cand_end:
+        raise ValueError("tree does not hold the candidates [0, cand_end)")
     kk = min(k + 1, cand_end)
     dist, _ = tree.query(pos64[queries], k=kk)
     dist = np.asarray(dist).reshape(nq, kk)

@@ -122,3 +122,34 @@ def check_step(case: Case, out, loss, grad, refs) -> str:
     assert worst_a[0][1] <= 2e-2, worst_a
     return (f"vs model: out {e_out:.2e} loss {e_loss:.2e} grad {total:.2e} worst {worst} | "
             f"vs cast weights: out {e_out_a:.2e} grad {rel_l2(grad, g_a):.2e} worst {worst_a}")
+
+
+def cone_graph(case, seed, trees):
+    """The in-lists of every node within L - 1 hops of `seed` (receiver =
+    query), computed node set by node set with the oracle's kNN over the
+    full cloud, as an oracle Graph over all N nodes whose other rows are
+    empty.  The L-hop in-cone of the seed in it equals its in-cone in the
+    full multi-scale graph, whose whole construction takes minutes at 4M
+    points."""
+    pos, le = case.inp.pos, case.levels
+    seen = np.zeros(case.N, dtype=bool)
+    seen[seed] = True
+    frontier = np.array([seed], dtype=np.int64)
+    recv, send = [], []
+    for _ in range(case.L):  # rows of hops 0 .. L-1
+        for lvl, n_l in enumerate(le):
+            q = frontier[frontier < n_l]
+            if len(q) == 0:
+                continue
+            nb = og.knn(pos, q, n_l, case.k_intra, trees[n_l])
+            recv.append(np.repeat(q, case.k_intra))
+            send.append(nb.reshape(-1).astype(np.int64))
+            if lvl >= 1 and case.k_cross > 0:
+                nb = og.knn(pos, q, le[lvl - 1], case.k_cross, trees[le[lvl - 1]])
+                recv.append(np.repeat(q, case.k_cross))
+                send.append(nb.reshape(-1).astype(np.int64))
+        new = np.unique(np.concatenate(send))
+        new = new[~seen[new]]
+        seen[new] = True
+        frontier = new
+    return og.Graph(case.N, np.concatenate(recv), np.concatenate(send))

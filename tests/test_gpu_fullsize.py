@@ -13,7 +13,7 @@ benchmark times.
 import numpy as np
 import pytest
 
-from cases import Case, log, rel_l2
+from cases import Case, cone_graph, log, rel_l2
 from oracle import graph as og
 from oracle import model as om
 from oracle import partition as opart
@@ -142,3 +142,35 @@ def test_graph_replay_equals_eager(api, ctx):
         r.step()
         torch.cuda.synchronize()
         assert torch.equal(r.dp, g0)
+
+
+def test_fullsize_car_4m_sampled_outputs(api, ctx):
+    """The 4M-point car recipe at H = 256 (BF16, 15 layers) as one batch:
+    outputs of sampled nodes against the oracle through their 15-hop
+    in-cones, and the kNN rows of every node of those cones bit for bit."""
+    from scipy.spatial import cKDTree
+    case = Case(5, precision="bf16")
+    log(f"full-size car: N={case.N}")
+    r = Run(api, ctx, case)
+    r.ctx.forward(r.model, r.p, r.ps, r.part_ids, r.node_in, r.pos, case.inp.edge_norm, r.out, keep_tape=False)
+    torch.cuda.synchronize()
+    y = r.out.cpu().numpy()
+    assert np.isfinite(y).all()
+    rp, col = r.g.export()
+    pos64 = case.inp.pos.astype(np.float64)
+    trees = {n_l: cKDTree(pos64[:n_l]) for n_l in case.levels}
+    rng = np.random.default_rng(99)
+    for s in np.sort(rng.choice(case.N, 2, replace=False)):
+        G = cone_graph(case, int(s), trees)
+        rows = np.flatnonzero(np.diff(G.row_ptr) > 0)
+        for q in rows:
+            assert (col[rp[q]:rp[q + 1]] == G.col[G.row_ptr[q]:G.row_ptr[q + 1]]).all(), q
+        c = opart.in_cone(G, [s], case.L)
+        yo = om.forward(case.desc, case.params.astype(np.float64), c.graph, case.inp.node_in[c.gid],
+                        case.inp.pos[c.gid], case.inp.edge_norm)
+        ya = om.forward(case.desc, om.amp_cast(case.desc, case.params), c.graph, case.inp.node_in[c.gid],
+                        case.inp.pos[c.gid], case.inp.edge_norm)
+        e, ea = rel_l2(y[s], yo[0]), rel_l2(y[s], ya[0])
+        log(f"  seed {s}: in-cone {len(c.gid)} nodes, {len(rows)} kNN rows bit-exact, rel-L2 {e:.2e} "
+            f"(cast weights {ea:.2e})")
+        assert e <= 2e-2 and ea <= 2e-2

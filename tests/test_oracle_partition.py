@@ -93,3 +93,21 @@ def test_in_cone_gives_single_outputs():
     c = opart.in_cone(G, seeds, L)
     y = om.forward(d, blob, c.graph, node_in[c.gid], pos[c.gid], en)
     assert np.allclose(y[:3], y_f[seeds], rtol=1e-12, atol=1e-12)
+
+
+def test_lazy_in_cone_equals_full_graph_cone():
+    """The test helper that builds a seed's in-cone from kNN queries of the
+    cone's own nodes (used at 4M points, where the whole graph is too slow
+    to build) gives the same cone, node for node and edge for edge, as the
+    full multi-scale graph."""
+    from scipy.spatial import cKDTree
+    from cases import Case, cone_graph
+    case = Case(5, levels=(300, 1200, 4000), layers=4)
+    G = case.oracle_graph()
+    pos64 = case.inp.pos.astype(np.float64)
+    trees = {n: cKDTree(pos64[:n]) for n in case.levels}
+    for s in (0, 17, 3999):
+        a = opart.in_cone(G, [s], case.L)
+        b = opart.in_cone(cone_graph(case, s, trees), [s], case.L)
+        assert (a.gid == b.gid).all() and (a.hop == b.hop).all()
+        assert (a.graph.row_ptr == b.graph.row_ptr).all() and (a.graph.col == b.graph.col).all()
