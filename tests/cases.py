@@ -124,17 +124,18 @@ def check_step(case: Case, out, loss, grad, refs) -> str:
             f"vs cast weights: out {e_out_a:.2e} grad {rel_l2(grad, g_a):.2e} worst {worst_a}")
 
 
-def cone_graph(case, seed, trees):
-    """The in-lists of every node within L - 1 hops of `seed` (receiver =
-    query), computed node set by node set with the oracle's kNN over the
-    full cloud, as an oracle Graph over all N nodes whose other rows are
-    empty.  The L-hop in-cone of the seed in it equals its in-cone in the
-    full multi-scale graph, whose whole construction takes minutes at 4M
-    points."""
+def cone_graph(case, seeds, trees):
+    """The in-lists of every node within L - 1 hops of the seed node(s)
+    (receiver = query), computed node set by node set with the oracle's kNN
+    over the full cloud, as an oracle Graph over all N nodes whose other
+    rows are empty.  The L-hop in-cone of the seeds in it (a sampled output,
+    or a partition with its halo) equals their in-cone in the full
+    multi-scale graph, whose whole construction takes minutes at 4M points.
+    trees: {candidate count: cKDTree over those points} for every level."""
     pos, le = case.inp.pos, case.levels
+    frontier = np.unique(np.atleast_1d(np.asarray(seeds, dtype=np.int64)))
     seen = np.zeros(case.N, dtype=bool)
-    seen[seed] = True
-    frontier = np.array([seed], dtype=np.int64)
+    seen[frontier] = True
     recv, send = [], []
     for _ in range(case.L):  # rows of hops 0 .. L-1
         for lvl, n_l in enumerate(le):

@@ -13,7 +13,7 @@ benchmark times.
 import numpy as np
 import pytest
 
-from cases import Case, cone_graph, log, rel_l2
+from cases import Case, check_step, cone_graph, log, rel_l2
 from oracle import graph as og
 from oracle import model as om
 from oracle import partition as opart
@@ -174,3 +174,32 @@ def test_fullsize_car_4m_sampled_outputs(api, ctx):
         log(f"  seed {s}: in-cone {len(c.gid)} nodes, {len(rows)} kNN rows bit-exact, rel-L2 {e:.2e} "
             f"(cast weights {ea:.2e})")
         assert e <= 2e-2 and ea <= 2e-2
+
+
+def test_fullsize_partition_gradient(api, ctx):
+    """One partition of the 1M-point, 24-part workload (its smallest, with
+    its 15-hop halo; FP32, 15 layers) in the configuration the benchmark
+    runs it: the partition's nodes against the oracle's RCB and halo, and
+    its outputs, loss and every gradient tensor G_p (before accumulation,
+    with the global normaliser) against the oracle's step on it."""
+    from scipy.spatial import cKDTree
+    case = Case(4, precision="fp32")
+    sizes = case.inp.part_sizes
+    p = int(np.argmin(sizes))
+    log(f"full-size partition {p} of {len(sizes)}: {sizes[p]} inner nodes of {case.N}")
+    g = ctx.build_knn(dev(case.inp.pos), case.levels, case.k_intra, case.k_cross)
+    ps = api.Partset.halo(g, case.inp.pos, sizes, case.L)
+    r = Run(api, ctx, case, part_ids=(p,), ps=ps, g=g)
+    r.step()
+    torch.cuda.synchronize()
+    inner = np.flatnonzero(opart.rcb(case.inp.pos, sizes) == p)
+    pos64 = case.inp.pos.astype(np.float64)
+    trees = {n_l: cKDTree(pos64[:n_l]) for n_l in case.levels}
+    P = opart.Part(cone_graph(case, inner, trees), inner, case.L)
+    x = ps.export(p)
+    assert (x["gid"] == P.gid).all() and (x["col"] == P.graph.col).all()
+    log(f"  {len(P.gid)} local nodes, {P.graph.n_edges} edges: partition bit-exact")
+    refs = (om.step_part(case.desc, case.params.astype(np.float64), P, case.inp.node_in, case.inp.pos,
+                         case.inp.edge_norm, case.inp.targets, case.N), None)
+    y = r.out.cpu().numpy()[P.gid[: P.n_inner]]
+    log("  " + check_step(case, y, float(r.loss.item()), r.dp.cpu().numpy(), refs))
