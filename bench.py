@@ -138,7 +138,7 @@ def cpu_baseline(cfg_idx: int, layers: int, hidden: int):
 
 
 def study(args):
-    """Memory studies on one GPU, one partition per batch (Sec. V.F.1-2).
+    """Studies on one GPU, one partition per batch (Sec. V.F.1-2, III.D).
 
     offload: the 3-level 400k-point ellipsoid in two halo partitions, with
     the per-layer checkpoints on the device and offloaded to host memory.
@@ -155,6 +155,8 @@ def study(args):
     H, L = cfg.hidden, cfg.layers
     dev = torch.device("cuda:0")
     to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    if args.study == "inference":
+        return study_inference(args, cfg, to)
     if args.study == "offload":
         plan = [("3-level", cfg.levels, [2])]
     else:
@@ -205,6 +207,67 @@ def study(args):
                 del ctx
 
 
+def study_inference(args, cfg, to):
+    """Inference and the optimizer on the 400k-point 3-level graph (Sec. III.D,
+    V.D): forward without a tape over the whole graph and over 4 halo
+    partitions one at a time (halo rows dropped, inner rows re-assembled),
+    and a full training step with the Adam update.  One JSON line each."""
+    import torch
+
+    from paper_2411_17164_amd import api
+    from synth import init_params, make_inputs
+
+    H, L = cfg.hidden, cfg.layers
+    inp = make_inputs(cfg)
+    pos, node_in, tgt = to(inp.pos), to(inp.node_in), to(inp.targets)
+    ctx = api.Context(0)
+    g = ctx.build_knn(pos, [int(x) for x in inp.level_end], cfg.k_intra, cfg.k_cross)
+    N, E = g.info()
+    model = api.Model(H, L, precision="bf16")
+    entries = [(kind, shape) for (_, _, _, kind, shape, _) in model.param_tensors()]
+    params = to(init_params(entries, cfg.seed("weights")))
+    out = torch.zeros(N, 4, device=params.device)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps * 1e3
+
+    for P in (1, 4):
+        sizes = None if P == 1 else [N // P + (1 if i < N % P else 0) for i in range(P)]
+        ps = api.Partset.halo(g, inp.pos, sizes, L)
+        E_proc = sum(ps.info(p)[2] for p in range(P))
+
+        def infer():
+            for p in range(P):
+                ctx.forward(model, params, ps, [p], node_in, pos, inp.edge_norm, out, keep_tape=False)
+
+        ms = timed(infer)
+        print(json.dumps({"study": "inference", "graph": "3-level", "nodes": N, "edges": E, "partitions": P,
+                          "processed_edges": E_proc, "ms_per_forward": round(ms, 2),
+                          "edge_updates_per_s": E * L / (ms * 1e-3), "dtype": "bf16", "data": "synthetic"}),
+              flush=True)
+    full = api.Partset.halo(g, inp.pos, None, L)
+    d_out, loss = torch.zeros_like(out), torch.zeros(1, device=out.device)
+    d_params = torch.zeros_like(params)
+    opt = api.Adam(ctx, params, clip_norm=32.0)
+
+    def train():
+        ctx.forward(model, params, full, [0], node_in, pos, inp.edge_norm, out, keep_tape=True)
+        ctx.mse_grad(out, tgt, N, d_out, loss)
+        ctx.backward(model, params, d_out, d_params)
+        opt.step(d_params, api.cosine_lr(opt.t, 1000, 1e-3, 1e-6))
+
+    ms = timed(train)
+    print(json.dumps({"study": "train", "graph": "3-level", "nodes": N, "edges": E, "ms_per_step": round(ms, 2),
+                      "edge_updates_per_s": E * L / (ms * 1e-3), "loss": float(loss.item()), "dtype": "bf16",
+                      "data": "synthetic"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,7 +286,7 @@ def main():
                     help="partitions per batch (wave) for partitioned workloads (0 = all in one batch)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB device copy first (to scale HBM counters)")
-    ap.add_argument("--study", choices=["offload", "memory"],
+    ap.add_argument("--study", choices=["offload", "memory", "inference"],
                     help="memory studies instead of the benchmark line (one JSON line per run)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
