@@ -38,6 +38,10 @@ WORKLOADS = {
     "car-ms-4m-16p": 5,
     "car-ms-2m-21p-h512": 6,
 }
+# partitions per batch when --wave-parts is not given: every part in one batch
+# where its tape and workspace fit in HBM (288 GB), else waves of this many
+# (about 90 GB at H = 256 and 110 GB at H = 512)
+DEFAULT_WAVE_PARTS = {"car-ms-4m-16p": 2, "car-ms-2m-21p-h512": 3}
 
 
 def log(msg):
@@ -283,7 +287,8 @@ def main():
     ap.add_argument("--edge-waves", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tiles")
     ap.add_argument("--wave-parts", type=int, default=0,
-                    help="partitions per batch (wave) for partitioned workloads (0 = all in one batch)")
+                    help="partitions per batch (wave) for partitioned workloads (0 = the workload's default: "
+                         "all in one batch where it fits in HBM)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB device copy first (to scale HBM counters)")
     ap.add_argument("--study", choices=["offload", "memory", "inference"],
@@ -330,7 +335,7 @@ def main():
     t_part = time.perf_counter() - t0
     infos = [ps.info(p) for p in range(n_parts)]
     E_proc = int(sum(i[2] for i in infos))
-    wp = args.wave_parts if args.wave_parts > 0 else n_parts
+    wp = args.wave_parts if args.wave_parts > 0 else DEFAULT_WAVE_PARTS.get(args.workload, n_parts)
     waves = [list(range(i, min(i + wp, n_parts))) for i in range(0, n_parts, wp)]
     wave_sizes = [(sum(infos[p][0] + infos[p][1] for p in w), sum(infos[p][2] for p in w)) for w in waves]
     log(f"[bench] graph N={N} E={E} (processed {E_proc}, {n_parts} parts in {len(waves)} waves) "
