@@ -283,10 +283,10 @@ class Adam:
     def step(self, grad: torch.Tensor, lr: float, stream=None):
         if grad.numel() != self.params.numel():
             raise ValueError("size mismatch")
-        self.t += 1
         check(lib.xmgn_adam_step(self.ctx._h, _dev(self.params), _dev(grad), _dev(self.m), _dev(self.v),
-                                 self.params.numel(), self.t, lr, self.betas[0], self.betas[1], self.eps,
+                                 self.params.numel(), self.t + 1, lr, self.betas[0], self.betas[1], self.eps,
                                  self.clip_norm, _dev(self.norm), _stream(stream)))
+        self.t += 1
 
 
 class ProcessorFn(torch.autograd.Function):
