@@ -62,10 +62,13 @@ def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: bool = False,
         # receiver: h_r read, m (FP32) written
         return E * (3 + (1 if ztape else 0)) * H * s + n * (H * s + 4 * H)
     if name == "edge_bwd":
-        # per edge: h_s (or z), e, de' (FP32) read; de (FP32), da written
-        # (+ z, du when not fused); per receiver: h_r (not with ztape), dm
-        # (FP32) read, S_r (FP32) written
-        per_edge = (2 + 1 + (0 if fused else 2)) * H * s + 4 * H * (1 + de_in)
+        # per edge: de' (FP32) read, de (FP32) and da written, and
+        #   fused, z on the tape:   z, e read
+        #   fused, recompute:       h_s, e read
+        #   unfused, z on the tape: z read, du written
+        #   unfused, recompute:     h_s, e read, z, du written
+        # per receiver: h_r (not with ztape), dm (FP32) read, S_r (FP32) written
+        per_edge = (3 if (fused or ztape) else 5) * H * s + 4 * H * (1 + de_in)
         return E * per_edge + n * ((0 if ztape else H * s) + 8 * H)
     if name == "node_fwd":
         return n * (2 * H * s + 4 * H)
@@ -414,7 +417,7 @@ def main():
     # dominant kernel of the BF16 step and its roofline
     kern = bf["kernels"]
     fused = H == 128  # the BF16 edge adjoint fuses its weight gradients at H = 128
-    ztape = fused  # ... and, with ReLU, reads z from the forward's tape
+    ztape = cfg.activation == "relu"  # with ReLU it reads z from the forward's tape
     de_in = (L - 1) / L
     kb = lambda k, n_w, e_w: kernel_bytes(k, n_w, e_w, H, 2, fused, de_in, ztape)  # noqa: E731
     dom = max((k for k in kern if kb(k, N, E) is not None), key=lambda k: kern[k][0])

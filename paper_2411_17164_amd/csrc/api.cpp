@@ -521,7 +521,7 @@ struct xmgn_ctx {
   DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, wfused, redtmp, lossp;
   DBuf xe;    // edge features of the forward [E][4]
   DBuf optp;  // optimizer: per-workgroup squared-norm partials (FP64)
-  DBuf zt;  // hidden activations of the edge MLPs [L][E][H] (edge_z_tape forms, full tape)
+  DBuf zt;  // hidden activations of the edge MLPs [L][E][H] (BF16 ReLU forms, device-resident tape)
   bool tape_z = false;
   // per-kernel timing
   bool timing = false;
@@ -1244,11 +1244,8 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     const MlpW we = weights(c, d, params, 2 + 2 * l, 2, l);
     EdgeBwdOut eo{de_out->as<float>(), c->Sr.as<float>(), c->fa.p, c->fb.p, c->fc.p, part,
                   fw ? c->wfused.as<float>() : nullptr};
-    {
-      KT("edge_bwd");
-      const void* zt = edge_z_tape(se) ? zslot(c, d, l) : nullptr;  // the forward's z, when it kept it
-      launch_edge_bwd(se, b, we, hl(l), eslot(c, d, l), zt, de_in, c->dm.as<float>(), eo, st);
-    }
+    const void* zt = edge_z_tape(se) ? zslot(c, d, l) : nullptr;  // the forward's z, when it kept it
+    { KT("edge_bwd"); launch_edge_bwd(se, b, we, hl(l), eslot(c, d, l), zt, de_in, c->dm.as<float>(), eo, st); }
     VecSeg es[4] = {{0, (int)H, P(2, l, 1)}, {(int)H, (int)H, P(2, l, 3)}, {2 * (int)H, (int)H, P(2, l, 4)},
                     {3 * (int)H, (int)H, P(2, l, 5)}};
     launch_vec_reduce(part, se.grid, 4 * (int)H, es, 4, rt, st);
@@ -1267,8 +1264,8 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     if (!fw) {
       wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, eslot(c, d, l), 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H,
                    P(2, l, 0) + 2 * H, 3 * (int)H), c->wpart, st);
-      wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, c->fc.p, 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H,
-                   P(2, l, 2), (int)H), c->wpart, st);
+      wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, zt ? zt : c->fc.p, 0, (int)H, 0, nullptr, (int)E, (int)H,
+                   (int)H, P(2, l, 2), (int)H), c->wpart, st);
     }
     de_in = de_out->as<float>();
     std::swap(de_out, de_other);

@@ -95,8 +95,9 @@ bool edge_bwd_fuses_wgrad(const Shape& s);
 size_t reduce_tmp_floats(int max_cols);
 void launch_wgrad_reduce(const float* partial, int n_chunks, int M_valid, int N, float* dst, int ldd, int MN,
                          float* tmp, hipStream_t st);
-// True when the edge adjoint reads z from the forward's tape (BF16, H = 128,
-// ReLU) instead of recomputing it; zt is then that tape (else NULL).
+// True when the edge adjoint reads z from the forward's tape (BF16, ReLU)
+// instead of recomputing it; zt is then that tape (else NULL), and the
+// unfused form does not write o.z (its dW2 product reads the tape).
 bool edge_z_tape(const Shape& s);
 void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
                      const void* zt, const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st);

@@ -152,9 +152,10 @@ struct EdgeBwdLds {
   static constexpr size_t bytes = XS + ZS + 2 * WS + 2 * NW * MT * 4 + 2 * MT * 4;
 };
 
-// ZT (BF16, H = 128, ReLU): z of every edge comes from the forward's tape
-// (zt) instead of being recomputed -- no gather of h_r, h_s and no first
-// product; ReLU's derivative is [z > 0], exactly [a > 0].
+// ZT (BF16, ReLU): z of every edge comes from the forward's tape (zt)
+// instead of being recomputed -- no gather of h_r, h_s and no first
+// product; ReLU's derivative is [z > 0], exactly [a > 0].  Unfused (H = 256,
+// 512), the dW2 product then reads z from the tape too.
 template <typename T, int H, int MT, int ACT, int AGG, int FW, int NW, int ZT>
 __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW>::bytes, NW)) void k_edge_bwd(
     BatchView b, MlpW w, const T* __restrict__ h, const T* __restrict__ e, const T* __restrict__ zt,
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
   constexpr size_t XS = L::XS, ZS = L::ZS, WS = L::WS;
   constexpr int LDW = L::LDW, LDF = L::LDF;
   static_assert(!FW || (sizeof(T) == 2 && H == 128), "fused weight gradients: BF16, H = 128");
-  static_assert(!ZT || (FW && ACT == 0), "z from the tape: fused BF16 ReLU form");
+  static_assert(!ZT || (sizeof(T) == 2 && ACT == 0), "z from the tape: BF16 ReLU form");
   static_assert((size_t)MT * LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
   static_assert(!FW || (size_t)H * 4 <= 2 * H * sizeof(T), "FP32 rows must leave the e columns intact");
   __shared__ __align__(16) unsigned char smem[L::bytes];
@@ -208,8 +209,9 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
     }
     __syncthreads();
     if constexpr (ZT) {
-      // z rows into zs and e rows into the e columns of xs, one batch of loads
-      constexpr int E8 = 8, CPR = H / E8, TOT = 2 * MT * CPR, IT = TOT / (64 * NW);
+      // z rows into zs and (fused: for dW1's e-block) e rows into the e
+      // columns of xs, one batch of loads
+      constexpr int E8 = 8, CPR = H / E8, TOT = (FW ? 2 : 1) * MT * CPR, IT = TOT / (64 * NW);
       static_assert(TOT % (64 * NW) == 0, "whole steps of the workgroup");
       uint4 v[IT];
 #pragma unroll
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
         ne, de_in != nullptr, [&](int i, int q) { return *(const float4*)(dm + (size_t)rs[i] * H + 4 * q); },
         [&](int i, int q) { return *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q); },
         [&](int i, int q, const float4& v) { *(float4*)(ft + i * LDF + 4 * q) = v; });
-    if constexpr (!FW) lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.z + (size_t)e0 * H, H, [](int i) { return i; });
+    if constexpr (!FW && !ZT) lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.z + (size_t)e0 * H, H, [](int i) { return i; });
     __syncthreads();
     f32x4 g[MB][NB];
 #pragma unroll
@@ -1103,7 +1105,7 @@ static void edge_bwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const
                         const void* zt, const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st) {
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
     constexpr int FW = (sizeof(T) == 2 && H == 128) ? 1 : 0;
-    constexpr int ZT = (FW && ACT == 0) ? 1 : 0;
+    constexpr int ZT = (sizeof(T) == 2 && ACT == 0) ? 1 : 0;
     if constexpr (edge_bwd_fits<T, H, MT>()) {
       if (zt && !ZT) {
         g_config_error = 1;
@@ -1128,7 +1130,7 @@ static void edge_bwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const
   }))));
 }
 
-bool edge_z_tape(const Shape& s) { return s.prec == 1 && s.H == 128 && s.act == 0; }
+bool edge_z_tape(const Shape& s) { return s.prec == 1 && s.act == 0; }
 
 void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
                      const void* zt, const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st) {
