@@ -429,12 +429,19 @@ def main():
     by = tot_bytes / per_step
     fl = tot_flops / per_step
     achieved = by / (avg_ms * 1e-3) / 1e9
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+    tflops = fl / (avg_ms * 1e-3) / 1e12
+    # the bound is the roof the kernel's arithmetic intensity meets first: HBM
+    # below the BF16 ridge point (peak flops / peak bandwidth), MFMA above it
+    mfma_bound = fl / by > BF16_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    roofline = {"kernel": dom, "bound": "mfma" if mfma_bound else "hbm",
+                "achieved": round(tflops, 2) if mfma_bound else round(achieved, 1),
+                "peak": BF16_PEAK_TFLOPS if mfma_bound else HBM_PEAK_GBS,
+                "unit": "TFLOP/s" if mfma_bound else "GB/s",
+                "frac": round(tflops / BF16_PEAK_TFLOPS if mfma_bound else achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args.workload, dom), "source_hash": kernel_source_hash(),
                 "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": by,
-                "mfma_tflops": round(fl / (avg_ms * 1e-3) / 1e12, 2),
-                "mfma_frac_bf16": round(fl / (avg_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4)}
+                "algorithmic_flops_per_launch": fl, "hbm_gbs": round(achieved, 1),
+                "mfma_tflops": round(tflops, 2), "mfma_frac_bf16": round(tflops / BF16_PEAK_TFLOPS, 4)}
     line = {
         "metric": "processor edge-updates/s fwd+bwd, BF16 vs FP32 plain, 15 layers, 1 MI355X",
         "value": value,
