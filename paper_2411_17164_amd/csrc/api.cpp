@@ -521,8 +521,9 @@ struct xmgn_ctx {
   DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, wfused, redtmp, lossp;
   DBuf xe;    // edge features of the forward [E][4]
   DBuf optp;  // optimizer: per-workgroup squared-norm partials (FP64)
-  DBuf zt;  // hidden activations of the edge MLPs [L][E][H] (BF16 ReLU forms, device-resident tape)
-  bool tape_z = false;
+  DBuf zt;  // hidden activations of the edge MLPs [L][E][H] (BF16 forms, device-resident tape)
+  DBuf at;  // their pre-activations [L][E][H] (BF16 SiLU forms, device-resident tape)
+  bool tape_z = false, tape_a = false;
   // per-kernel timing
   bool timing = false;
   std::vector<std::string> tnames;
@@ -688,7 +689,7 @@ extern "C" xmgn_status xmgn_ctx_memory(const xmgn_ctx* c, int64_t* bytes) {
   const DBuf* bufs[] = {&c->batch.ints, &c->jobs_dev, &c->blob, &c->h, &c->e, &c->m, &c->dhA, &c->dhMid,
                         &c->dm, &c->Sr, &c->Ss, &c->deA, &c->deB, &c->fa, &c->fb, &c->fc, &c->fd,
                         &c->dy, &c->part, &c->wpart, &c->wfused, &c->redtmp, &c->lossp, &c->xe, &c->zt,
-                        &c->optp};
+                        &c->at, &c->optp};
   int64_t t = 0;
   for (const DBuf* b : bufs) t += (int64_t)b->bytes;
   *bytes = t;
@@ -713,6 +714,7 @@ extern "C" xmgn_status xmgn_ctx_set_offload(xmgn_ctx* c, int32_t enable) {
   c->e.release();
   c->m.release();
   c->zt.release();
+  c->at.release();
   if (!c->offload) c->ht.release();
   c->fwd_valid = false;
   return XMGN_OK;
@@ -932,7 +934,7 @@ static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32
   return XMGN_OK;
 }
 
-static xmgn_status ensure_tape(xmgn_ctx* c, const xmgn_model_desc* d, bool full, bool z) {
+static xmgn_status ensure_tape(xmgn_ctx* c, const xmgn_model_desc* d, bool full, bool z, bool a) {
   const size_t ts = tsize(d), H = d->hidden, L = d->n_layers;
   const size_t n = c->batch.n, E = c->batch.E;
   const int mode = !full ? 0 : c->offload ? 2 : 1;
@@ -943,8 +945,11 @@ static xmgn_status ensure_tape(xmgn_ctx* c, const xmgn_model_desc* d, bool full,
   if (xmgn_status s = c->m.ensure(sm * n * H * 4)) return s;
   // the offloaded tape keeps no z: the edge adjoint recomputes it
   c->tape_z = mode == 1 && z;
+  c->tape_a = c->tape_z && a;
   if (c->tape_z)
     if (xmgn_status s = c->zt.ensure(L * E * H * ts)) return s;
+  if (c->tape_a)
+    if (xmgn_status s = c->at.ensure(L * E * H * ts)) return s;
   if (mode == 2)
     if (xmgn_status s = c->ht.ensure(((L + 1) * n + L * E) * H * ts + L * n * H * 4)) return s;
   c->tape_mode = mode;
@@ -963,6 +968,10 @@ static void* eslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
 static void* zslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   if (!c->tape_z) return nullptr;
   return (char*)c->zt.p + (size_t)l * c->batch.E * d->hidden * tsize(d);
+}
+static void* aslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
+  if (!c->tape_a) return nullptr;
+  return (char*)c->at.p + (size_t)l * c->batch.E * d->hidden * tsize(d);
 }
 static float* mslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   const size_t s = c->tape_mode == 1 ? l : c->tape_mode == 2 ? l % 2 : 0;
@@ -1045,7 +1054,7 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
   const Shape s = make_shape(c, d);
   if (xmgn_status r = ensure_batch(c, ps, part_ids, n_batch, s.mt_edge)) return r;
   if (xmgn_status r = ensure_wplan(c, d)) return r;
-  if (xmgn_status r = ensure_tape(c, d, keep_tape != 0, edge_z_tape(s))) return r;
+  if (xmgn_status r = ensure_tape(c, d, keep_tape != 0, edge_z_tape(s), edge_a_tape(s))) return r;
   const BatchView& b = c->batch.view;
   const int L = d->n_layers;
   g_config_error = 0;
@@ -1067,7 +1076,7 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
   for (int l = 0; l < L; ++l) {
     if (off && l >= 1) HIPCHK(hipStreamWaitEvent(st, copies[l - 1], 0));
     { KT("edge_fwd"); launch_edge_fwd(s, b, weights(c, d, params, 2 + 2 * l, 2, l), hslot(c, d, l), eslot(c, d, l),
-                    l + 1 < L ? eslot(c, d, l + 1) : nullptr, mslot(c, d, l), zslot(c, d, l), st); }
+                    l + 1 < L ? eslot(c, d, l + 1) : nullptr, mslot(c, d, l), zslot(c, d, l), aslot(c, d, l), st); }
     { KT("node_fwd"); launch_node_fwd(s, b, weights(c, d, params, 3 + 2 * l, 3, l), hslot(c, d, l), mslot(c, d, l), hslot(c, d, l + 1),
                     st); }
     if (off)
@@ -1245,7 +1254,8 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     EdgeBwdOut eo{de_out->as<float>(), c->Sr.as<float>(), c->fa.p, c->fb.p, c->fc.p, part,
                   fw ? c->wfused.as<float>() : nullptr};
     const void* zt = edge_z_tape(se) ? zslot(c, d, l) : nullptr;  // the forward's z, when it kept it
-    { KT("edge_bwd"); launch_edge_bwd(se, b, we, hl(l), eslot(c, d, l), zt, de_in, c->dm.as<float>(), eo, st); }
+    const void* at = edge_a_tape(se) ? aslot(c, d, l) : nullptr;  // ... and a (SiLU)
+    { KT("edge_bwd"); launch_edge_bwd(se, b, we, hl(l), eslot(c, d, l), zt, at, de_in, c->dm.as<float>(), eo, st); }
     VecSeg es[4] = {{0, (int)H, P(2, l, 1)}, {(int)H, (int)H, P(2, l, 3)}, {2 * (int)H, (int)H, P(2, l, 4)},
                     {3 * (int)H, (int)H, P(2, l, 5)}};
     launch_vec_reduce(part, se.grid, 4 * (int)H, es, 4, rt, st);

@@ -69,9 +69,10 @@ void launch_enc_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, cons
 void launch_edge_feat(const BatchView& b, const float* pos, EdgeNorm en, float* xe, hipStream_t st);
 void launch_enc_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const float* xe, void* e0,
                          hipStream_t st);
-// z_out (or NULL): the hidden activation of every edge, for edge_z_tape forms.
+// z_out (or NULL): the hidden activation of every edge, for edge_z_tape forms;
+// a_out (or NULL): its pre-activation, for edge_a_tape forms.
 void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h,
-                     const void* e, void* e_out, float* m, void* z_out, hipStream_t st);
+                     const void* e, void* e_out, float* m, void* z_out, void* a_out, hipStream_t st);
 void launch_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h,
                      const float* m, void* h_out, hipStream_t st);
 void launch_dec_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, float* out,
@@ -95,12 +96,16 @@ bool edge_bwd_fuses_wgrad(const Shape& s);
 size_t reduce_tmp_floats(int max_cols);
 void launch_wgrad_reduce(const float* partial, int n_chunks, int M_valid, int N, float* dst, int ldd, int MN,
                          float* tmp, hipStream_t st);
-// True when the edge adjoint reads z from the forward's tape (BF16, ReLU)
-// instead of recomputing it; zt is then that tape (else NULL), and the
-// unfused form does not write o.z (its dW2 product reads the tape).
+// True when the edge adjoint reads z from the forward's tape (BF16) instead
+// of recomputing it; zt is then that tape (else NULL), and the unfused form
+// does not write o.z (its dW2 product reads the tape).
 bool edge_z_tape(const Shape& s);
+// True when the forms that read z from the tape also need a (SiLU); at is
+// then the tape of pre-activations (else NULL).
+bool edge_a_tape(const Shape& s);
 void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
-                     const void* zt, const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st);
+                     const void* zt, const void* at, const float* de_in, const float* dm, const EdgeBwdOut& o,
+                     hipStream_t st);
 
 struct NodeBwdOut {
   float* dh_mid;   // [n][H]

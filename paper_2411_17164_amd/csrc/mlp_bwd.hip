@@ -152,21 +152,23 @@ struct EdgeBwdLds {
   static constexpr size_t bytes = XS + ZS + 2 * WS + 2 * NW * MT * 4 + 2 * MT * 4;
 };
 
-// ZT (BF16, ReLU): z of every edge comes from the forward's tape (zt)
-// instead of being recomputed -- no gather of h_r, h_s and no first
-// product; ReLU's derivative is [z > 0], exactly [a > 0].  Unfused (H = 256,
-// 512), the dW2 product then reads z from the tape too.
+// ZT (BF16): z of every edge comes from the forward's tape (zt) instead of
+// being recomputed -- no gather of h_r, h_s and no first product.  ReLU's
+// derivative is [z > 0], exactly [a > 0]; SiLU's takes a from the tape of
+// pre-activations (at, BF16).  Unfused (H = 256, 512), the dW2 product then
+// reads z from the tape too.
 template <typename T, int H, int MT, int ACT, int AGG, int FW, int NW, int ZT>
 __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW>::bytes, NW)) void k_edge_bwd(
     BatchView b, MlpW w, const T* __restrict__ h, const T* __restrict__ e, const T* __restrict__ zt,
-    const float* __restrict__ de_in, const float* __restrict__ dm, EdgeBwdOut o, float eps) {
+    const T* __restrict__ at, const float* __restrict__ de_in, const float* __restrict__ dm, EdgeBwdOut o,
+    float eps) {
   using D = BD<T, H, NW>;
   using L = EdgeBwdLds<T, H, MT, FW, NW>;
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t XS = L::XS, ZS = L::ZS, WS = L::WS;
   constexpr int LDW = L::LDW, LDF = L::LDF;
   static_assert(!FW || (sizeof(T) == 2 && H == 128), "fused weight gradients: BF16, H = 128");
-  static_assert(!ZT || (sizeof(T) == 2 && ACT == 0), "z from the tape: BF16 ReLU form");
+  static_assert(!ZT || sizeof(T) == 2, "z from the tape: BF16 forms");
   static_assert((size_t)MT * LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
   static_assert(!FW || (size_t)H * 4 <= 2 * H * sizeof(T), "FP32 rows must leave the e columns intact");
   __shared__ __align__(16) unsigned char smem[L::bytes];
@@ -209,23 +211,29 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
     }
     __syncthreads();
     if constexpr (ZT) {
-      // z rows into zs and (fused: for dW1's e-block) e rows into the e
-      // columns of xs, one batch of loads
-      constexpr int E8 = 8, CPR = H / E8, TOT = (FW ? 2 : 1) * MT * CPR, IT = TOT / (64 * NW);
+      // z rows into zs, (fused: for dW1's e-block) e rows into the e columns
+      // of xs and (SiLU) a rows into its first H columns, one batch of loads
+      constexpr int NPART = 1 + (FW ? 1 : 0) + (ACT != 0 ? 1 : 0);
+      constexpr int E8 = 8, CPR = H / E8, TOT = NPART * MT * CPR, IT = TOT / (64 * NW);
       static_assert(TOT % (64 * NW) == 0, "whole steps of the workgroup");
+      auto src = [&](int p) -> const T* { return p == 0 ? zt : (FW && p == 1) ? e : at; };
+      auto dst = [&](int p, int i, int q) -> T* {
+        return p == 0 ? zs + i * D::LDH + q * E8 : (FW && p == 1) ? xs + i * D::LD3 + 2 * H + q * E8
+                                                                  : xs + i * D::LD3 + q * E8;
+      };
       uint4 v[IT];
 #pragma unroll
       for (int k = 0; k < IT; ++k) {
         const int c = (int)threadIdx.x + k * 64 * NW, p = c / (MT * CPR), rem = c - p * (MT * CPR);
         const int i = rem / CPR, q = rem - i * CPR;
         v[k] = uint4{0u, 0u, 0u, 0u};
-        if (i < ne) v[k] = *(const uint4*)((p == 0 ? zt : e) + (size_t)(e0 + i) * H + q * E8);
+        if (i < ne) v[k] = *(const uint4*)(src(p) + (size_t)(e0 + i) * H + q * E8);
       }
 #pragma unroll
       for (int k = 0; k < IT; ++k) {
         const int c = (int)threadIdx.x + k * 64 * NW, p = c / (MT * CPR), rem = c - p * (MT * CPR);
         const int i = rem / CPR, q = rem - i * CPR;
-        *(uint4*)(p == 0 ? zs + i * D::LDH + q * E8 : xs + i * D::LD3 + 2 * H + q * E8) = v[k];
+        *(uint4*)dst(p, i, q) = v[k];
       }
     } else {
       gather_tile<T, D::LD3, MT, 3, H, 64 * NW>(
@@ -236,7 +244,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
     if (t + sch.step < sch.end) nx.load(b, t + sch.step);  // next tile's indices, in flight from here
     __syncthreads();
 
-    // recompute: a, z, u, xhat (ZT: a holds z, whose sign is a's)
+    // recompute: a, z, u, xhat (ZT, ReLU: a holds z, whose sign is a's)
     f32x4 a[MB][NB];
     f32x4 x[MB][NB];
     zero_acc(a);
@@ -246,7 +254,9 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) a[mb][nb][r] = to_f(zs[acc_row(mb, r) * D::LDH + acc_col(n0, nb)]);
+          for (int r = 0; r < 4; ++r)
+            a[mb][nb][r] = ACT == 0 ? to_f(zs[acc_row(mb, r) * D::LDH + acc_col(n0, nb)])
+                                    : to_f(xs[acc_row(mb, r) * D::LD3 + acc_col(n0, nb)]);
     } else if constexpr (FW) {
       wave_gemm<T, MB, NB, 2 * H, D::LD3>(a, xs, W1, 3 * H, n0);  // [h_r ; h_s] blocks from global
       wave_gemm_lds<MB, NB, H, D::LD3>(a, (const bf16*)xs + 2 * H, [&](int k, int nb) {
@@ -1102,27 +1112,28 @@ bool edge_bwd_fuses_wgrad(const Shape& s) { return s.prec == 1 && s.H == 128; }
 
 template <int NW>
 static void edge_bwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
-                        const void* zt, const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st) {
+                        const void* zt, const void* at, const float* de_in, const float* dm, const EdgeBwdOut& o,
+                        hipStream_t st) {
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
     constexpr int FW = (sizeof(T) == 2 && H == 128) ? 1 : 0;
-    constexpr int ZT = (sizeof(T) == 2 && ACT == 0) ? 1 : 0;
+    constexpr int ZT = sizeof(T) == 2 ? 1 : 0;
     if constexpr (edge_bwd_fits<T, H, MT>()) {
-      if (zt && !ZT) {
+      if (zt && (!ZT || (ACT != 0 && !at))) {
         g_config_error = 1;
       } else if (zt) {
         if (s.agg)
-          k_edge_bwd<T, H, MT, ACT, 1, FW, NW, ZT><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e,
-                                                                               (const T*)zt, de_in, dm, o, s.eps);
+          k_edge_bwd<T, H, MT, ACT, 1, FW, NW, ZT><<<s.grid, 64 * NW, 0, st>>>(
+              b, w, (const T*)h, (const T*)e, (const T*)zt, (const T*)at, de_in, dm, o, s.eps);
         else
-          k_edge_bwd<T, H, MT, ACT, 0, FW, NW, ZT><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e,
-                                                                               (const T*)zt, de_in, dm, o, s.eps);
+          k_edge_bwd<T, H, MT, ACT, 0, FW, NW, ZT><<<s.grid, 64 * NW, 0, st>>>(
+              b, w, (const T*)h, (const T*)e, (const T*)zt, (const T*)at, de_in, dm, o, s.eps);
       } else {
         if (s.agg)
           k_edge_bwd<T, H, MT, ACT, 1, FW, NW, 0><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, nullptr,
-                                                                              de_in, dm, o, s.eps);
+                                                                              nullptr, de_in, dm, o, s.eps);
         else
           k_edge_bwd<T, H, MT, ACT, 0, FW, NW, 0><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, nullptr,
-                                                                              de_in, dm, o, s.eps);
+                                                                              nullptr, de_in, dm, o, s.eps);
       }
     } else {
       g_config_error = 1;
@@ -1130,14 +1141,16 @@ static void edge_bwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const
   }))));
 }
 
-bool edge_z_tape(const Shape& s) { return s.prec == 1 && s.act == 0; }
+bool edge_z_tape(const Shape& s) { return s.prec == 1; }
+bool edge_a_tape(const Shape& s) { return s.prec == 1 && s.act != 0; }
 
 void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
-                     const void* zt, const float* de_in, const float* dm, const EdgeBwdOut& o, hipStream_t st) {
+                     const void* zt, const void* at, const float* de_in, const float* dm, const EdgeBwdOut& o,
+                     hipStream_t st) {
   if (s.nw_edge == 8)
-    edge_bwd_nw<8>(s, b, w, h, e, zt, de_in, dm, o, st);
+    edge_bwd_nw<8>(s, b, w, h, e, zt, at, de_in, dm, o, st);
   else
-    edge_bwd_nw<4>(s, b, w, h, e, zt, de_in, dm, o, st);
+    edge_bwd_nw<4>(s, b, w, h, e, zt, at, de_in, dm, o, st);
 }
 
 void launch_node_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const float* m,

@@ -36,11 +36,12 @@ struct EdgeFwdLds {
 };
 
 // z_out (or NULL): the hidden activation z = act(W1 x + b1) of every edge,
-// kept for the adjoint.
+// kept for the adjoint; a_out (or NULL): its pre-activation a = W1 x + b1
+// (SiLU's derivative needs a).
 template <typename T, int H, int MT, int ACT, int AGG, int NW>
 __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::bytes, NW)) void k_edge_fwd(
     BatchView b, MlpW w, const T* __restrict__ h, const T* __restrict__ e, T* __restrict__ e_out,
-    float* __restrict__ m, T* __restrict__ z_out, float eps) {
+    float* __restrict__ m, T* __restrict__ z_out, T* __restrict__ a_out, float eps) {
   using D = Dims<T, H, NW>;
   using L = EdgeFwdLds<T, H, MT, NW>;
   constexpr int MB = MT / 16, NB = D::NB;
@@ -87,10 +88,22 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
         const float bb = w.b1[c];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r] + bb);
+          acc[mb][nb][r] += bb;
           ev[mb][nb][r] = to_f(xs[acc_row(mb, r) * D::LD3 + 2 * H + c]);
         }
       }
+    if (a_out) {  // uniform: the pre-activation goes out through zs first
+      acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
+      __syncthreads();
+      lds_rows_to_global<T, D::LDH>(zs, ne, H, a_out + (size_t)e0 * H, H, [](int i) { return i; });
+      __syncthreads();
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r]);
     acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
     __syncthreads();
     if (z_out) lds_rows_to_global<T, D::LDH>(zs, ne, H, z_out + (size_t)e0 * H, H, [](int i) { return i; });
@@ -479,15 +492,15 @@ constexpr bool edge_fits() {
 
 template <int NW>
 static void edge_fwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e, void* e_out,
-                        float* m, void* z_out, hipStream_t st) {
+                        float* m, void* z_out, void* a_out, hipStream_t st) {
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
     if constexpr (edge_fits<T, H, MT>()) {
       if (s.agg)
         k_edge_fwd<T, H, MT, ACT, 1, NW><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m,
-                                                                     (T*)z_out, s.eps);
+                                                                     (T*)z_out, (T*)a_out, s.eps);
       else
         k_edge_fwd<T, H, MT, ACT, 0, NW><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m,
-                                                                     (T*)z_out, s.eps);
+                                                                     (T*)z_out, (T*)a_out, s.eps);
     } else {
       g_config_error = 1;
     }
@@ -495,12 +508,12 @@ static void edge_fwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const
 }
 
 void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
-                     void* e_out, float* m, void* z_out, hipStream_t st) {
+                     void* e_out, float* m, void* z_out, void* a_out, hipStream_t st) {
   if (b.n_etiles == 0) return;
   if (s.nw_edge == 8)
-    edge_fwd_nw<8>(s, b, w, h, e, e_out, m, z_out, st);
+    edge_fwd_nw<8>(s, b, w, h, e, e_out, m, z_out, a_out, st);
   else
-    edge_fwd_nw<4>(s, b, w, h, e, e_out, m, z_out, st);
+    edge_fwd_nw<4>(s, b, w, h, e, e_out, m, z_out, a_out, st);
 }
 
 void launch_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const float* m,

@@ -2,9 +2,9 @@
 
 The offloaded tape must give the same forward bit for bit, the same
 gradients bit for bit wherever the device-resident tape recomputes the edge
-MLP's hidden activations too (FP32, SiLU), and gradients within 5e-3 of the
-resident tape's where that tape keeps them instead (BF16 ReLU); every run
-meets the parity bar against the FP64 oracle.  Depths 1, 2, 3 and 5 cover every case of which checkpoints stay in
+MLP's hidden activations too (FP32), and gradients within 5e-3 of the
+resident tape's where that tape keeps them instead (BF16); every run meets
+the parity bar against the FP64 oracle.  Depths 1, 2, 3 and 5 cover every case of which checkpoints stay in
 their device slots and which travel."""
 import numpy as np
 import pytest
@@ -69,7 +69,7 @@ def test_offload_matches_device_tape(api, precision, act, layers):
     assert resident.host_memory() == 0
     # one layer: two h slots, one e and one m slot either way
     assert off.memory() < resident.memory() if layers > 1 else off.memory() <= resident.memory()
-    ztape = precision == "bf16" and act == "relu" and case.H == 128
+    ztape = precision == "bf16"  # the resident tape keeps z (and a under SiLU); the offloaded one recomputes
     if not ztape:
         assert (g_a == g_b).all()
     else:
@@ -119,4 +119,6 @@ def test_offload_partitions_and_switching(api):
     assert (y2 == y_full).all() and (g2 == g_full).all()
     ctx.set_offload(True)
     y3, loss3, g3 = step(api, ctx, case, full, [0])
-    assert (y3 == y_full).all() and (g3 == g_full).all()
+    assert (y3 == y_full).all()
+    errs = per_tensor_errors(case, g3, g_full)  # BF16 SiLU: the resident run read z and a from its tapes
+    assert max(errs.values()) <= 5e-3, sorted(errs.items(), key=lambda kv: -kv[1])[:3]
