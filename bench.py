@@ -49,18 +49,20 @@ def log(msg):
 
 
 def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: bool = False, de_in: float = 1.0,
-                 ztape: bool = False) -> float | None:
+                 ztape: bool = False, atape: bool = False) -> float | None:
     """Algorithmic HBM bytes of one launch of a processor kernel: each input
     read once, each output written once (s = bytes per stored latent; FP32
     adjoints are 4 bytes).  `fused`: the edge adjoint accumulates dW2 and the
     e-block of dW1 itself, so z and du are not written.  `de_in`: fraction of
     launches that read an incoming edge adjoint de' (all but the last layer).
+    `atape`: the forward also writes the pre-activation a (SiLU), which the
+    adjoint reads too.
     `ztape`: the forward writes z for the adjoint, which reads it instead of
     h_s and h_r."""
     if name == "edge_fwd":
         # per edge: e and the gathered h_s read, e' (and z) written; per
         # receiver: h_r read, m (FP32) written
-        return E * (3 + (1 if ztape else 0)) * H * s + n * (H * s + 4 * H)
+        return E * (3 + (1 if ztape else 0) + (1 if atape else 0)) * H * s + n * (H * s + 4 * H)
     if name == "edge_bwd":
         # per edge: de' (FP32) read, de (FP32) and da written, and
         #   fused, z on the tape:   z, e read
@@ -68,7 +70,7 @@ def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: bool = False,
         #   unfused, z on the tape: z read, du written
         #   unfused, recompute:     h_s, e read, z, du written
         # per receiver: h_r (not with ztape), dm (FP32) read, S_r (FP32) written
-        per_edge = (3 if (fused or ztape) else 5) * H * s + 4 * H * (1 + de_in)
+        per_edge = ((3 if (fused or ztape) else 5) + (1 if atape else 0)) * H * s + 4 * H * (1 + de_in)
         return E * per_edge + n * ((0 if ztape else H * s) + 8 * H)
     if name == "node_fwd":
         return n * (2 * H * s + 4 * H)
@@ -417,9 +419,10 @@ def main():
     # dominant kernel of the BF16 step and its roofline
     kern = bf["kernels"]
     fused = H == 128  # the BF16 edge adjoint fuses its weight gradients at H = 128
-    ztape = cfg.activation == "relu"  # with ReLU it reads z from the forward's tape
+    ztape = True  # the BF16 edge adjoint reads z from the forward's tape
+    atape = cfg.activation != "relu"  # ... and, under SiLU, a
     de_in = (L - 1) / L
-    kb = lambda k, n_w, e_w: kernel_bytes(k, n_w, e_w, H, 2, fused, de_in, ztape)  # noqa: E731
+    kb = lambda k, n_w, e_w: kernel_bytes(k, n_w, e_w, H, 2, fused, de_in, ztape, atape)  # noqa: E731
     dom = max((k for k in kern if kb(k, N, E) is not None), key=lambda k: kern[k][0])
     avg_ms = kern[dom][0] / kern[dom][1]
     # launches of a processor kernel per step: L per wave (edge/node kernels)
