@@ -286,11 +286,12 @@ xmgn_status xmgn_ctx_memory(const xmgn_ctx* ctx, int64_t* bytes);
  * on a copy stream of its own, overlapped with the next layer (a layer waits
  * only for the copies of the layer two before it).  The backward copies
  * layer l-1's checkpoint back while layer l runs.  The hidden activations of
- * the edge MLP are never offloaded: the edge adjoint recomputes them.  The
+ * the edge MLP (and their pre-activations) are never offloaded: the edge
+ * adjoint recomputes them.  The
  * checkpoints of the last two layers stay in their device slots and are not
  * copied.  Results equal those of the device-resident tape up to the
- * recomputed hidden activations (bitwise wherever the device-resident tape
- * recomputes them too).  Enabling or disabling synchronises the device,
+ * recomputed hidden activations (bitwise in the FP32 form, whose
+ * device-resident tape recomputes them too).  Enabling or disabling synchronises the device,
  * frees the current tape (it is re-allocated at its new size by the next
  * forward) and invalidates the last forward.  The forward completes (on its
  * stream) only when its host copies have landed; each call's copies stay
