@@ -16,6 +16,16 @@ Modules
 Every function is float64 unless it produces integers.  Where the paper is
 silent the reading taken is stated in the function's docstring.
 
-Parity status: every function is pinned by tests under tests/ (brute force,
-closed forms, invariants, finite differences); none is "parity unpinned".
+Parity status: every function is pinned by a test under tests/ that does
+not retype its own formula:
+  graph      brute-force kNN, tie lattices, the cross-level dedupe invariant
+  partition  backward reachability (scipy), partitioned = full graph at halo L
+  model      hand-worked edge features (sign, norm, affine); the whole step
+             against float64 torch autograd (both activations, both
+             aggregated quantities); closed forms (zero MLPs, the sparse
+             adjacency product, LayerNorm statistics); node-permutation
+             equivariance; exact translation invariance; central finite
+             differences; bfloat16 rounding against torch's conversion
+  optim      Adam, clipping and the cosine schedule against torch's CPU ones
+No function is "parity unpinned".
 """
