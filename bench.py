@@ -4,10 +4,17 @@ BF16 against plain FP32, 15 layers, one MI355X.
 
 A step is one full training pass of the hot path over the workload:
 forward (encoders, 15 fused edge + node processor layers, decoder), masked
-MSE gradient, and the hand-written backward with per-layer recompute and all
-parameter gradients.  Inputs (graph, partition plan, parameters, features,
-targets) are resident in HBM before the timed region starts; the kNN graph
-build and the partitioner run once beforehand and are reported separately.
+MSE gradient, and the hand-written backward with all parameter gradients.
+Inputs (graph, partition plan, parameters, features, targets) are resident
+in HBM before the timed region starts; the kNN graph build and the
+partitioner run once beforehand and are reported separately and in an
+end-to-end total (kNN + partitioning + one step).
+
+Two tape policies are timed, for both precisions, each BF16 leg against the
+plain FP32 leg of the same policy: "keep" (the forward also stores every
+edge's hidden activation z, so the edge adjoint skips the first product;
+the headline) and "recompute" (per-layer checkpoints only, every edge MLP
+recomputed in the backward).
 
 edge-updates/s = E_useful * L / t_step.
 
@@ -285,6 +292,9 @@ def main():
     ap.add_argument("--workload", default="ellipsoid-ms-400k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--tape", choices=["keep", "recompute", "both"], default="both",
+                    help="tape policy: keep the edge MLPs' hidden activations, recompute them from the "
+                         "per-layer checkpoints, or time both (the first listed is the headline)")
     ap.add_argument("--graph", action="store_true", help="replay each step from a captured HIP graph")
     ap.add_argument("--edge-rows", type=int, default=0)
     ap.add_argument("--node-rows", type=int, default=0)
@@ -349,7 +359,14 @@ def main():
     results = {}
     if H == 512 and not args.no_fp32:
         log("[bench] H = 512 runs in the BF16 form only: no FP32 leg")
-    for prec in (["bf16"] if args.no_fp32 or H == 512 else ["bf16", "fp32"]):
+    precs = ["bf16"] if args.no_fp32 or H == 512 else ["bf16", "fp32"]
+    policies = {"keep": [True], "recompute": [False], "both": [True, False]}[args.tape]
+    # legs: (name, precision, keep_hidden); the first is the headline
+    legs = [(p + ("" if keep else "_recompute"), p, keep) for keep in policies for p in precs]
+    for leg, prec, keep in legs:
+        ctx = api.Context(0)  # a context per leg, so that its workspace is the leg's own
+        ctx.set_tiles(args.edge_rows, args.node_rows, args.grid, args.edge_waves)
+        ctx.set_tape(keep)
         model = api.Model(H, L, node_in=cfg.node_in, activation=cfg.activation, precision=prec)
         entries = [(kind, shape) for (_, _, _, kind, shape, _) in model.param_tensors()]
         params = to(init_params(entries, cfg.seed("weights")))
@@ -378,9 +395,9 @@ def main():
         elif not args.no_autotune and not (args.edge_rows or args.node_rows or args.grid or args.edge_waves):
             ctx.set_tiles(0, 0, 0, 0)
             tuned = ctx.autotune(model, params, ps, waves[0], node_in, pos, inp.edge_norm, out, d_out, d_params)
-            log(f"[bench] {prec}: autotuned edge_rows={tuned[0]} node_rows={tuned[1]} grid={tuned[2]} "
+            log(f"[bench] {leg}: autotuned edge_rows={tuned[0]} node_rows={tuned[1]} grid={tuned[2]} "
                 f"edge_waves={tuned[3]} ({tuned[4]:.2f} ms)")
-        log(f"[bench] {prec}: warmup {args.warmup}")
+        log(f"[bench] {leg}: warmup {args.warmup}")
         for _ in range(max(1, args.warmup)):
             step()
         torch.cuda.synchronize()
@@ -402,25 +419,27 @@ def main():
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.steps
         ev = e0.elapsed_time(e1) / 1e3 / args.steps
-        log(f"[bench] {prec}: {wall * 1e3:.2f} ms/step wall, {ev * 1e3:.2f} ms/step events, loss {loss.item():.5f}")
+        log(f"[bench] {leg}: {wall * 1e3:.2f} ms/step wall, {ev * 1e3:.2f} ms/step events, loss {loss.item():.5f}")
         # per-kernel breakdown from one extra (untimed) step
         ctx.set_timing(True)
         step()
         torch.cuda.synchronize()
         tk = ctx.timings()
         ctx.set_timing(False)
-        results[prec] = dict(wall=wall, ev=ev, kernels=tk, mem=ctx.memory(), tiles=tuned)
-        log(f"[bench] {prec} kernels: " + ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in
+        results[leg] = dict(wall=wall, ev=ev, kernels=tk, mem=ctx.memory(), tiles=tuned, keep=keep)
+        log(f"[bench] {leg} kernels: " + ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in
                                                      sorted(tk.items(), key=lambda kv: -kv[1][0])))
-        del params, out, d_out, d_params
+        del params, out, d_out, d_params, ctx
+        torch.cuda.empty_cache()
 
-    bf = results["bf16"]
+    head = legs[0][0]
+    bf = results[head]
     value = E * L / bf["wall"]
-    # dominant kernel of the BF16 step and its roofline
+    # dominant kernel of the headline BF16 step and its roofline
     kern = bf["kernels"]
     fused = H == 128  # the BF16 edge adjoint fuses its weight gradients at H = 128
-    ztape = True  # the BF16 edge adjoint reads z from the forward's tape
-    atape = cfg.activation != "relu"  # ... and, under SiLU, a
+    ztape = bf["keep"]  # the edge adjoint reads z from the forward's tape (tape policy keep)
+    atape = ztape and cfg.activation != "relu"  # ... and, under SiLU, a
     de_in = (L - 1) / L
     kb = lambda k, n_w, e_w: kernel_bytes(k, n_w, e_w, H, 2, fused, de_in, ztape, atape)  # noqa: E731
     dom = max((k for k in kern if kb(k, N, E) is not None), key=lambda k: kern[k][0])
@@ -469,11 +488,17 @@ def main():
         "knn_build_ms": round(t_knn * 1e3, 2),
         "partition_plan_ms": round(t_part * 1e3, 2),
     }
-    if "fp32" in results:
-        f = results["fp32"]
-        line["fp32_value"] = E * L / f["wall"]
-        line["fp32_ms_per_step"] = round(f["wall"] * 1e3, 3)
-        line["bf16_over_fp32"] = round(f["wall"] / bf["wall"], 3)
+    line["tape"] = "keep hidden activations" if bf["keep"] else "checkpoints only (recompute)"
+    line["end_to_end_ms"] = round((t_knn + t_part) * 1e3 + bf["wall"] * 1e3, 3)
+    for leg, r in results.items():
+        if leg == head:
+            continue
+        line[f"{leg}_value"] = E * L / r["wall"]
+        line[f"{leg}_ms_per_step"] = round(r["wall"] * 1e3, 3)
+    # BF16 against plain FP32 under the same tape policy
+    for sfx in ("", "_recompute"):
+        if "bf16" + sfx in results and "fp32" + sfx in results:
+            line["bf16_over_fp32" + sfx] = round(results["fp32" + sfx]["wall"] / results["bf16" + sfx]["wall"], 3)
     line["tiles"] = {p: (dict(zip(["edge_rows", "node_rows", "grid", "edge_waves"], r["tiles"][:4]))
                          if r["tiles"] else None) for p, r in results.items()}
     line["kernels_ms"] = {p: {k: round(v[0], 3) for k, v in r["kernels"].items()} for p, r in results.items()}

@@ -203,10 +203,26 @@ xmgn_status xmgn_mse_grad(xmgn_ctx* ctx, const float* out, const float* target, 
                           float* d_out, float* loss, xmgn_stream stream);
 
 /*
- * 4. Backward of the last forward on ctx (which must have kept its tape).
- * d_out: dev FP32 [N_global][out_dim] (halo rows ignored).
+ * 4. Backward of the last forward on ctx (which must have kept its tape):
+ * the gradient of sum(d_out * out) with respect to every parameter, by the
+ * hand-written adjoint of the encoders, the processor layers (Eq. 1-4) and
+ * the decoder.
+ * d_out: dev FP32 [N_global][out_dim]; only the rows of the batch's inner
+ *        nodes are read (halo predictions are dropped, Sec. III.D, so they
+ *        carry no gradient).
  * d_params: dev FP32, same layout as params; written, not added.
- * Each layer is recomputed from its checkpoint (activation checkpointing).
+ * Gradient aggregation (Sec. III.A): each part's halo reproduces the
+ * computational graph of its inner nodes, so the gradients of the parts of a
+ * partition set (one backward per batch, summed with xmgn_grad_accumulate in
+ * a fixed order) add up to the full graph's, as if the whole graph had been
+ * processed; a batch of several parts returns that sum itself.
+ * Activation checkpointing (Sec. V.D, V.F): the forward keeps only each
+ * layer's input latents (h^l, e^l) and sums m^l; every layer's MLPs are
+ * recomputed from them here, except that the BF16 forms may keep the edge
+ * MLP's hidden activations (and, under SiLU, their pre-activations) when
+ * the tape policy allows (xmgn_ctx_set_tape).
+ * Errors: XMGN_ERR_STATE when ctx holds no tape, or desc or params differ
+ * from the forward's; nothing is enqueued then.
  */
 xmgn_status xmgn_backward(xmgn_ctx* ctx, const xmgn_model_desc* desc, const float* params,
                           const float* d_out, float* d_params, xmgn_stream stream);
@@ -275,6 +291,18 @@ xmgn_status xmgn_ctx_timing_count(const xmgn_ctx* ctx, int32_t* n_classes);
 xmgn_status xmgn_ctx_timing_read(xmgn_ctx* ctx, int32_t i, char* name, int32_t name_len, double* total_ms,
                                  int64_t* launches);
 
+/*
+ * Serial number of the tape the next xmgn_backward on ctx would consume: a
+ * positive count of the forwards enqueued on ctx so far, taken at the last
+ * one if it kept its tape, else 0 (no tape: no forward yet, the last forward
+ * had keep_tape = 0 or failed, or the tiles or the offload mode changed
+ * since).  A caller that holds several forwards open on one context (e.g.
+ * an autograd graph over two partitions) records it after each forward and
+ * compares it before the matching backward: a different value means a later
+ * forward replaced the tape.  Host-only, never fails for a valid ctx.
+ */
+xmgn_status xmgn_ctx_tape_serial(const xmgn_ctx* ctx, int64_t* serial);
+
 /* Device bytes currently held by the context (tape and workspace). */
 xmgn_status xmgn_ctx_memory(const xmgn_ctx* ctx, int64_t* bytes);
 
@@ -300,6 +328,23 @@ xmgn_status xmgn_ctx_memory(const xmgn_ctx* ctx, int64_t* bytes);
  * s = 2 (BF16) or 4 (FP32).
  */
 xmgn_status xmgn_ctx_set_offload(xmgn_ctx* ctx, int32_t enable);
+/*
+ * Tape policy of the training forward (activation checkpointing, Sec. V.D,
+ * V.F).  keep_hidden = 0: the tape holds each layer's checkpoints only
+ * (h^l, e^l, m^l) and the backward recomputes both products of every edge
+ * MLP from them.  keep_hidden = 1 (the default): the tape also keeps every
+ * edge's hidden activation z = act(a) of every layer, stored like the
+ * latents (BF16 or FP32; under SiLU also a), L E H s bytes each, and the
+ * edge adjoint reads it instead of recomputing the first product; the
+ * offloaded tape always recomputes.  Both policies give the same forward
+ * outputs bitwise; their gradients agree to the rounding of the stored z
+ * (the recompute may sum the first product in another order, and SiLU's
+ * derivative is taken at the stored pre-activation).  Changing it
+ * synchronises the device, frees the hidden-activation tape and
+ * invalidates the last forward.
+ */
+xmgn_status xmgn_ctx_set_tape(xmgn_ctx* ctx, int32_t keep_hidden);
+xmgn_status xmgn_ctx_get_tape(const xmgn_ctx* ctx, int32_t* keep_hidden);
 /* Page-locked host bytes currently held by the context (the offloaded tape). */
 xmgn_status xmgn_ctx_host_memory(const xmgn_ctx* ctx, int64_t* bytes);
 

@@ -194,6 +194,12 @@ class Context:
             out[buf.value.decode()] = (ms.value, cnt.value)
         return out
 
+    def tape_serial(self) -> int:
+        """Serial of the tape the next backward would consume (0 = none)."""
+        n = C.c_int64()
+        check(lib.xmgn_ctx_tape_serial(self._h, C.byref(n)))
+        return n.value
+
     def memory(self) -> int:
         """Device bytes held by the context."""
         b = C.c_int64()
@@ -205,6 +211,16 @@ class Context:
         b = C.c_int64()
         check(lib.xmgn_ctx_host_memory(self._h, C.byref(b)))
         return b.value
+
+    def set_tape(self, keep_hidden: bool):
+        """Tape policy: keep the edge MLPs' hidden activations (BF16 forms) or
+        recompute them from the checkpoints (synchronises the device)."""
+        check(lib.xmgn_ctx_set_tape(self._h, 1 if keep_hidden else 0))
+
+    def get_tape(self) -> bool:
+        v = C.c_int32()
+        check(lib.xmgn_ctx_get_tape(self._h, C.byref(v)))
+        return bool(v.value)
 
     def set_offload(self, enable: bool):
         """Keep the training tape's checkpoints in host memory (synchronises the device)."""
@@ -291,19 +307,30 @@ class Adam:
 
 class ProcessorFn(torch.autograd.Function):
     """out = X-MeshGraphNet(params) on a batch of partitions; backward returns
-    d_params through the hand-written adjoint (xmgn_backward)."""
+    d_params through the hand-written adjoint (xmgn_backward), which
+    recomputes every layer from the context's checkpoints.
+
+    A context holds the tape of its last forward only.  The backward of an
+    application whose tape a later forward on the same context replaced
+    raises XmgnError (code XMGN_ERR_STATE) instead of returning the gradient
+    of another batch; give each application that must stay differentiable a
+    context of its own, or run its backward before the next forward."""
 
     @staticmethod
     def forward(fctx, params, node_in, pos, ctx: Context, model: Model, ps: Partset, part_ids, edge_norm):
         out = torch.zeros(node_in.shape[0], model.out_dim, device=params.device, dtype=torch.float32)
         ctx.forward(model, params, ps, part_ids, node_in, pos, edge_norm, out, keep_tape=True)
-        fctx.xm = (ctx, model)
+        fctx.xm = (ctx, model, ctx.tape_serial())
         fctx.save_for_backward(params)
         return out
 
     @staticmethod
     def backward(fctx, d_out):
-        ctx, model = fctx.xm
+        ctx, model, serial = fctx.xm
+        if ctx.tape_serial() != serial:
+            raise XmgnError(-6, "the context's tape belongs to a later forward: this application's "
+                                "checkpoints are gone (run its backward before the next forward on "
+                                "the context, or give it a context of its own)")
         (params,) = fctx.saved_tensors
         d_params = torch.empty_like(params)
         ctx.backward(model, params, d_out.contiguous(), d_params)

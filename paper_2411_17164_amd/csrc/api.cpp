@@ -54,6 +54,20 @@ extern "C" const char* xmgn_version(void) { return "xmgn 0.1 gfx950"; }
 // ---------------------------------------------------------------------------
 // device buffers
 // ---------------------------------------------------------------------------
+// Before memory that work already enqueued on `st` may still read is freed
+// or rewritten from the host: wait for that work.  Refused while `st` is
+// being captured into a graph (the replay would not see the new contents,
+// and allocation is not allowed under capture).
+static xmgn_status quiesce(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(st, &cs));
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(XMGN_ERR_STATE, "a batch plan, weight plan or buffer would change during stream capture: "
+                                "run one uncaptured step of the same batch first");
+  HIPCHK(hipStreamSynchronize(st));
+  return XMGN_OK;
+}
+
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -66,9 +80,12 @@ struct DBuf {
     p = nullptr;
     bytes = 0;
   }
-  // grow-only; contents are not preserved
-  xmgn_status ensure(size_t need) {
+  // grow-only; contents are not preserved.  Growing waits for the work
+  // enqueued on st (which may still read the old buffer) and is refused
+  // under capture.
+  xmgn_status ensure(size_t need, hipStream_t st) {
     if (need <= bytes && p) return XMGN_OK;
+    if (xmgn_status s = quiesce(st)) return s;
     release();
     size_t b = need > 0 ? need : 16;
     hipError_t e = hipMalloc(&p, b);
@@ -100,8 +117,9 @@ struct HBuf {
     p = nullptr;
     bytes = 0;
   }
-  xmgn_status ensure(size_t need) {
+  xmgn_status ensure(size_t need, hipStream_t st) {
     if (need <= bytes && p) return XMGN_OK;
+    if (xmgn_status s = quiesce(st)) return s;
     release();
     size_t b = need > 0 ? need : 16;
     hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
@@ -524,6 +542,7 @@ struct xmgn_ctx {
   DBuf zt;  // hidden activations of the edge MLPs [L][E][H] (BF16 forms, device-resident tape)
   DBuf at;  // their pre-activations [L][E][H] (BF16 SiLU forms, device-resident tape)
   bool tape_z = false, tape_a = false;
+  bool tape_hidden = true;  // tape policy: BF16 forms keep z (and a) of every edge
   // per-kernel timing
   bool timing = false;
   std::vector<std::string> tnames;
@@ -533,6 +552,7 @@ struct xmgn_ctx {
   // state of the last forward
   bool fwd_valid = false;
   bool fwd_tape = false;
+  uint64_t fwd_serial = 0;  // counts the forwards that completed their enqueue
   xmgn_model_desc fdesc{};
   const float* f_params = nullptr;
   const float* f_node_in = nullptr;
@@ -684,6 +704,12 @@ extern "C" xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int3
   return XMGN_OK;
 }
 
+extern "C" xmgn_status xmgn_ctx_tape_serial(const xmgn_ctx* c, int64_t* serial) {
+  if (!c || !serial) return fail(XMGN_ERR_INVALID, "NULL argument");
+  *serial = c->fwd_valid && c->fwd_tape ? (int64_t)c->fwd_serial : 0;
+  return XMGN_OK;
+}
+
 extern "C" xmgn_status xmgn_ctx_memory(const xmgn_ctx* c, int64_t* bytes) {
   if (!c || !bytes) return fail(XMGN_ERR_INVALID, "NULL argument");
   const DBuf* bufs[] = {&c->batch.ints, &c->jobs_dev, &c->blob, &c->h, &c->e, &c->m, &c->dhA, &c->dhMid,
@@ -719,6 +745,26 @@ extern "C" xmgn_status xmgn_ctx_set_offload(xmgn_ctx* c, int32_t enable) {
   c->fwd_valid = false;
   return XMGN_OK;
   GUARD_END
+}
+
+extern "C" xmgn_status xmgn_ctx_set_tape(xmgn_ctx* c, int32_t keep_hidden) {
+  GUARD_BEGIN
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (keep_hidden != 0 && keep_hidden != 1) return fail(XMGN_ERR_INVALID, "keep_hidden must be 0 or 1");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipDeviceSynchronize());
+  c->tape_hidden = keep_hidden != 0;
+  c->zt.release();
+  c->at.release();
+  c->fwd_valid = false;
+  return XMGN_OK;
+  GUARD_END
+}
+
+extern "C" xmgn_status xmgn_ctx_get_tape(const xmgn_ctx* c, int32_t* keep_hidden) {
+  if (!c || !keep_hidden) return fail(XMGN_ERR_INVALID, "NULL argument");
+  *keep_hidden = c->tape_hidden ? 1 : 0;
+  return XMGN_OK;
 }
 
 // Records an event (from the context's pool, one entry per use in a call) on
@@ -763,8 +809,11 @@ static void add_job(xmgn_ctx* c, int64_t src, int src_ld, int col0, int transpos
   c->jobs.push_back(j);
 }
 
-static xmgn_status ensure_wplan(xmgn_ctx* c, const xmgn_model_desc* d) {
+static xmgn_status ensure_wplan(xmgn_ctx* c, const xmgn_model_desc* d, hipStream_t st) {
   if (c->have_wplan && std::memcmp(&c->wdesc, d, sizeof(*d)) == 0) return XMGN_OK;
+  // the job table and the blob may still be read by enqueued kernels
+  if (xmgn_status s = quiesce(st)) return s;
+  c->have_wplan = false;
   c->jobs.clear();
   c->blob_elems = 0;
   const int H = d->hidden, L = d->n_layers;
@@ -797,9 +846,9 @@ static xmgn_status ensure_wplan(xmgn_ctx* c, const xmgn_model_desc* d) {
   add_job(c, poff(d, 4, 0, 2), H, 0, 0, H, H, wd.W2);
   add_job(c, poff(d, 4, 0, 0), H, 0, 1, H, H, wd.W1T);
   add_job(c, poff(d, 4, 0, 2), H, 0, 1, H, H, wd.W2T);
-  if (xmgn_status s = c->jobs_dev.ensure(c->jobs.size() * sizeof(PrepJob))) return s;
+  if (xmgn_status s = c->jobs_dev.ensure(c->jobs.size() * sizeof(PrepJob), st)) return s;
   HIPCHK(hipMemcpy(c->jobs_dev.p, c->jobs.data(), c->jobs.size() * sizeof(PrepJob), hipMemcpyHostToDevice));
-  if (xmgn_status s = c->blob.ensure((size_t)c->blob_elems * tsize(d))) return s;
+  if (xmgn_status s = c->blob.ensure((size_t)c->blob_elems * tsize(d), st)) return s;
   c->wdesc = *d;
   c->have_wplan = true;
   return XMGN_OK;
@@ -840,10 +889,13 @@ static MlpW weights(const xmgn_ctx* c, const xmgn_model_desc* d, const float* pa
 }
 
 static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32_t* part_ids, int32_t n_batch,
-                                int mt_edge) {
+                                int mt_edge, hipStream_t st) {
   if (c->have_batch && c->batch.ps == ps && c->batch.ps_serial == ps->serial && c->batch.mt_edge == mt_edge &&
       c->batch.part_ids == std::vector<int32_t>(part_ids, part_ids + n_batch))
     return XMGN_OK;
+  // the plan's device arrays are rewritten below: kernels of the previous
+  // batch enqueued on st must be done with them
+  if (xmgn_status s = quiesce(st)) return s;
   c->have_batch = false;
   Batch& B = c->batch;
   B.ps = ps;
@@ -903,7 +955,7 @@ static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32
   }
   const int64_t nt = (int64_t)etiles.size() - 1;
   const int64_t total = n + (n + 1) + E + E + (n + 1) + E + (nt + 1) + ni;
-  if (xmgn_status s = B.ints.ensure((size_t)total * 4)) return s;
+  if (xmgn_status s = B.ints.ensure((size_t)total * 4, st)) return s;
   int32_t* d = B.ints.as<int32_t>();
   int64_t o = 0;
   auto up = [&](const std::vector<int32_t>& v) -> const int* {
@@ -934,24 +986,24 @@ static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32
   return XMGN_OK;
 }
 
-static xmgn_status ensure_tape(xmgn_ctx* c, const xmgn_model_desc* d, bool full, bool z, bool a) {
+static xmgn_status ensure_tape(xmgn_ctx* c, const xmgn_model_desc* d, bool full, bool z, bool a, hipStream_t st) {
   const size_t ts = tsize(d), H = d->hidden, L = d->n_layers;
   const size_t n = c->batch.n, E = c->batch.E;
   const int mode = !full ? 0 : c->offload ? 2 : 1;
   const size_t sh = mode == 1 ? L + 1 : 2, se = mode == 1 ? L : std::min<size_t>(L, 2),
                sm = mode == 1 ? L : mode == 2 ? std::min<size_t>(L, 2) : 1;
-  if (xmgn_status s = c->h.ensure(sh * n * H * ts)) return s;
-  if (xmgn_status s = c->e.ensure(se * E * H * ts)) return s;
-  if (xmgn_status s = c->m.ensure(sm * n * H * 4)) return s;
+  if (xmgn_status s = c->h.ensure(sh * n * H * ts, st)) return s;
+  if (xmgn_status s = c->e.ensure(se * E * H * ts, st)) return s;
+  if (xmgn_status s = c->m.ensure(sm * n * H * 4, st)) return s;
   // the offloaded tape keeps no z: the edge adjoint recomputes it
   c->tape_z = mode == 1 && z;
   c->tape_a = c->tape_z && a;
   if (c->tape_z)
-    if (xmgn_status s = c->zt.ensure(L * E * H * ts)) return s;
+    if (xmgn_status s = c->zt.ensure(L * E * H * ts, st)) return s;
   if (c->tape_a)
-    if (xmgn_status s = c->at.ensure(L * E * H * ts)) return s;
+    if (xmgn_status s = c->at.ensure(L * E * H * ts, st)) return s;
   if (mode == 2)
-    if (xmgn_status s = c->ht.ensure(((L + 1) * n + L * E) * H * ts + L * n * H * 4)) return s;
+    if (xmgn_status s = c->ht.ensure(((L + 1) * n + L * E) * H * ts + L * n * H * 4, st)) return s;
   c->tape_mode = mode;
   return XMGN_OK;
 }
@@ -1052,15 +1104,19 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   const Shape s = make_shape(c, d);
-  if (xmgn_status r = ensure_batch(c, ps, part_ids, n_batch, s.mt_edge)) return r;
-  if (xmgn_status r = ensure_wplan(c, d)) return r;
-  if (xmgn_status r = ensure_tape(c, d, keep_tape != 0, edge_z_tape(s), edge_a_tape(s))) return r;
+  // from here on the batch plan and the tape change: a failure leaves no
+  // forward for a backward to consume
+  c->fwd_valid = false;
+  if (xmgn_status r = ensure_batch(c, ps, part_ids, n_batch, s.mt_edge, st)) return r;
+  if (xmgn_status r = ensure_wplan(c, d, st)) return r;
+  const bool keep_z = c->tape_hidden && edge_z_tape(s);
+  if (xmgn_status r = ensure_tape(c, d, keep_tape != 0, keep_z, keep_z && edge_a_tape(s), st)) return r;
   const BatchView& b = c->batch.view;
   const int L = d->n_layers;
   g_config_error = 0;
   { KT("prep"); launch_prep(params, c->blob.p, d->precision, c->jobs_dev.as<PrepJob>(), (int)c->jobs.size(), st); }
   { KT("enc_node_fwd"); launch_enc_node_fwd(s, b, weights(c, d, params, 0, 0, 0), node_in, d->node_in, hslot(c, d, 0), st); }
-  if (xmgn_status r = c->xe.ensure((size_t)b.E * 4 * sizeof(float))) return r;
+  if (xmgn_status r = c->xe.ensure((size_t)b.E * 4 * sizeof(float), st)) return r;
   { KT("edge_feat"); launch_edge_feat(b, pos, en, c->xe.as<float>(), st); }
   { KT("enc_edge_fwd"); launch_enc_edge_fwd(s, b, weights(c, d, params, 1, 1, 0), c->xe.as<float>(), eslot(c, d, 0), st); }
   // offloaded tape: copies[j] completes with the copies of the checkpoint rows
@@ -1091,6 +1147,7 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
   if (g_config_error) return fail(XMGN_ERR_UNSUPPORTED, "tile configuration does not fit this kernel");
   c->fwd_valid = true;
   c->fwd_tape = keep_tape != 0;
+  ++c->fwd_serial;
   c->fdesc = *d;
   c->f_params = params;
   c->f_node_in = node_in;
@@ -1107,9 +1164,9 @@ extern "C" xmgn_status xmgn_mse_grad(xmgn_ctx* c, const float* out, const float*
   if (n_total < 1) return fail(XMGN_ERR_INVALID, "n_total must be >= 1");
   HIPCHK(hipSetDevice(c->device));
   const int G = 256;
-  if (xmgn_status s = c->lossp.ensure(G * sizeof(float))) return s;
-  const double inv = 1.0 / ((double)n_total * c->fdesc.out_dim);
   hipStream_t st = (hipStream_t)stream;
+  if (xmgn_status s = c->lossp.ensure(G * sizeof(float), st)) return s;
+  const double inv = 1.0 / ((double)n_total * c->fdesc.out_dim);
   KT("mse");
   launch_mse(out, target, c->batch.view.gid, c->batch.view.inner, c->batch.n_inner, c->fdesc.out_dim, inv, d_out,
              c->lossp.as<float>(), G, loss, st);
@@ -1163,20 +1220,20 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   const int L = d->n_layers, G = s.grid;
   const size_t rows = std::max(n, E);
   for (DBuf* p : {&c->dhA, &c->dhMid, &c->dm, &c->Sr, &c->Ss})
-    if (xmgn_status r = p->ensure(n * H * 4)) return r;
+    if (xmgn_status r = p->ensure(n * H * 4, st)) return r;
   for (DBuf* p : {&c->deA, &c->deB})
-    if (xmgn_status r = p->ensure(E * H * 4)) return r;
+    if (xmgn_status r = p->ensure(E * H * 4, st)) return r;
   for (DBuf* p : {&c->fa, &c->fb, &c->fc, &c->fd})
-    if (xmgn_status r = p->ensure(rows * H * ts)) return r;
-  if (xmgn_status r = c->dy.ensure((size_t)c->batch.n_inner * 16 * 4)) return r;
-  if (xmgn_status r = c->part.ensure((size_t)G * 13 * H * 4)) return r;
+    if (xmgn_status r = p->ensure(rows * H * ts, st)) return r;
+  if (xmgn_status r = c->dy.ensure((size_t)c->batch.n_inner * 16 * 4, st)) return r;
+  if (xmgn_status r = c->part.ensure((size_t)G * 13 * H * 4, st)) return r;
   {
     size_t need = 0;
     const int Rs[3] = {(int)n, (int)E, c->batch.n_inner};
     for (int R : Rs)
       need = std::max(need, wgrad_partial_floats(s, wop(nullptr, 0, 0, 0, nullptr, nullptr, 0, 0, 0, nullptr, R,
                                                         (int)H, (int)H, nullptr, 0)));
-    if (xmgn_status r = c->wpart.ensure(need * 4)) return r;
+    if (xmgn_status r = c->wpart.ensure(need * 4, st)) return r;
   }
   // the edge adjoint may accumulate its dense weight gradients itself
   const bool fw = edge_bwd_fuses_wgrad(s);
@@ -1185,9 +1242,9 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   if (fw || enc_bwd_fuses_wgrad(s) || node_bwd_fuses_wgrad(s)) {
     // edge adjoint: [se.grid][2][H][H]; encoders: [<=256][2][H][H]; node adjoint: [<=256][3][H][H]
     const size_t mats = std::max((size_t)se.grid * 2, (size_t)std::min(s.grid, 256) * 3);
-    if (xmgn_status r = c->wfused.ensure(mats * H * H * 4)) return r;
+    if (xmgn_status r = c->wfused.ensure(mats * H * H * 4, st)) return r;
   }
-  if (xmgn_status r = c->redtmp.ensure(reduce_tmp_floats((int)std::max<size_t>(H * H, 16 * H)) * 4)) return r;
+  if (xmgn_status r = c->redtmp.ensure(reduce_tmp_floats((int)std::max<size_t>(H * H, 16 * H)) * 4, st)) return r;
   float* rt = c->redtmp.as<float>();
   float* part = c->part.as<float>();
   auto P = [&](int block, int layer, int t) { return d_params + poff(d, block, layer, t); };
@@ -1350,7 +1407,7 @@ extern "C" xmgn_status xmgn_adam_step(xmgn_ctx* c, float* params, const float* g
     return fail(XMGN_ERR_INVALID, "betas must be in [0, 1)");
   HIPCHK(hipSetDevice(c->device));
   const int G = 256;
-  if (xmgn_status r = c->optp.ensure(G * sizeof(double))) return r;
+  if (xmgn_status r = c->optp.ensure(G * sizeof(double), (hipStream_t)stream)) return r;
   AdamArgs a{(float)lr, (float)beta1, (float)beta2, (float)(1.0 - beta1), (float)(1.0 - beta2), (float)eps,
              (float)(1.0 - std::pow(beta1, (double)step)), (float)(1.0 - std::pow(beta2, (double)step)), clip_norm};
   launch_adam(params, grad, m, v, n, c->optp.as<double>(), G, a, grad_norm, (hipStream_t)stream);

@@ -96,9 +96,9 @@ bool edge_bwd_fuses_wgrad(const Shape& s);
 size_t reduce_tmp_floats(int max_cols);
 void launch_wgrad_reduce(const float* partial, int n_chunks, int M_valid, int N, float* dst, int ldd, int MN,
                          float* tmp, hipStream_t st);
-// True when the edge adjoint reads z from the forward's tape (BF16) instead
-// of recomputing it; zt is then that tape (else NULL), and the unfused form
-// does not write o.z (its dW2 product reads the tape).
+// True when the edge adjoint can read z from the forward's tape instead of
+// recomputing it (every form); zt is then that tape (else NULL: recompute),
+// and the unfused form does not write o.z (its dW2 product reads the tape).
 bool edge_z_tape(const Shape& s);
 // True when the forms that read z from the tape also need a (SiLU); at is
 // then the tape of pre-activations (else NULL).

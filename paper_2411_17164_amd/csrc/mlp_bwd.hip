@@ -168,7 +168,6 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
   constexpr size_t XS = L::XS, ZS = L::ZS, WS = L::WS;
   constexpr int LDW = L::LDW, LDF = L::LDF;
   static_assert(!FW || (sizeof(T) == 2 && H == 128), "fused weight gradients: BF16, H = 128");
-  static_assert(!ZT || sizeof(T) == 2, "z from the tape: BF16 forms");
   static_assert((size_t)MT * LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
   static_assert(!FW || (size_t)H * 4 <= 2 * H * sizeof(T), "FP32 rows must leave the e columns intact");
   __shared__ __align__(16) unsigned char smem[L::bytes];
@@ -214,7 +213,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
       // z rows into zs, (fused: for dW1's e-block) e rows into the e columns
       // of xs and (SiLU) a rows into its first H columns, one batch of loads
       constexpr int NPART = 1 + (FW ? 1 : 0) + (ACT != 0 ? 1 : 0);
-      constexpr int E8 = 8, CPR = H / E8, TOT = NPART * MT * CPR, IT = TOT / (64 * NW);
+      constexpr int E8 = 16 / sizeof(T), CPR = H / E8, TOT = NPART * MT * CPR, IT = TOT / (64 * NW);
       static_assert(TOT % (64 * NW) == 0, "whole steps of the workgroup");
       auto src = [&](int p) -> const T* { return p == 0 ? zt : (FW && p == 1) ? e : at; };
       auto dst = [&](int p, int i, int q) -> T* {
@@ -1116,9 +1115,9 @@ static void edge_bwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const
                         hipStream_t st) {
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
     constexpr int FW = (sizeof(T) == 2 && H == 128) ? 1 : 0;
-    constexpr int ZT = sizeof(T) == 2 ? 1 : 0;
+    constexpr int ZT = 1;
     if constexpr (edge_bwd_fits<T, H, MT>()) {
-      if (zt && (!ZT || (ACT != 0 && !at))) {
+      if (zt && ACT != 0 && !at) {
         g_config_error = 1;
       } else if (zt) {
         if (s.agg)
@@ -1141,8 +1140,8 @@ static void edge_bwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const
   }))));
 }
 
-bool edge_z_tape(const Shape& s) { return s.prec == 1; }
-bool edge_a_tape(const Shape& s) { return s.prec == 1 && s.act != 0; }
+bool edge_z_tape(const Shape&) { return true; }
+bool edge_a_tape(const Shape& s) { return s.act != 0; }
 
 void launch_edge_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
                      const void* zt, const void* at, const float* de_in, const float* dm, const EdgeBwdOut& o,

@@ -223,20 +223,29 @@ def test_partitions_equal_full_graph(api, ctx, precision, cfg):
     assert (y_parts == y_full).all()
     assert abs(loss_sum - loss_full) <= 1e-5 * loss_full
     g_acc = acc.cpu().numpy()
-    # FP32: the two sums differ by summation order only.  BF16: each
-    # partition rounds its own partial factors (e.g. sender sums over its
-    # local out-edges) to BF16, so the two agree to BF16 rounding, and both
-    # must meet the BF16 bound against the FP64 oracle.
-    tol_pair = 1e-5 if precision == "fp32" else 5e-3
-    errs = per_tensor_errors(case, g_acc, g_full)
-    worst = sorted(errs.items(), key=lambda kv: -kv[1])[:4]
-    log(f"  partition-sum vs full: {worst}")
-    assert worst[0][1] <= tol_pair, worst
-    # all partitions in one batch (the ragged union) gives the same gradient
+    # all partitions in one batch (the ragged union)
     y_b, loss_b, g_b = gpu_step(api, ctx, case, ps, list(range(len(sizes))))
-    errs_b = per_tensor_errors(case, g_b, g_full)
-    assert max(errs_b.values()) <= tol_pair, sorted(errs_b.items(), key=lambda kv: -kv[1])[:4]
     assert (y_b == y_full).all()
+    # the accumulated partition gradients and the ragged batch's against the
+    # FP64 oracle's partitioned step (Sec. III.A), at the parity bar
+    args = (parts, case.inp.node_in, case.inp.pos, case.inp.edge_norm, case.inp.targets)
+    base = om.step_partitioned(case.desc, case.params.astype(np.float64), *args)
+    amp = om.step_partitioned(case.desc, om.amp_cast(case.desc, case.params), *args) if precision == "bf16" else None
+    log("  partition sum vs oracle: " + check_step(case, y_parts, loss_sum, g_acc, (base, amp)))
+    log("  ragged batch vs oracle: " + check_step(case, y_b, loss_b, g_b, (base, amp)))
+    # and against the GPU's own full-graph gradient.  FP32: the sums differ
+    # in order only.  BF16: every MFMA operand of the adjoint (du, da, the
+    # segment sums S_r, S_s) is rounded to BF16, and a halo node's adjoint
+    # in a partition is a partial sum over that partition's paths, so the
+    # roundings fall on different values than in the full graph; the two
+    # agree to a fraction of BF16's unit roundoff 2^-9 (the bar is a
+    # quarter of it).
+    tol_pair = 1e-5 if precision == "fp32" else 2.0 ** -11
+    for name, g_x in (("partition sum", g_acc), ("ragged batch", g_b)):
+        errs = per_tensor_errors(case, g_x, g_full)
+        worst = sorted(errs.items(), key=lambda kv: -kv[1])[:4]
+        log(f"  {name} vs full graph: {worst}")
+        assert worst[0][1] <= tol_pair, worst
 
 
 def test_halo_one_short_differs(api, ctx):
