@@ -272,6 +272,25 @@ xmgn_status xmgn_grad_accumulate(float* acc, const float* g, int64_t n, xmgn_str
 xmgn_status xmgn_adam_step(xmgn_ctx* ctx, float* params, const float* grad, float* m, float* v,
                            int64_t n, int64_t step, double lr, double beta1, double beta2, double eps,
                            double clip_norm, float* grad_norm, xmgn_stream stream);
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): xmgn_adam_step without a context, allocating nothing.  Same
+ * arguments, checks and kernels, and bitwise the same results; the clipping
+ * norm's per-workgroup partials go to a fixed array of the library instead
+ * of a context buffer: 256 FP64 values (2 KiB) on each GPU the library runs
+ * on, held until the process ends.  The partial count does not grow with n,
+ * so every n >= 0 fits.  device: the HIP device the arrays live on (made
+ * current, like a context's calls do); its array's address is looked up on
+ * the first call on that device.  Every call writes all 256 partials before
+ * reading them, so nothing carries over from an earlier call; calls that
+ * overlap on one GPU (other streams, other threads) race on the array:
+ * order them on one stream.  Errors: as xmgn_adam_step, plus
+ * XMGN_ERR_INVALID for a device index out of range.
+ */
+xmgn_status xmgn_adam_step_noalloc(int32_t device, float* params, const float* grad, float* m, float* v,
+                                   int64_t n, int64_t step, double lr, double beta1, double beta2, double eps,
+                                   double clip_norm, float* grad_norm, xmgn_stream stream);
 /* Cosine-annealed learning rate (Sec. V.D) at step t of T (host, no device
  * work): lr_min + (lr_max - lr_min) (1 + cos(pi t / T)) / 2 with t clamped
  * to [0, T]; lr_min when T <= 0. */

@@ -72,6 +72,8 @@ _SIGS = {
     "xmgn_grad_accumulate": (_i32, [_p, _p, _i64, _p]),
     "xmgn_adam_step": (_i32, [_p, _p, _p, _p, _p, _i64, _i64, C.c_double, C.c_double, C.c_double, C.c_double,
                               C.c_double, _p, _p]),
+    "xmgn_adam_step_noalloc": (_i32, [_i32, _p, _p, _p, _p, _i64, _i64, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, _p, _p]),
     "xmgn_cosine_lr": (C.c_double, [_i64, _i64, C.c_double, C.c_double]),
     "xmgn_autotune": (_i32, [_p, _pdesc, _p, _p, _pi32, _i32, _p, _p, _pf, _p, _p, _p, C.c_char_p,
                              _pi32, _pi32, _pi32, _pi32, _pf, _p]),

@@ -305,6 +305,19 @@ class Adam:
         self.t += 1
 
 
+def adam_step_noalloc(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
+                      lr: float, betas=(0.9, 0.999), eps: float = 1e-8, clip_norm: float = 32.0,
+                      grad_norm: torch.Tensor | None = None, stream=None):
+    """One Adam step through xmgn_adam_step_noalloc (no context, allocates
+    nothing; see include/xmgn.h) on the tensors' device."""
+    n = params.numel()
+    if not (grad.numel() == m.numel() == v.numel() == n):
+        raise ValueError("size mismatch")
+    check(lib.xmgn_adam_step_noalloc(params.device.index or 0, _dev(params), _dev(grad), _dev(m), _dev(v), n, step,
+                                     lr, betas[0], betas[1], eps, clip_norm,
+                                     None if grad_norm is None else _dev(grad_norm), _stream(stream)))
+
+
 class ProcessorFn(torch.autograd.Function):
     """out = X-MeshGraphNet(params) on a batch of partitions; backward returns
     d_params through the hand-written adjoint (xmgn_backward), which

@@ -1393,11 +1393,10 @@ extern "C" xmgn_status xmgn_grad_accumulate(float* acc, const float* g, int64_t 
   return XMGN_OK;
 }
 
-extern "C" xmgn_status xmgn_adam_step(xmgn_ctx* c, float* params, const float* grad, float* m, float* v, int64_t n,
-                                      int64_t step, double lr, double beta1, double beta2, double eps,
-                                      double clip_norm, float* grad_norm, xmgn_stream stream) {
-  GUARD_BEGIN
-  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+// Arguments of an optimizer step, checked on the host; the FP32 constants
+// of the update, each rounded once from its FP64 value.
+static xmgn_status adam_args(float* params, const float* grad, float* m, float* v, int64_t n, int64_t step,
+                             double lr, double beta1, double beta2, double eps, double clip_norm, AdamArgs* a) {
   if (n < 0) return fail(XMGN_ERR_INVALID, "n must be >= 0");
   if (n > 0 && (!params || !grad || !m || !v)) return fail(XMGN_ERR_INVALID, "NULL argument");
   if (step < 1) return fail(XMGN_ERR_INVALID, "step is 1-based");
@@ -1405,12 +1404,46 @@ extern "C" xmgn_status xmgn_adam_step(xmgn_ctx* c, float* params, const float* g
     return fail(XMGN_ERR_INVALID, "lr must be finite and >= 0, eps finite and > 0, clip_norm finite");
   if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0))
     return fail(XMGN_ERR_INVALID, "betas must be in [0, 1)");
+  *a = AdamArgs{(float)lr, (float)beta1, (float)beta2, (float)(1.0 - beta1), (float)(1.0 - beta2), (float)eps,
+                (float)(1.0 - std::pow(beta1, (double)step)), (float)(1.0 - std::pow(beta2, (double)step)), clip_norm};
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_adam_step(xmgn_ctx* c, float* params, const float* grad, float* m, float* v, int64_t n,
+                                      int64_t step, double lr, double beta1, double beta2, double eps,
+                                      double clip_norm, float* grad_norm, xmgn_stream stream) {
+  GUARD_BEGIN
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  AdamArgs a{};
+  if (xmgn_status r = adam_args(params, grad, m, v, n, step, lr, beta1, beta2, eps, clip_norm, &a)) return r;
   HIPCHK(hipSetDevice(c->device));
-  const int G = 256;
+  const int G = kAdamScratchPartials;
   if (xmgn_status r = c->optp.ensure(G * sizeof(double), (hipStream_t)stream)) return r;
-  AdamArgs a{(float)lr, (float)beta1, (float)beta2, (float)(1.0 - beta1), (float)(1.0 - beta2), (float)eps,
-             (float)(1.0 - std::pow(beta1, (double)step)), (float)(1.0 - std::pow(beta2, (double)step)), clip_norm};
   launch_adam(params, grad, m, v, n, c->optp.as<double>(), G, a, grad_norm, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return XMGN_OK;
+  GUARD_END
+}
+
+extern "C" xmgn_status xmgn_adam_step_noalloc(int32_t device, float* params, const float* grad, float* m, float* v,
+                                              int64_t n, int64_t step, double lr, double beta1, double beta2,
+                                              double eps, double clip_norm, float* grad_norm, xmgn_stream stream) {
+  GUARD_BEGIN
+  AdamArgs a{};
+  if (xmgn_status r = adam_args(params, grad, m, v, n, step, lr, beta1, beta2, eps, clip_norm, &a)) return r;
+  int n_dev = 0;
+  HIPCHK(hipGetDeviceCount(&n_dev));
+  if (device < 0 || device >= n_dev || device >= kMaxDevices) return fail(XMGN_ERR_INVALID, "device out of range");
+  // the partial count is fixed (the array's size), so no n needs more
+  const int G = kAdamScratchPartials;
+  HIPCHK(hipSetDevice(device));
+  double* partial = nullptr;
+  const char* err = "";
+  if (const int rc = adam_noalloc_scratch(device, &partial, &err))
+    return fail(rc == -1 ? XMGN_ERR_INVALID : XMGN_ERR_HIP, std::string("optimizer scratch: ") + err);
+  // k_sumsq writes all G partials before k_adam reads them (stream order),
+  // so nothing of a previous call needs clearing
+  launch_adam(params, grad, m, v, n, partial, G, a, grad_norm, (hipStream_t)stream);
   HIPCHK(hipGetLastError());
   return XMGN_OK;
   GUARD_END

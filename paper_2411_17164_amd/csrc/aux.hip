@@ -2,6 +2,7 @@
 // (split over row chunks, reduced in a fixed order), fixed-order reductions
 // of per-workgroup partial vectors, weight preparation (cast / transpose into
 // the compute type), the masked MSE and gradient accumulation.
+#include <mutex>
 #include <type_traits>
 
 #include "common.hpp"
@@ -383,6 +384,38 @@ void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, double
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   k_adam<<<(unsigned)blocks, 256, 0, st>>>(p, g, m, v, n, partial, G, a, norm_out);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free optimizer step.  The clipping norm's per-workgroup
+// partials live in `scratch`, a fixed array of the library on every device
+// it runs on (held until the process ends), instead of a context buffer.
+// In host code `scratch` names a host-side stand-in: its device address is
+// looked up once per device and only that address is ever used.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kAdamScratchPartials];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kMaxDevices] = {};
+
+int adam_noalloc_scratch(int device, double** out, const char** err) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) {
+    *err = "device index out of range";
+    return -1;
+  }
+  if (!g_scratch_dev[device]) {
+    // with `device` current (the caller made it so): this device's copy
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      *err = hipGetErrorString(e);
+      return -3;
+    }
+    g_scratch_dev[device] = (double*)ptr;
+  }
+  *out = g_scratch_dev[device];
+  return 0;
 }
 
 // Masked MSE over the batch's inner rows: per-workgroup partial sums in a

@@ -212,6 +212,15 @@ struct AdamArgs {
 // partial: dev double [G] scratch; norm_out: dev float [1] or NULL.
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, double* partial, int G,
                  const AdamArgs& a, float* norm_out, hipStream_t st);
+// Partials of the allocation-free optimizer step: the count launch_adam is
+// given by both optimizer entry points, and the capacity of the library's
+// fixed per-device array that the allocation-free one uses.
+constexpr int kAdamScratchPartials = 256;
+constexpr int kMaxDevices = 64;
+// Device address (on `device`, which must be current) of that array; looked
+// up on the first call per device.  Returns 0, or -1 (bad device) / -3
+// (HIP error) with *err set.
+int adam_noalloc_scratch(int device, double** out, const char** err);
 void launch_mse(const float* out, const float* target, const int* gid, const int* inner, int n_inner,
                 int out_dim, double inv_norm, float* d_out, float* partial, int G, float* loss,
                 hipStream_t st);
