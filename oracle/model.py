@@ -275,6 +275,41 @@ def forward(d: Desc, blob, g: Graph, node_in, pos, edge_norm, keep=False):
     return y
 
 
+def forward_cone(d: Desc, blob, part, node_in, pos, edge_norm):
+    """Outputs of a cone's inner nodes (its seeds), evaluating each layer only
+    on the rows that can still reach them.
+
+    `part` is an L-hop in-cone (partition.in_cone): local nodes ordered by
+    hop, every node with hop < L keeping all its in-edges.  An output of
+    layer l at a node with hop j feeds the seeds only if j <= L - 1 - l
+    (Eq. 4: one hop per layer), so layer l updates the nodes with hop
+    <= L - 1 - l from the edges into them: a prefix of the local nodes and
+    of the local CSR edges.  Every row it computes is the same per-row
+    arithmetic as forward() on the whole cone; the rows it skips never reach
+    a seed."""
+    P = unpack(d, blob)
+    g = part.graph
+    hop = np.asarray(part.hop)
+    L = d.layers
+    assert part.depth == L, "the cone must be L hops deep"
+    n_upto = [int(np.searchsorted(hop, j, side="right")) for j in range(L + 1)]  # nodes with hop <= j
+    h, _ = mlp_fwd(d, P["enc_node"], np.asarray(node_in, np.float64), True)
+    e, _ = mlp_fwd(d, P["enc_edge"], edge_features(g, pos, edge_norm), True)
+    for l in range(L):
+        nr = n_upto[L - 1 - l]            # receivers updated by this layer
+        ns = n_upto[L - l]                # rows of h it reads (their senders)
+        ne = int(g.row_ptr[nr])           # their in-edges: a CSR prefix
+        sub = Graph.__new__(Graph)
+        sub.n = ns
+        sub.recv = g.recv[:ne]
+        sub.col = g.col[:ne]
+        sub.row_ptr = np.concatenate([g.row_ptr[: nr + 1], np.full(ns - nr, ne, dtype=g.row_ptr.dtype)])
+        h, e, _ = processor_layer_fwd(d, sub, P[f"edge{l}"], P[f"node{l}"], h[:ns], e[:ne])
+        h = h[:nr]                        # rows past nr had no in-edges here and reach no seed
+    y, _ = mlp_fwd(d, P["dec"], h[: part.n_inner], False)
+    return y
+
+
 def loss_and_grad(y, targets, n_inner, n_total):
     """Masked MSE: rows [0, n_inner) are inner nodes, the rest is halo.
     Returns (loss, d loss / d y) with halo rows zero."""

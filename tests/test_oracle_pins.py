@@ -152,3 +152,25 @@ def test_bf16_weight_cast_alone():
     assert rel_l2(g1, g0) <= 1.6e-2
     assert rel_l2(y1, y0) <= 1e-2
     assert abs(loss1 - loss0) <= 1e-3 * loss0
+
+
+@pytest.mark.parametrize("act,agg", [("relu", "message"), ("silu", "edge")])
+def test_forward_cone_equals_full_forward(act, agg):
+    """The cone-restricted forward (each layer on the rows that can still
+    reach the seeds) gives the whole graph's outputs at the seeds."""
+    case = Case(3, levels=(300, 1200, 3000), layers=4, activation=act, aggregate=agg)
+    G = case.oracle_graph()
+    blob = case.params.astype(np.float64)
+    y_full = om.forward(case.desc, blob, G, case.inp.node_in, case.inp.pos, case.inp.edge_norm)
+    from oracle import partition as opart
+    rng = np.random.default_rng(3)
+    seeds = np.sort(rng.choice(case.N, 5, replace=False))
+    part = opart.in_cone(G, seeds, case.L)
+    y = om.forward_cone(case.desc, blob, part, case.inp.node_in[part.gid], case.inp.pos[part.gid],
+                        case.inp.edge_norm)
+    assert y.shape == (len(seeds), 4)
+    assert rel_l2(y, y_full[seeds]) <= 1e-12
+    # a cone one hop short is not enough
+    with pytest.raises(AssertionError):
+        om.forward_cone(case.desc, blob, opart.in_cone(G, seeds, case.L - 1), case.inp.node_in, case.inp.pos,
+                        case.inp.edge_norm)
