@@ -55,29 +55,34 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: bool = False, de_in: float = 1.0,
+def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: int = 0, de_in: float = 1.0,
                  ztape: bool = False, atape: bool = False) -> float | None:
     """Algorithmic HBM bytes of one launch of a processor kernel: each input
     read once, each output written once (s = bytes per stored latent; FP32
-    adjoints are 4 bytes).  `fused`: the edge adjoint accumulates dW2 and the
-    e-block of dW1 itself, so z and du are not written.  `de_in`: fraction of
-    launches that read an incoming edge adjoint de' (all but the last layer).
-    `atape`: the forward also writes the pre-activation a (SiLU), which the
-    adjoint reads too.
-    `ztape`: the forward writes z for the adjoint, which reads it instead of
-    h_s and h_r."""
+    adjoints are 4 bytes).  `fused`: the edge adjoint accumulates dW2 (1), or
+    dW2 and the e-block of dW1 (2), itself, so z and du are not written (and
+    with 1 the e-block is a separate product that reads da and e again).
+    `de_in`: fraction of launches that read an incoming edge adjoint de' (all
+    but the last layer).  `atape`: the forward also writes the
+    pre-activation a (SiLU), which the adjoint reads too.  `ztape`: the
+    forward writes z for the adjoint, which reads it instead of h_s and h_r."""
     if name == "edge_fwd":
         # per edge: e and the gathered h_s read, e' (and z) written; per
         # receiver: h_r read, m (FP32) written
         return E * (3 + (1 if ztape else 0) + (1 if atape else 0)) * H * s + n * (H * s + 4 * H)
     if name == "edge_bwd":
         # per edge: de' (FP32) read, de (FP32) and da written, and
-        #   fused, z on the tape:   z, e read
-        #   fused, recompute:       h_s, e read
-        #   unfused, z on the tape: z read, du written
-        #   unfused, recompute:     h_s, e read, z, du written
+        #   both fused, z on the tape: z, e read
+        #   dW2 fused, z on the tape:  z read
+        #   fused, recompute:          h_s, e read
+        #   unfused, z on the tape:    z read, du written
+        #   unfused, recompute:        h_s, e read, z, du written
         # per receiver: h_r (not with ztape), dm (FP32) read, S_r (FP32) written
-        per_edge = ((3 if (fused or ztape) else 5) + (1 if atape else 0)) * H * s + 4 * H * (1 + de_in)
+        if ztape:
+            lat = 3 if fused == 2 else 2
+        else:
+            lat = 3 if fused else 5
+        per_edge = (lat + (1 if atape else 0)) * H * s + 4 * H * (1 + de_in)
         return E * per_edge + n * ((0 if ztape else H * s) + 8 * H)
     if name == "node_fwd":
         return n * (2 * H * s + 4 * H)
@@ -86,14 +91,14 @@ def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: bool = False,
     return None
 
 
-def kernel_flops(name: str, n: int, E: int, H: int, fused: bool = False, ztape: bool = False) -> float | None:
+def kernel_flops(name: str, n: int, E: int, H: int, fused: int = 0, ztape: bool = False) -> float | None:
     """Dense multiply-add flops of one launch (2 per MAC)."""
     if name == "edge_fwd":
         return E * 8.0 * H * H
     if name == "edge_bwd":
         # recompute (3H x H unless z is on the tape, H x H), W2^T du, W1e^T da;
-        # fused: du^T z, da^T e
-        return E * ((16.0 if fused else 12.0) - (6.0 if ztape else 0.0)) * H * H
+        # fused: du^T z (1), and da^T e (2)
+        return E * (12.0 + 2.0 * fused - (6.0 if ztape else 0.0)) * H * H
     if name == "node_fwd":
         return n * 6.0 * H * H
     if name == "node_bwd":
@@ -300,6 +305,7 @@ def main():
     ap.add_argument("--node-rows", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--edge-waves", type=int, default=0)
+    ap.add_argument("--adjoint-edge-rows", type=int, default=0, help="edge tile rows of the edge adjoint")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tiles")
     ap.add_argument("--wave-parts", type=int, default=0,
                     help="partitions per batch (wave) for partitioned workloads (0 = the workload's default: "
@@ -366,6 +372,7 @@ def main():
     for leg, prec, keep in legs:
         ctx = api.Context(0)  # a context per leg, so that its workspace is the leg's own
         ctx.set_tiles(args.edge_rows, args.node_rows, args.grid, args.edge_waves)
+        ctx.set_bwd_tiles(args.adjoint_edge_rows)
         ctx.set_tape(keep)
         model = api.Model(H, L, node_in=cfg.node_in, activation=cfg.activation, precision=prec)
         entries = [(kind, shape) for (_, _, _, kind, shape, _) in model.param_tensors()]
@@ -392,17 +399,19 @@ def main():
         tuned = None
         if H == 512 and not args.no_autotune:
             log("[bench] H = 512: fixed tiles (32-row edge, 16-row node), no autotuning")
-        elif not args.no_autotune and not (args.edge_rows or args.node_rows or args.grid or args.edge_waves):
+        elif not args.no_autotune and not (args.edge_rows or args.node_rows or args.grid or args.edge_waves
+                                           or args.adjoint_edge_rows):
             ctx.set_tiles(0, 0, 0, 0)
             tuned = ctx.autotune(model, params, ps, waves[0], node_in, pos, inp.edge_norm, out, d_out, d_params)
+            tuned = tuned[:4] + (ctx.get_bwd_tiles(),) + tuned[4:]
             log(f"[bench] {leg}: autotuned edge_rows={tuned[0]} node_rows={tuned[1]} grid={tuned[2]} "
-                f"edge_waves={tuned[3]} ({tuned[4]:.2f} ms)")
+                f"edge_waves={tuned[3]} adjoint_edge_rows={tuned[4]} ({tuned[5]:.2f} ms)")
         log(f"[bench] {leg}: warmup {args.warmup}")
         for _ in range(max(1, args.warmup)):
             step()
         torch.cuda.synchronize()
         run = step
-        if args.graph and len(waves) == 1:
+        if args.graph:  # every wave's batch plan is cached by now: the whole step is captured
             gr = torch.cuda.CUDAGraph()
             with torch.cuda.graph(gr):
                 step()
@@ -437,8 +446,11 @@ def main():
     value = E * L / bf["wall"]
     # dominant kernel of the headline BF16 step and its roofline
     kern = bf["kernels"]
-    fused = H == 128  # the BF16 edge adjoint fuses its weight gradients at H = 128
     ztape = bf["keep"]  # the edge adjoint reads z from the forward's tape (tape policy keep)
+    # the BF16 edge adjoint at H = 128 fuses its weight gradients: dW2 only on
+    # its 32-row tiles with the z tape, dW2 and the e-block of dW1 otherwise
+    adj_rows = (bf["tiles"][4] or bf["tiles"][0]) if bf["tiles"] else (args.adjoint_edge_rows or args.edge_rows or 64)
+    fused = 0 if H != 128 else (1 if (ztape and adj_rows == 32) else 2)
     atape = ztape and cfg.activation != "relu"  # ... and, under SiLU, a
     de_in = (L - 1) / L
     kb = lambda k, n_w, e_w: kernel_bytes(k, n_w, e_w, H, 2, fused, de_in, ztape, atape)  # noqa: E731
@@ -481,7 +493,7 @@ def main():
                    "levels": levels, "k": [cfg.k_intra, cfg.k_cross], "partitions": n_parts,
                    "halo": L if n_parts > 1 else 0, "waves": len(waves), "processed_edges": E_proc,
                    "parallelism": "halo-partition batches" if n_parts > 1 else "none",
-                   "graph_replay": bool(args.graph and len(waves) == 1), "activation": cfg.activation,
+                   "graph_replay": bool(args.graph), "activation": cfg.activation,
                    "node_in": cfg.node_in},
         "processed_edge_updates_per_s": E_proc * L / bf["wall"],
         "roofline": roofline,
@@ -499,7 +511,8 @@ def main():
     for sfx in ("", "_recompute"):
         if "bf16" + sfx in results and "fp32" + sfx in results:
             line["bf16_over_fp32" + sfx] = round(results["fp32" + sfx]["wall"] / results["bf16" + sfx]["wall"], 3)
-    line["tiles"] = {p: (dict(zip(["edge_rows", "node_rows", "grid", "edge_waves"], r["tiles"][:4]))
+    line["tiles"] = {p: (dict(zip(["edge_rows", "node_rows", "grid", "edge_waves", "adjoint_edge_rows"],
+                                  r["tiles"][:5]))
                          if r["tiles"] else None) for p, r in results.items()}
     line["kernels_ms"] = {p: {k: round(v[0], 3) for k, v in r["kernels"].items()} for p, r in results.items()}
     line["device_workspace_gb"] = {p: round(r["mem"] / 1e9, 2) for p, r in results.items()}

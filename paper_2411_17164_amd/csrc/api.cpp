@@ -501,13 +501,15 @@ extern "C" void xmgn_partset_destroy(xmgn_partset* ps) { delete ps; }
 struct Batch {
   const xmgn_partset* ps = nullptr;
   uint64_t ps_serial = 0;
+  uint64_t last_use = 0;  // context clock of the last forward that used the plan
   std::vector<int32_t> part_ids;
-  int mt_edge = 0;
+  int mt_edge = 0, mt_edge_bwd = 0;
   int n = 0, n_inner = 0;
   int64_t E = 0;
   int n_etiles = 0;
-  DBuf ints;  // gid | row_ptr | col | recv | csc_ptr | csc_edge | etiles | inner
+  DBuf ints;  // gid | row_ptr | col | recv | csc_ptr | csc_edge | etiles | inner | etiles of the adjoint
   BatchView view{};
+  BatchView view_b{};  // the same batch with the edge adjoint's tiles
 };
 
 struct BlockW {
@@ -517,8 +519,16 @@ struct BlockW {
 struct xmgn_ctx {
   int device = 0;
   int mt_edge = 0, mt_node = 0, grid = 0, nw_edge = 0;  // 0 = default
-  Batch batch;
-  bool have_batch = false;
+  int mt_edge_bwd = 0;                                  // 0 = the forward's edge tile
+  // Batch plans, one per (partition set, part list, edge-tile rows), kept
+  // while the context lives (at most kMaxPlans, least recently used evicted),
+  // so a step over several batches (waves of partitions) builds each plan
+  // once and can then be captured and replayed; `cur` is the plan of the
+  // last forward, the one its backward uses.
+  static constexpr size_t kMaxPlans = 16;
+  std::vector<std::unique_ptr<Batch>> plans;
+  Batch* cur = nullptr;
+  uint64_t plan_clock = 0;
   // weights
   xmgn_model_desc wdesc{};
   bool have_wplan = false;
@@ -605,10 +615,11 @@ static Shape make_shape(const xmgn_ctx* c, const xmgn_model_desc* d) {
   s.agg = d->aggregate;
   s.eps = d->ln_eps;
   int me = c->mt_edge > 0 ? c->mt_edge : 64, mn = c->mt_node > 0 ? c->mt_node : 64;
-  // LDS budget: H = 256 runs 32-row tiles; H = 512 32-row edge tiles (a
-  // tile holds whole receiver segments) and 16-row node tiles
+  // LDS budget: H = 256 runs 32-row node tiles and 32-row edge tiles, or
+  // 64-row edge tiles in the BF16 form when asked for; H = 512 32-row edge
+  // tiles (a tile holds whole receiver segments) and 16-row node tiles
   if (d->hidden == 256) {
-    me = 32;
+    me = (d->precision == 1 && c->mt_edge == 64) ? 64 : 32;
     mn = 32;
   }
   if (d->hidden == 512) {
@@ -617,6 +628,9 @@ static Shape make_shape(const xmgn_ctx* c, const xmgn_model_desc* d) {
   }
   s.mt_edge = me;
   s.mt_node = mn;
+  // the edge adjoint may tile the same edges differently (BF16, H = 128:
+  // 32 or 64 rows, independent of the forward)
+  s.mt_edge_bwd = (d->hidden == 128 && d->precision == 1 && c->mt_edge_bwd > 0) ? c->mt_edge_bwd : me;
   s.grid = c->grid > 0 ? c->grid : 1024;
   s.nw_edge = c->nw_edge > 0 ? c->nw_edge : d->hidden == 512 ? 8 : 4;  // H = 512: fewer spills at 8 waves
   return s;
@@ -699,8 +713,21 @@ extern "C" xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int3
   ctx->mt_node = node_rows;
   ctx->grid = grid;
   ctx->nw_edge = edge_waves;
-  ctx->have_batch = false;
   ctx->fwd_valid = false;
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_ctx_set_bwd_tiles(xmgn_ctx* ctx, int32_t edge_rows) {
+  if (!ctx) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (edge_rows != 0 && edge_rows != 32 && edge_rows != 64) return fail(XMGN_ERR_INVALID, "edge_rows must be 0, 32 or 64");
+  ctx->mt_edge_bwd = edge_rows;
+  ctx->fwd_valid = false;
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_ctx_get_bwd_tiles(const xmgn_ctx* ctx, int32_t* edge_rows) {
+  if (!ctx || !edge_rows) return fail(XMGN_ERR_INVALID, "NULL argument");
+  *edge_rows = ctx->mt_edge_bwd;
   return XMGN_OK;
 }
 
@@ -712,11 +739,12 @@ extern "C" xmgn_status xmgn_ctx_tape_serial(const xmgn_ctx* c, int64_t* serial) 
 
 extern "C" xmgn_status xmgn_ctx_memory(const xmgn_ctx* c, int64_t* bytes) {
   if (!c || !bytes) return fail(XMGN_ERR_INVALID, "NULL argument");
-  const DBuf* bufs[] = {&c->batch.ints, &c->jobs_dev, &c->blob, &c->h, &c->e, &c->m, &c->dhA, &c->dhMid,
+  int64_t t = 0;
+  for (const auto& P : c->plans) t += (int64_t)P->ints.bytes;
+  const DBuf* bufs[] = {&c->jobs_dev, &c->blob, &c->h, &c->e, &c->m, &c->dhA, &c->dhMid,
                         &c->dm, &c->Sr, &c->Ss, &c->deA, &c->deB, &c->fa, &c->fb, &c->fc, &c->fd,
                         &c->dy, &c->part, &c->wpart, &c->wfused, &c->redtmp, &c->lossp, &c->xe, &c->zt,
                         &c->at, &c->optp};
-  int64_t t = 0;
   for (const DBuf* b : bufs) t += (int64_t)b->bytes;
   *bytes = t;
   return XMGN_OK;
@@ -889,19 +917,30 @@ static MlpW weights(const xmgn_ctx* c, const xmgn_model_desc* d, const float* pa
 }
 
 static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32_t* part_ids, int32_t n_batch,
-                                int mt_edge, hipStream_t st) {
-  if (c->have_batch && c->batch.ps == ps && c->batch.ps_serial == ps->serial && c->batch.mt_edge == mt_edge &&
-      c->batch.part_ids == std::vector<int32_t>(part_ids, part_ids + n_batch))
-    return XMGN_OK;
-  // the plan's device arrays are rewritten below: kernels of the previous
-  // batch enqueued on st must be done with them
-  if (xmgn_status s = quiesce(st)) return s;
-  c->have_batch = false;
-  Batch& B = c->batch;
+                                int mt_edge, int mt_edge_bwd, hipStream_t st) {
+  const std::vector<int32_t> ids(part_ids, part_ids + n_batch);
+  for (auto& P : c->plans)
+    if (P->ps == ps && P->ps_serial == ps->serial && P->mt_edge == mt_edge && P->mt_edge_bwd == mt_edge_bwd &&
+        P->part_ids == ids) {
+      P->last_use = ++c->plan_clock;
+      c->cur = P.get();
+      return XMGN_OK;
+    }
+  c->cur = nullptr;
+  if (c->plans.size() >= xmgn_ctx::kMaxPlans) {
+    // the evicted plan's device arrays may still be read by enqueued kernels
+    if (xmgn_status s = quiesce(st)) return s;
+    auto lru = std::min_element(c->plans.begin(), c->plans.end(),
+                                [](const auto& a, const auto& b) { return a->last_use < b->last_use; });
+    c->plans.erase(lru);
+  }
+  auto owned = std::make_unique<Batch>();
+  Batch& B = *owned;
   B.ps = ps;
   B.ps_serial = ps->serial;
-  B.part_ids.assign(part_ids, part_ids + n_batch);
+  B.part_ids = ids;
   B.mt_edge = mt_edge;
+  B.mt_edge_bwd = mt_edge_bwd;
   int64_t n = 0, E = 0, ni = 0;
   for (int32_t p : B.part_ids) {
     const PartHost& P = ps->parts[p];
@@ -932,9 +971,9 @@ static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32
     io += P.n_inner;
   }
   row_ptr[n] = (int32_t)E;
-  if (maxdeg > mt_edge)
+  if (maxdeg > std::min(mt_edge, mt_edge_bwd))
     return fail(XMGN_ERR_UNSUPPORTED, "in-degree " + std::to_string(maxdeg) + " exceeds the edge tile (" +
-                                          std::to_string(mt_edge) + " rows)");
+                                          std::to_string(std::min(mt_edge, mt_edge_bwd)) + " rows)");
   // sender CSR: stable counting sort by sender (edges already in receiver order)
   for (int64_t k = 0; k < E; ++k) ++csc_ptr[col[k] + 1];
   for (int64_t i = 0; i < n; ++i) csc_ptr[i + 1] += csc_ptr[i];
@@ -942,19 +981,24 @@ static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32
     std::vector<int32_t> fill(csc_ptr.begin(), csc_ptr.end() - 1);
     for (int64_t k = 0; k < E; ++k) csc_edge[fill[col[k]]++] = (int32_t)k;
   }
-  // edge tiles: whole receiver segments, at most mt_edge edges and receivers
-  etiles.push_back(0);
-  for (int64_t r = 0; r < n;) {
-    int64_t cnt = 0, r1 = r;
-    while (r1 < n && r1 - r < mt_edge && cnt + (row_ptr[r1 + 1] - row_ptr[r1]) <= mt_edge) {
-      cnt += row_ptr[r1 + 1] - row_ptr[r1];
-      ++r1;
+  // edge tiles: whole receiver segments, at most mt edges and receivers
+  auto make_tiles = [&](int mt) {
+    std::vector<int32_t> t{0};
+    for (int64_t r = 0; r < n;) {
+      int64_t cnt = 0, r1 = r;
+      while (r1 < n && r1 - r < mt && cnt + (row_ptr[r1 + 1] - row_ptr[r1]) <= mt) {
+        cnt += row_ptr[r1 + 1] - row_ptr[r1];
+        ++r1;
+      }
+      t.push_back((int32_t)r1);
+      r = r1;
     }
-    etiles.push_back((int32_t)r1);
-    r = r1;
-  }
+    return t;
+  };
+  etiles = make_tiles(mt_edge);
+  const std::vector<int32_t> etiles_b = mt_edge_bwd == mt_edge ? std::vector<int32_t>{} : make_tiles(mt_edge_bwd);
   const int64_t nt = (int64_t)etiles.size() - 1;
-  const int64_t total = n + (n + 1) + E + E + (n + 1) + E + (nt + 1) + ni;
+  const int64_t total = n + (n + 1) + E + E + (n + 1) + E + (nt + 1) + ni + (int64_t)etiles_b.size();
   if (xmgn_status s = B.ints.ensure((size_t)total * 4, st)) return s;
   int32_t* d = B.ints.as<int32_t>();
   int64_t o = 0;
@@ -977,18 +1021,25 @@ static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32
   V.n_etiles = (int)nt;
   V.inner = up(inner);
   V.n_inner = (int)ni;
+  B.view_b = V;
+  if (!etiles_b.empty()) {
+    B.view_b.etiles = up(etiles_b);
+    B.view_b.n_etiles = (int)etiles_b.size() - 1;
+  }
   HIPCHK(hipGetLastError());
   B.n = (int)n;
   B.E = E;
   B.n_inner = (int)ni;
   B.n_etiles = (int)nt;
-  c->have_batch = true;
+  B.last_use = ++c->plan_clock;
+  c->plans.push_back(std::move(owned));
+  c->cur = c->plans.back().get();
   return XMGN_OK;
 }
 
 static xmgn_status ensure_tape(xmgn_ctx* c, const xmgn_model_desc* d, bool full, bool z, bool a, hipStream_t st) {
   const size_t ts = tsize(d), H = d->hidden, L = d->n_layers;
-  const size_t n = c->batch.n, E = c->batch.E;
+  const size_t n = c->cur->n, E = c->cur->E;
   const int mode = !full ? 0 : c->offload ? 2 : 1;
   const size_t sh = mode == 1 ? L + 1 : 2, se = mode == 1 ? L : std::min<size_t>(L, 2),
                sm = mode == 1 ? L : mode == 2 ? std::min<size_t>(L, 2) : 1;
@@ -1011,36 +1062,36 @@ static xmgn_status ensure_tape(xmgn_ctx* c, const xmgn_model_desc* d, bool full,
 // Device slot of layer l's checkpoint.
 static void* hslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   const size_t s = c->tape_mode == 1 ? l : l % 2;
-  return (char*)c->h.p + s * c->batch.n * d->hidden * tsize(d);
+  return (char*)c->h.p + s * c->cur->n * d->hidden * tsize(d);
 }
 static void* eslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   const size_t s = c->tape_mode == 1 ? l : l % 2;
-  return (char*)c->e.p + s * c->batch.E * d->hidden * tsize(d);
+  return (char*)c->e.p + s * c->cur->E * d->hidden * tsize(d);
 }
 static void* zslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   if (!c->tape_z) return nullptr;
-  return (char*)c->zt.p + (size_t)l * c->batch.E * d->hidden * tsize(d);
+  return (char*)c->zt.p + (size_t)l * c->cur->E * d->hidden * tsize(d);
 }
 static void* aslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   if (!c->tape_a) return nullptr;
-  return (char*)c->at.p + (size_t)l * c->batch.E * d->hidden * tsize(d);
+  return (char*)c->at.p + (size_t)l * c->cur->E * d->hidden * tsize(d);
 }
 static float* mslot(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   const size_t s = c->tape_mode == 1 ? l : c->tape_mode == 2 ? l % 2 : 0;
-  return c->m.as<float>() + s * c->batch.n * d->hidden;
+  return c->m.as<float>() + s * c->cur->n * d->hidden;
 }
 
 // Host copy of layer l's checkpoint in the offloaded tape.
 static void* host_h(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
-  return (char*)c->ht.p + (size_t)l * c->batch.n * d->hidden * tsize(d);
+  return (char*)c->ht.p + (size_t)l * c->cur->n * d->hidden * tsize(d);
 }
 static void* host_e(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   const size_t H = d->hidden, ts = tsize(d), L = d->n_layers;
-  return (char*)c->ht.p + ((L + 1) * c->batch.n + (size_t)l * c->batch.E) * H * ts;
+  return (char*)c->ht.p + ((L + 1) * c->cur->n + (size_t)l * c->cur->E) * H * ts;
 }
 static void* host_m(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
   const size_t H = d->hidden, ts = tsize(d), L = d->n_layers;
-  return (char*)c->ht.p + ((L + 1) * c->batch.n + L * c->batch.E) * H * ts + (size_t)l * c->batch.n * H * 4;
+  return (char*)c->ht.p + ((L + 1) * c->cur->n + L * c->cur->E) * H * ts + (size_t)l * c->cur->n * H * 4;
 }
 
 // Offloaded tape, forward: copy, on the copy stream, the checkpoint rows the
@@ -1049,7 +1100,7 @@ static void* host_m(xmgn_ctx* c, const xmgn_model_desc* d, int l) {
 // `done` receives an event that completes with these copies.
 static xmgn_status tape_out(xmgn_ctx* c, const xmgn_model_desc* d, hipStream_t st, int lh, int le, int lm,
                             hipEvent_t* done) {
-  const size_t H = d->hidden, ts = tsize(d), n = c->batch.n, E = c->batch.E;
+  const size_t H = d->hidden, ts = tsize(d), n = c->cur->n, E = c->cur->E;
   if (xmgn_status r = stream_order(c, st, c->cs)) return r;
   if (lh >= 0) HIPCHK(hipMemcpyAsync(host_h(c, d, lh), hslot(c, d, lh), n * H * ts, hipMemcpyDeviceToHost, c->cs));
   if (le >= 0) HIPCHK(hipMemcpyAsync(host_e(c, d, le), eslot(c, d, le), E * H * ts, hipMemcpyDeviceToHost, c->cs));
@@ -1062,7 +1113,7 @@ static xmgn_status tape_out(xmgn_ctx* c, const xmgn_model_desc* d, hipStream_t s
 // reader of that slot) has finished.
 static xmgn_status tape_in(xmgn_ctx* c, const xmgn_model_desc* d, hipStream_t st, int l, bool h, bool e, bool m,
                            hipEvent_t* done) {
-  const size_t H = d->hidden, ts = tsize(d), n = c->batch.n, E = c->batch.E;
+  const size_t H = d->hidden, ts = tsize(d), n = c->cur->n, E = c->cur->E;
   if (xmgn_status r = stream_order(c, st, c->cs)) return r;
   if (h) HIPCHK(hipMemcpyAsync(hslot(c, d, l), host_h(c, d, l), n * H * ts, hipMemcpyHostToDevice, c->cs));
   if (e) HIPCHK(hipMemcpyAsync(eslot(c, d, l), host_e(c, d, l), E * H * ts, hipMemcpyHostToDevice, c->cs));
@@ -1107,11 +1158,11 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
   // from here on the batch plan and the tape change: a failure leaves no
   // forward for a backward to consume
   c->fwd_valid = false;
-  if (xmgn_status r = ensure_batch(c, ps, part_ids, n_batch, s.mt_edge, st)) return r;
+  if (xmgn_status r = ensure_batch(c, ps, part_ids, n_batch, s.mt_edge, s.mt_edge_bwd, st)) return r;
   if (xmgn_status r = ensure_wplan(c, d, st)) return r;
   const bool keep_z = c->tape_hidden && edge_z_tape(s);
   if (xmgn_status r = ensure_tape(c, d, keep_tape != 0, keep_z, keep_z && edge_a_tape(s), st)) return r;
-  const BatchView& b = c->batch.view;
+  const BatchView& b = c->cur->view;
   const int L = d->n_layers;
   g_config_error = 0;
   { KT("prep"); launch_prep(params, c->blob.p, d->precision, c->jobs_dev.as<PrepJob>(), (int)c->jobs.size(), st); }
@@ -1168,7 +1219,7 @@ extern "C" xmgn_status xmgn_mse_grad(xmgn_ctx* c, const float* out, const float*
   if (xmgn_status s = c->lossp.ensure(G * sizeof(float), st)) return s;
   const double inv = 1.0 / ((double)n_total * c->fdesc.out_dim);
   KT("mse");
-  launch_mse(out, target, c->batch.view.gid, c->batch.view.inner, c->batch.n_inner, c->fdesc.out_dim, inv, d_out,
+  launch_mse(out, target, c->cur->view.gid, c->cur->view.inner, c->cur->n_inner, c->fdesc.out_dim, inv, d_out,
              c->lossp.as<float>(), G, loss, st);
   HIPCHK(hipGetLastError());
   return XMGN_OK;
@@ -1215,8 +1266,8 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   const Shape s = make_shape(c, d);
-  const BatchView& b = c->batch.view;
-  const size_t H = d->hidden, n = c->batch.n, E = c->batch.E, ts = tsize(d);
+  const BatchView& b = c->cur->view;
+  const size_t H = d->hidden, n = c->cur->n, E = c->cur->E, ts = tsize(d);
   const int L = d->n_layers, G = s.grid;
   const size_t rows = std::max(n, E);
   for (DBuf* p : {&c->dhA, &c->dhMid, &c->dm, &c->Sr, &c->Ss})
@@ -1225,19 +1276,22 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     if (xmgn_status r = p->ensure(E * H * 4, st)) return r;
   for (DBuf* p : {&c->fa, &c->fb, &c->fc, &c->fd})
     if (xmgn_status r = p->ensure(rows * H * ts, st)) return r;
-  if (xmgn_status r = c->dy.ensure((size_t)c->batch.n_inner * 16 * 4, st)) return r;
+  if (xmgn_status r = c->dy.ensure((size_t)c->cur->n_inner * 16 * 4, st)) return r;
   if (xmgn_status r = c->part.ensure((size_t)G * 13 * H * 4, st)) return r;
   {
     size_t need = 0;
-    const int Rs[3] = {(int)n, (int)E, c->batch.n_inner};
+    const int Rs[3] = {(int)n, (int)E, c->cur->n_inner};
     for (int R : Rs)
       need = std::max(need, wgrad_partial_floats(s, wop(nullptr, 0, 0, 0, nullptr, nullptr, 0, 0, 0, nullptr, R,
                                                         (int)H, (int)H, nullptr, 0)));
     if (xmgn_status r = c->wpart.ensure(need * 4, st)) return r;
   }
   // the edge adjoint may accumulate its dense weight gradients itself
-  const bool fw = edge_bwd_fuses_wgrad(s);
+  // the edge adjoint runs on its own tiling of the batch's edges
   Shape se = s;
+  se.mt_edge = s.mt_edge_bwd;
+  const bool fw = edge_bwd_fuses_wgrad(se);
+  const bool fw1e = edge_bwd_fuses_dw1e(se, c->tape_z);  // else the e-block of dW1 is a separate product
   if (fw) se.grid = std::min(s.grid, 512);
   if (fw || enc_bwd_fuses_wgrad(s) || node_bwd_fuses_wgrad(s)) {
     // edge adjoint: [se.grid][2][H][H]; encoders: [<=256][2][H][H]; node adjoint: [<=256][3][H][H]
@@ -1258,7 +1312,7 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     { KT("dec_bwd"); launch_dec_bwd(s, b, weights(c, d, params, 2 + 2 * L, 4, 0), hl(L), d_out, d->out_dim, o, st); }
     VecSeg segs[3] = {{0, (int)H, P(4, 0, 1)}, {(int)H, (int)H, P(4, 0, 3)}, {2 * (int)H, d->out_dim, P(4, 0, 5)}};
     launch_vec_reduce(part, G, 2 * (int)H + 16, segs, 3, rt, st);
-    const int ni = c->batch.n_inner;
+    const int ni = c->cur->n_inner;
     wgrad(s, wop(c->dy.p, 1, 16, 0, nullptr, c->fb.p, 0, (int)H, 0, nullptr, ni, 16, (int)H, P(4, 0, 4), (int)H,
                  d->out_dim), c->wpart, st);
     wgrad(s, wop(c->fd.p, 0, (int)H, 0, nullptr, c->fa.p, 0, (int)H, 0, nullptr, ni, (int)H, (int)H, P(4, 0, 2), (int)H),
@@ -1312,15 +1366,16 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
                   fw ? c->wfused.as<float>() : nullptr};
     const void* zt = edge_z_tape(se) ? zslot(c, d, l) : nullptr;  // the forward's z, when it kept it
     const void* at = edge_a_tape(se) ? aslot(c, d, l) : nullptr;  // ... and a (SiLU)
-    { KT("edge_bwd"); launch_edge_bwd(se, b, we, hl(l), eslot(c, d, l), zt, at, de_in, c->dm.as<float>(), eo, st); }
+    { KT("edge_bwd"); launch_edge_bwd(se, c->cur->view_b, we, hl(l), eslot(c, d, l), zt, at, de_in, c->dm.as<float>(), eo, st); }
     VecSeg es[4] = {{0, (int)H, P(2, l, 1)}, {(int)H, (int)H, P(2, l, 3)}, {2 * (int)H, (int)H, P(2, l, 4)},
                     {3 * (int)H, (int)H, P(2, l, 5)}};
     launch_vec_reduce(part, se.grid, 4 * (int)H, es, 4, rt, st);
     if (fw) {
       KT("wgrad");
       launch_wgrad_reduce(c->wfused.as<float>(), se.grid, (int)H, (int)H, P(2, l, 2), (int)H, 2 * (int)(H * H), rt, st);
-      launch_wgrad_reduce(c->wfused.as<float>() + H * H, se.grid, (int)H, (int)H, P(2, l, 0) + 2 * H, 3 * (int)H,
-                          2 * (int)(H * H), rt, st);
+      if (fw1e)
+        launch_wgrad_reduce(c->wfused.as<float>() + H * H, se.grid, (int)H, (int)H, P(2, l, 0) + 2 * H, 3 * (int)H,
+                            2 * (int)(H * H), rt, st);
     }
     { KT("sender_sum"); launch_sender_sum(s, b, c->fa.p, c->Ss.as<float>(), st); }
     { KT("node_dh"); launch_node_dh(s, b, we, c->dhMid.as<float>(), c->Sr.as<float>(), c->Ss.as<float>(), c->dhA.as<float>(), st); }
@@ -1328,12 +1383,12 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
                  3 * (int)H), c->wpart, st);
     wgrad(s, wop(c->Ss.p, 1, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
                  P(2, l, 0) + H, 3 * (int)H), c->wpart, st);
-    if (!fw) {
+    if (!fw1e)
       wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, eslot(c, d, l), 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H,
                    P(2, l, 0) + 2 * H, 3 * (int)H), c->wpart, st);
+    if (!fw)
       wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, zt ? zt : c->fc.p, 0, (int)H, 0, nullptr, (int)E, (int)H,
                    (int)H, P(2, l, 2), (int)H), c->wpart, st);
-    }
     de_in = de_out->as<float>();
     std::swap(de_out, de_other);
   }
@@ -1504,7 +1559,8 @@ static std::string tune_key(const xmgn_ctx* c, const xmgn_model_desc* d) {
   if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
   std::ostringstream k;
   k << arch.substr(0, arch.find(':')) << ":H" << d->hidden << ":L" << d->n_layers << ":p" << d->precision << ":a"
-    << d->activation << ":g" << d->aggregate << ":n" << c->batch.n << ":E" << c->batch.E;
+    << d->activation << ":g" << d->aggregate << ":t" << (c->tape_hidden ? 1 : 0) << ":n" << c->cur->n << ":E"
+    << c->cur->E;
   return k.str();
 }
 
@@ -1527,7 +1583,7 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
   if (xmgn_status r = xmgn_forward(c, d, params, ps, part_ids, n_batch, node_in, pos, edge_norm, out, 1, stream))
     return r;
   const std::string key = tune_key(c, d);
-  int best[4] = {0, 0, 0, 0};
+  int best[5] = {0, 0, 0, 0, 0};  // edge rows, node rows, grid, edge waves, adjoint edge rows
   float best_ms = -1.f;
   if (cache_path) {
     std::ifstream f(cache_path);
@@ -1535,13 +1591,14 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
     while (std::getline(f, line)) {
       std::istringstream is(line);
       std::string k;
-      int e, n, g, wv;
+      int e, n, g, wv, br;
       float ms;
-      if (is >> k >> e >> n >> g >> wv >> ms && k == key) {
+      if (is >> k >> e >> n >> g >> wv >> br >> ms && k == key) {
         best[0] = e;
         best[1] = n;
         best[2] = g;
         best[3] = wv;
+        best[4] = br;
         best_ms = ms;
       }
     }
@@ -1551,8 +1608,9 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     xmgn_status err = XMGN_OK;
-    auto trial = [&](int er, int nr, int g, int wv) -> xmgn_status {
+    auto trial = [&](int er, int nr, int g, int wv, int br) -> xmgn_status {
       if (xmgn_status r = xmgn_ctx_set_tiles(c, er, nr, g, wv)) return r;
+      if (xmgn_status r = xmgn_ctx_set_bwd_tiles(c, br)) return r;
       auto step = [&]() -> xmgn_status {
         if (xmgn_status r = xmgn_forward(c, d, params, ps, part_ids, n_batch, node_in, pos, edge_norm, out, 1, stream))
           return r;
@@ -1573,25 +1631,34 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
         best[1] = nr;
         best[2] = g;
         best[3] = wv;
+        best[4] = br;
       }
       return XMGN_OK;
     };
-    const std::vector<int> rows = d->hidden == 128 ? std::vector<int>{32, 64} : std::vector<int>{32};
+    const std::vector<int> rows = d->hidden == 128 || (d->hidden == 256 && d->precision == 1)
+                                      ? std::vector<int>{32, 64}
+                                      : std::vector<int>{32};
     // stage 1: edge kernels (the bulk of the step), stage 2: node tiles
     for (int er : rows)
       for (int wv : {4, 8})
         for (int wpc : {4, 8})
-          if (!err) err = trial(er, 32, ((cus * wpc + 7) / 8) * 8, wv);
-    if (!err && rows.size() > 1) err = trial(best[0], 64, best[2], best[3]);
+          if (!err) err = trial(er, 32, ((cus * wpc + 7) / 8) * 8, wv, 0);
+    if (!err && d->hidden == 128) err = trial(best[0], 64, best[2], best[3], 0);
+    // stage 3 (BF16, H = 128): the edge adjoint on its own tile rows
+    if (!err && d->hidden == 128 && d->precision == 1)
+      for (int br : {32, 64})
+        if (!err && br != best[0]) err = trial(best[0], best[1], best[2], best[3], br);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (err) return err;
     if (cache_path) {
       std::ofstream f(cache_path, std::ios::app);
-      f << key << " " << best[0] << " " << best[1] << " " << best[2] << " " << best[3] << " " << best_ms << "\n";
+      f << key << " " << best[0] << " " << best[1] << " " << best[2] << " " << best[3] << " " << best[4] << " "
+        << best_ms << "\n";
     }
   }
   if (xmgn_status r = xmgn_ctx_set_tiles(c, best[0], best[1], best[2], best[3])) return r;
+  if (xmgn_status r = xmgn_ctx_set_bwd_tiles(c, best[4])) return r;
   if (edge_rows) *edge_rows = best[0];
   if (node_rows) *node_rows = best[1];
   if (grid) *grid = best[2];

@@ -59,6 +59,19 @@ __device__ __forceinline__ float from_f<float>(float x) { return x; }
 template <>
 __device__ __forceinline__ bf16 from_f<bf16>(float x) { return (bf16)x; }
 
+// Workgroup barrier for LDS traffic only.  The fences are restricted to the
+// LDS address space, so a wave waits for its own LDS accesses (lgkmcnt)
+// before the barrier but not for its global loads and stores (vmcnt): loads
+// issued ahead of their use (the next tile's indices, weight fragments) stay
+// in flight across it, and stores drain behind the following work.  No
+// kernel that uses it reads global memory written by another thread of the
+// same launch.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
@@ -251,7 +264,7 @@ __device__ __forceinline__ void row_sum(const f32x4 (&x)[MB][NB], float* red, fl
       s = sum16(s);
       if ((l & 15) == 0) red[w * MT + acc_row(mb, r)] = s;
     }
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -262,7 +275,7 @@ __device__ __forceinline__ void row_sum(const f32x4 (&x)[MB][NB], float* red, fl
       for (int k = 0; k < NW; k += 2) t += red[k * MT + row] + red[(k + 1) * MT + row];
       out[mb][r] = t;
     }
-  __syncthreads();
+  lds_sync();
 }
 
 // Two row sums (of x and of y) exchanged across the NW waves in one barrier
@@ -288,7 +301,7 @@ __device__ __forceinline__ void row_sum2(const f32x4 (&x)[MB][NB], const f32x4 (
         red[(NW + w) * MT + acc_row(mb, r)] = c;
       }
     }
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -303,7 +316,7 @@ __device__ __forceinline__ void row_sum2(const f32x4 (&x)[MB][NB], const f32x4 (
       ox[mb][r] = a;
       oy[mb][r] = c;
     }
-  __syncthreads();
+  lds_sync();
 }
 
 // LayerNorm of the rows of u (in place -> xhat), returning inv std per row.
@@ -336,7 +349,7 @@ __device__ __forceinline__ void ln_normalize(f32x4 (&u)[MB][NB], float* red, flo
         red[(NW + w) * MT + acc_row(mb, r)] = q;
       }
     }
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -356,7 +369,7 @@ __device__ __forceinline__ void ln_normalize(f32x4 (&u)[MB][NB], float* red, flo
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) u[mb][nb][r] = (u[mb][nb][r] - mean) * inv[mb][r];
     }
-  __syncthreads();
+  lds_sync();
 }
 
 // Column sums of x over all rows held by the wave, accumulated into acc[nb]

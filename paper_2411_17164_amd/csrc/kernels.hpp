@@ -51,6 +51,7 @@ struct Shape {
   int act;      // 0 relu, 1 silu
   int agg;      // 0 message, 1 edge
   int mt_edge;  // rows per edge tile
+  int mt_edge_bwd;  // rows per edge tile of the edge adjoint (its own tiling of the same edges)
   int mt_node;  // rows per node tile
   int grid;     // persistent grid (workgroups)
   int nw_edge;  // waves per workgroup of the edge kernels (4 or 8)
@@ -91,6 +92,9 @@ struct EdgeBwdOut {
 // True when the edge adjoint accumulates dW2 and the e-block of dW1 itself
 // (then du and z are not written and wpart must be given).
 bool edge_bwd_fuses_wgrad(const Shape& s);
+// True when it also accumulates the e-block of dW1 (else that block is a
+// separate product over da and e); s.mt_edge is the adjoint's tile rows.
+bool edge_bwd_fuses_dw1e(const Shape& s, bool ztape);
 // Fixed-order sums over the rows of partial matrices use a two-stage
 // reduction with caller scratch of reduce_tmp_floats(columns) floats.
 size_t reduce_tmp_floats(int max_cols);
@@ -147,9 +151,9 @@ struct EncBwdOut {
   float* wpart;    // fused weight gradients [grid][2][H][H] (dW2, dW3) or NULL
   float* da1;      // more than 8 inputs: adjoint of the input layer's output [rows][H] (FP32); dW1 not in partial
 };
-// Rows per tile of the edge encoder: the edge tile, except at H = 512 where
-// the encoder (no segment constraint) takes the 16-row node tile.
-inline int enc_edge_rows(const Shape& s) { return s.H == 512 ? s.mt_node : s.mt_edge; }
+// Rows per tile of the edge encoder (no segment constraint): the edge tile
+// at H = 128, the node tile at H = 256 and 512 (whose LDS budget it shares).
+inline int enc_edge_rows(const Shape& s) { return s.H == 128 ? s.mt_edge : s.mt_node; }
 // True when the encoder adjoint accumulates dW2 and dW3 itself (then z1,
 // z2, da2 and du3 are not written and wpart must be given).
 bool enc_bwd_fuses_wgrad(const Shape& s);

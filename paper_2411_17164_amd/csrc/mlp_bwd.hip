@@ -16,6 +16,8 @@
 // gradients are row-sums of outer products and are formed by the wgrad
 // kernel from the per-row factors written here; bias / LayerNorm gradients
 // are per-workgroup column sums reduced in a fixed order.  No float atomics.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -133,14 +135,20 @@ __device__ __forceinline__ void write_partial(float* p, int n0, const double (&v
 // ---------------------------------------------------------------------------
 // Edge adjoint (with recompute).
 // ---------------------------------------------------------------------------
-// FW (BF16, H = 128): also accumulate dW2 = sum du z^T and the e-block of
-// dW1 = sum da e^T per workgroup on MFMA -- du and da straight from the
+// FW = 1 (BF16, H = 128): also accumulate dW2 = sum du z^T and the e-block
+// of dW1 = sum da e^T per workgroup on MFMA -- du and da straight from the
 // accumulators, z and e read transposed from their LDS tiles -- so that z
 // and du never travel to HBM; partials go to o.wpart.  W2 and the e-block of
 // W1 then live in LDS for the whole kernel and serve both their products and
 // (read transposed) the adjoint products dz = du W2 and de = da W1e; the FP32
 // staging tile takes the first 2H columns of the gathered tile's rows so that
-// its e columns stay intact.
+// its e columns stay intact.  One workgroup per compute unit.
+// FW = 2 (BF16, H = 128, z from the tape, 32-row tiles): dW2 only, W2 alone
+// in LDS, the e-block of W1 read from L2 for de = da W1e, and the e-block of
+// dW1 left to a separate product over da (which is written anyway) and the e
+// tape.  Half the accumulator registers and under 80 KB of LDS: two
+// workgroups per compute unit, so one's loads and barriers overlap the
+// other's arithmetic.
 template <typename T, int H, int MT, int FW, int NW>
 struct EdgeBwdLds {
   using D = BD<T, H, NW>;
@@ -148,8 +156,9 @@ struct EdgeBwdLds {
   static constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
   static constexpr int LDW = H + 8;  // LDS-resident weights (BF16)
   static constexpr size_t WS = FW ? (size_t)H * LDW * 2 : 0;
+  static constexpr int NWS = FW == 1 ? 2 : FW == 2 ? 1 : 0;  // LDS-resident weight matrices
   static constexpr int LDF = FW ? D::LD3 * (int)sizeof(T) / 4 : D::LDF;  // FP32 staging row stride
-  static constexpr size_t bytes = XS + ZS + 2 * WS + 2 * NW * MT * 4 + 2 * MT * 4;
+  static constexpr size_t bytes = XS + ZS + NWS * WS + 2 * NW * MT * 4 + 2 * MT * 4;
 };
 
 // ZT (BF16): z of every edge comes from the forward's tape (zt) instead of
@@ -168,15 +177,19 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
   constexpr size_t XS = L::XS, ZS = L::ZS, WS = L::WS;
   constexpr int LDW = L::LDW, LDF = L::LDF;
   static_assert(!FW || (sizeof(T) == 2 && H == 128), "fused weight gradients: BF16, H = 128");
+  static_assert(FW != 2 || ZT, "dW2-only fusion reads z from the tape");
   static_assert((size_t)MT * LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
   static_assert(!FW || (size_t)H * 4 <= 2 * H * sizeof(T), "FP32 rows must leave the e columns intact");
+  // z from the tape, fused weight gradients, ReLU: the FP32 tile's columns
+  // are free from the start of a tile, so dv is loaded with z and e
+  constexpr bool EARLY_DV = ZT && FW && ACT == 0;
   __shared__ __align__(16) unsigned char smem[L::bytes];
   T* xs = (T*)smem;
   float* ft = (float*)smem;
   T* zs = (T*)(smem + XS);
   bf16* W2s = (bf16*)(smem + XS + ZS);       // W2 [out][in]
-  bf16* W1es = (bf16*)(smem + XS + ZS + WS);  // W1[:, 2H:3H] [out][in]
-  float* red = (float*)(smem + XS + ZS + 2 * WS);
+  bf16* W1es = (bf16*)(smem + XS + ZS + WS);  // W1[:, 2H:3H] [out][in] (FW = 1)
+  float* red = (float*)(smem + XS + ZS + L::NWS * WS);
   int* rs = (int*)(red + 2 * NW * MT);
   const T* W1 = (const T*)w.W1;
   const T* W2 = (const T*)w.W2;
@@ -188,12 +201,13 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
   f32x4 accW2[NB][H / 16], accW1[NB][H / 16];
   if constexpr (FW) {
     zero_acc(accW2);
-    zero_acc(accW1);
+    if constexpr (FW == 1) zero_acc(accW1);
     // weights resident in LDS (visible after the first barrier of the tile loop)
     for (int c = threadIdx.x; c < H * (H / 8); c += 64 * NW) {
       const int r = c / (H / 8), q = c - r * (H / 8);
       *(uint4*)(W2s + r * LDW + 8 * q) = *(const uint4*)(W2 + (size_t)r * H + 8 * q);
-      *(uint4*)(W1es + r * LDW + 8 * q) = *(const uint4*)(W1 + (size_t)r * 3 * H + 2 * H + 8 * q);
+      if constexpr (FW == 1)
+        *(uint4*)(W1es + r * LDW + 8 * q) = *(const uint4*)(W1 + (size_t)r * 3 * H + 2 * H + 8 * q);
     }
   }
 
@@ -208,16 +222,16 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
       rs[threadIdx.x] = cur.rv;
       ss[threadIdx.x] = cur.cv;
     }
-    __syncthreads();
+    lds_sync();
     if constexpr (ZT) {
       // z rows into zs, (fused: for dW1's e-block) e rows into the e columns
       // of xs and (SiLU) a rows into its first H columns, one batch of loads
-      constexpr int NPART = 1 + (FW ? 1 : 0) + (ACT != 0 ? 1 : 0);
+      constexpr int NPART = 1 + (FW == 1 ? 1 : 0) + (ACT != 0 ? 1 : 0);
       constexpr int E8 = 16 / sizeof(T), CPR = H / E8, TOT = NPART * MT * CPR, IT = TOT / (64 * NW);
       static_assert(TOT % (64 * NW) == 0, "whole steps of the workgroup");
-      auto src = [&](int p) -> const T* { return p == 0 ? zt : (FW && p == 1) ? e : at; };
+      auto src = [&](int p) -> const T* { return p == 0 ? zt : (FW == 1 && p == 1) ? e : at; };
       auto dst = [&](int p, int i, int q) -> T* {
-        return p == 0 ? zs + i * D::LDH + q * E8 : (FW && p == 1) ? xs + i * D::LD3 + 2 * H + q * E8
+        return p == 0 ? zs + i * D::LDH + q * E8 : (FW == 1 && p == 1) ? xs + i * D::LD3 + 2 * H + q * E8
                                                                   : xs + i * D::LD3 + q * E8;
       };
       uint4 v[IT];
@@ -228,6 +242,11 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
         v[k] = uint4{0u, 0u, 0u, 0u};
         if (i < ne) v[k] = *(const uint4*)(src(p) + (size_t)(e0 + i) * H + q * E8);
       }
+      if constexpr (EARLY_DV)  // dv = dm_r + de' in the same round trip, into the FP32 tile
+        f32_tile<MT, H, 64 * NW>(
+            ne, de_in != nullptr, [&](int i, int q) { return *(const float4*)(dm + (size_t)rs[i] * H + 4 * q); },
+            [&](int i, int q) { return *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q); },
+            [&](int i, int q, const float4& w4) { *(float4*)(ft + i * LDF + 4 * q) = w4; });
 #pragma unroll
       for (int k = 0; k < IT; ++k) {
         const int c = (int)threadIdx.x + k * 64 * NW, p = c / (MT * CPR), rem = c - p * (MT * CPR);
@@ -241,7 +260,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
           [](int, int, int, const uint4&) {});
     }
     if (t + sch.step < sch.end) nx.load(b, t + sch.step);  // next tile's indices, in flight from here
-    __syncthreads();
+    lds_sync();
 
     // recompute: a, z, u, xhat (ZT, ReLU: a holds z, whose sign is a's)
     f32x4 a[MB][NB];
@@ -256,7 +275,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
           for (int r = 0; r < 4; ++r)
             a[mb][nb][r] = ACT == 0 ? to_f(zs[acc_row(mb, r) * D::LDH + acc_col(n0, nb)])
                                     : to_f(xs[acc_row(mb, r) * D::LD3 + acc_col(n0, nb)]);
-    } else if constexpr (FW) {
+    } else if constexpr (FW == 1) {
       wave_gemm<T, MB, NB, 2 * H, D::LD3>(a, xs, W1, 3 * H, n0);  // [h_r ; h_s] blocks from global
       wave_gemm_lds<MB, NB, H, D::LD3>(a, (const bf16*)xs + 2 * H, [&](int k, int nb) {
         return *(const bf16x8*)(W1es + (n0 + 16 * nb + li) * LDW + k + 8 * lg);
@@ -277,7 +296,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
           }
         }
       acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
-      __syncthreads();
+      lds_sync();
     }
     zero_acc(x);
     if constexpr (FW) {
@@ -299,12 +318,13 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
     ln_normalize<MB, NB, MT, H, NW>(x, red, eps, inv);  // x = xhat
 
     // upstream gradient dv = dm_r + de'_k  (FP32 tile over the dead gather)
-    f32_tile<MT, H, 64 * NW>(
-        ne, de_in != nullptr, [&](int i, int q) { return *(const float4*)(dm + (size_t)rs[i] * H + 4 * q); },
-        [&](int i, int q) { return *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q); },
-        [&](int i, int q, const float4& v) { *(float4*)(ft + i * LDF + 4 * q) = v; });
+    if constexpr (!EARLY_DV)
+      f32_tile<MT, H, 64 * NW>(
+          ne, de_in != nullptr, [&](int i, int q) { return *(const float4*)(dm + (size_t)rs[i] * H + 4 * q); },
+          [&](int i, int q) { return *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q); },
+          [&](int i, int q, const float4& v) { *(float4*)(ft + i * LDF + 4 * q) = v; });
     if constexpr (!FW && !ZT) lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.z + (size_t)e0 * H, H, [](int i) { return i; });
-    __syncthreads();
+    lds_sync();
     f32x4 g[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -316,10 +336,10 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
     col_accumulate(g, cb2);
     if constexpr (FW) {
       wave_wgrad<MB, NB, H, D::LDH>(accW2, g, (const bf16*)zs);  // dW2 += du^T z
-      __syncthreads();  // every wave is done reading z before du replaces it
+      lds_sync();  // every wave is done reading z before du replaces it
     }
     acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
-    __syncthreads();
+    lds_sync();
     if constexpr (!FW) lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.du + (size_t)e0 * H, H, [](int i) { return i; });
     // dz = W2^T du ; da = dz * act'(a)
     zero_acc(x);
@@ -337,11 +357,27 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
 #pragma unroll
         for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a[mb][nb][r]);
     col_accumulate(x, cb1);
-    if constexpr (FW) wave_wgrad<MB, NB, H, D::LD3>(accW1, x, (const bf16*)xs + 2 * H);  // dW1[:, 2H:3H] += da^T e
-    __syncthreads();
+    if constexpr (FW == 1) wave_wgrad<MB, NB, H, D::LD3>(accW1, x, (const bf16*)xs + 2 * H);  // dW1[:, 2H:3H] += da^T e
+    lds_sync();
     acc_to_ldsf<MB, NB, LDF>(x, ft, n0);
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
-    __syncthreads();
+    lds_sync();
+    // de' (+ dm_r) for de_out, in flight while S_r and the de product run
+    constexpr int IT2 = MT * (H / 4) / (64 * NW);
+    static_assert(MT * (H / 4) % (64 * NW) == 0, "whole steps of the workgroup");
+    float4 dep[FW ? IT2 : 1];
+    if constexpr (FW) {
+#pragma unroll
+      for (int k = 0; k < IT2; ++k) {
+        const int c = (int)threadIdx.x + k * 64 * NW, i = c / (H / 4), q = c - i * (H / 4);
+        float4 va = float4{0.f, 0.f, 0.f, 0.f}, vb = float4{0.f, 0.f, 0.f, 0.f};
+        if (i < ne) {
+          if (de_in) va = *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q);
+          if (AGG != 0) vb = *(const float4*)(dm + (size_t)rs[i] * H + 4 * q);
+        }
+        dep[k] = float4{va.x + vb.x, va.y + vb.y, va.z + vb.z, va.w + vb.w};
+      }
+    }
     // S_r: receiver-segment sums of da (FP32, ascending sender order)
     const int nr = r1 - r0;
     for (int task = threadIdx.x; task < nr * (H / 4); task += 64 * NW) {
@@ -360,26 +396,37 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
     lds_rows_to_global<T, D::LDH>(zs, ne, H, (T*)o.da + (size_t)e0 * H, H, [](int i) { return i; });
     // de = de' (+ dm_r) + (W1^T da)[2H:3H]
     zero_acc(g);
-    if constexpr (FW) {
+    if constexpr (FW == 1) {
       wave_gemm_lds<MB, NB, H, D::LDH>(g, (const bf16*)zs, [&](int k, int nb) {
         return lds_bfrag_tr(W1es, LDW, k + 8 * lg, n0 + 16 * nb, 4);
       });
     } else {
       wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1Te, H, n0);
     }
-    __syncthreads();
+    lds_sync();
     acc_to_ldsf<MB, NB, LDF>(g, ft, n0);
-    __syncthreads();
-    f32_tile<MT, H, 64 * NW>(
-        ne, AGG != 0, [&](int i, int q) { return de_in ? *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q) : float4{0.f, 0.f, 0.f, 0.f}; },
-        [&](int i, int q) { return *(const float4*)(dm + (size_t)rs[i] * H + 4 * q); },
-        [&](int i, int q, const float4& v) {
-          if (i < ne) {
-            const float4 d = *(const float4*)(ft + i * LDF + 4 * q);
-            *(float4*)(o.de_out + (size_t)(e0 + i) * H + 4 * q) = float4{d.x + v.x, d.y + v.y, d.z + v.z, d.w + v.w};
-          }
-        });
-    __syncthreads();
+    lds_sync();
+    if constexpr (FW) {
+#pragma unroll
+      for (int k = 0; k < IT2; ++k) {
+        const int c = (int)threadIdx.x + k * 64 * NW, i = c / (H / 4), q = c - i * (H / 4);
+        if (i < ne) {
+          const float4 d = *(const float4*)(ft + i * LDF + 4 * q), v = dep[k];
+          *(float4*)(o.de_out + (size_t)(e0 + i) * H + 4 * q) = float4{d.x + v.x, d.y + v.y, d.z + v.z, d.w + v.w};
+        }
+      }
+    } else {
+      f32_tile<MT, H, 64 * NW>(
+          ne, AGG != 0, [&](int i, int q) { return de_in ? *(const float4*)(de_in + (size_t)(e0 + i) * H + 4 * q) : float4{0.f, 0.f, 0.f, 0.f}; },
+          [&](int i, int q) { return *(const float4*)(dm + (size_t)rs[i] * H + 4 * q); },
+          [&](int i, int q, const float4& v) {
+            if (i < ne) {
+              const float4 d = *(const float4*)(ft + i * LDF + 4 * q);
+              *(float4*)(o.de_out + (size_t)(e0 + i) * H + 4 * q) = float4{d.x + v.x, d.y + v.y, d.z + v.z, d.w + v.w};
+            }
+          });
+    }
+    lds_sync();
   }
   float* p = o.partial + (size_t)blockIdx.x * 4 * H;
   write_partial<NB>(p, n0, cb1);
@@ -397,7 +444,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
         for (int r = 0; r < 4; ++r) {
           const int m = n0 + nb * 16 + lg * 4 + r, n = jb * 16 + li;
           q2[m * H + n] = accW2[nb][jb][r];
-          q1[m * H + n] = accW1[nb][jb][r];
+          if constexpr (FW == 1) q1[m * H + n] = accW1[nb][jb][r];
         }
   }
 }
@@ -462,7 +509,7 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
     const int row0 = t * MT, nr = min(MT, n - row0);
     global_rows_to_lds<T, D::LD2, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
     global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
-    __syncthreads();
+    lds_sync();
     f32x4 a[MB][NB], x[MB][NB];
     zero_acc(a);
     if constexpr (FN) {
@@ -484,7 +531,7 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
         }
       }
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
-    __syncthreads();
+    lds_sync();
     zero_acc(x);
     if constexpr (FN) {
       wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)zs, [&](int k, int nb) {
@@ -505,7 +552,7 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
     ln_normalize<MB, NB, MT, H>(x, red, eps, inv);
     f32_rows_to_lds<H, D::LDF, MT>(ft, nr, [&](int i, int q) { return *(const float4*)(dh_in + (size_t)(row0 + i) * H + 4 * q); });
     if constexpr (!FN) lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z + (size_t)row0 * H, H, [](int i) { return i; });
-    __syncthreads();
+    lds_sync();
     f32x4 g[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -517,10 +564,10 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
     col_accumulate(g, cb2);
     if constexpr (FN) {
       wave_wgrad<MB, NB, H, D::LDH>(accW2, g, (const bf16*)zs);  // dW2 += du^T z
-      __syncthreads();  // every wave is done reading z before du replaces it
+      lds_sync();  // every wave is done reading z before du replaces it
     }
     acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
-    __syncthreads();
+    lds_sync();
     zero_acc(x);
     if constexpr (FN) {
       wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)zs, [&](int k, int nb) {
@@ -541,9 +588,9 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
       wave_wgrad<MB, NB, H, D::LD2>(accW1h, x, (const bf16*)xs);      // dW1[:, 0:H] += da^T h
       wave_wgrad<MB, NB, H, D::LD2>(accW1m, x, (const bf16*)xs + H);  // dW1[:, H:2H] += da^T m
     }
-    __syncthreads();
+    lds_sync();
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
-    __syncthreads();
+    lds_sync();
     if constexpr (!FN)
       lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.da + (size_t)row0 * H, H, [](int i) { return i; });
     zero_acc(g);
@@ -560,7 +607,7 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
       wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W1T + (size_t)H * H, H, n0);  // -> dm
     }
     acc_to_ldsf<MB, NB, D::LDF>(g, ft, n0);
-    __syncthreads();
+    lds_sync();
     f32_tile<MT, H, NTHR>(
         nr, false, [&](int i, int q) { return *(const float4*)(dh_in + (size_t)(row0 + i) * H + 4 * q); },
         [](int, int) { return float4{0.f, 0.f, 0.f, 0.f}; },
@@ -570,14 +617,14 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
             *(float4*)(o.dh_mid + (size_t)(row0 + i) * H + 4 * q) = float4{v.x + d.x, v.y + d.y, v.z + d.z, v.w + d.w};
           }
         });
-    __syncthreads();
+    lds_sync();
     acc_to_ldsf<MB, NB, D::LDF>(x, ft, n0);
-    __syncthreads();
+    lds_sync();
     for (int c = threadIdx.x; c < nr * (H / 4); c += NTHR) {
       const int i = c / (H / 4), q = c - i * (H / 4);
       *(float4*)(o.dm + (size_t)(row0 + i) * H + 4 * q) = *(const float4*)(ft + i * D::LDF + 4 * q);
     }
-    __syncthreads();
+    lds_sync();
   }
   float* p = o.partial + (size_t)blockIdx.x * 4 * H;
   write_partial<NB>(p, n0, cb1);
@@ -618,12 +665,12 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_node_dh(int n, const
     const int row0 = t * MT, nr = min(MT, n - row0);
     global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, 0, [&](int i) { return S_r + (size_t)(row0 + i) * H; });
     global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, H, [&](int i) { return S_s + (size_t)(row0 + i) * H; });
-    __syncthreads();
+    lds_sync();
     f32x4 acc[MB][NB];
     zero_acc(acc);
     wave_gemm<T, MB, NB, 2 * H, D::LD2>(acc, xs, Brs, 2 * H, n0);
     acc_to_ldsf<MB, NB, D::LDF>(acc, ft, n0);
-    __syncthreads();
+    lds_sync();
     f32_tile<MT, H, NTHR>(
         nr, false, [&](int i, int q) { return *(const float4*)(dh_mid + (size_t)(row0 + i) * H + 4 * q); },
         [](int, int) { return float4{0.f, 0.f, 0.f, 0.f}; },
@@ -633,7 +680,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_node_dh(int n, const
             *(float4*)(dh_out + (size_t)(row0 + i) * H + 4 * q) = float4{v.x + d.x, v.y + d.y, v.z + d.z, v.w + d.w};
           }
         });
-    __syncthreads();
+    lds_sync();
   }
 }
 
@@ -707,7 +754,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_bwd(BatchView b,
       const int i = c >> 4, oo = c & 15;
       dys[c] = (i < nr && oo < out_dim) ? d_out[(size_t)b.gid[b.inner[row0 + i]] * out_dim + oo] : 0.f;
     }
-    __syncthreads();
+    lds_sync();
     if ((int)threadIdx.x < out_dim)
       for (int i = 0; i < nr; ++i) cb3 += dys[i * 16 + threadIdx.x];
     f32x4 a1[MB][NB], a2[MB][NB], x[MB][NB];
@@ -725,7 +772,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_bwd(BatchView b,
         }
       }
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
-    __syncthreads();
+    lds_sync();
     zero_acc(a2);
     wave_gemm<T, MB, NB, H, D::LDH>(a2, zs, W2, H, n0);
 #pragma unroll
@@ -746,13 +793,13 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_bwd(BatchView b,
       }
     col_accumulate(a2, cb2);
     acc_to_lds<T, MB, NB, D::LDH>(x, z2s, n0);
-    __syncthreads();
+    lds_sync();
     lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.z2 + (size_t)row0 * H, H, [](int i) { return i; });
     lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z1 + (size_t)row0 * H, H, [](int i) { return i; });
     for (int c = threadIdx.x; c < nr * 16; c += NTHR) o.dy[(size_t)row0 * 16 + c] = dys[c];
-    __syncthreads();
+    lds_sync();
     acc_to_lds<T, MB, NB, D::LDH>(a2, z2s, n0);
-    __syncthreads();
+    lds_sync();
     lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.da2 + (size_t)row0 * H, H, [](int i) { return i; });
     zero_acc(x);
     wave_gemm<T, MB, NB, H, D::LDH>(x, z2s, W2T, H, n0);
@@ -763,19 +810,19 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_bwd(BatchView b,
 #pragma unroll
         for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a1[mb][nb][r]);
     col_accumulate(x, cb1);
-    __syncthreads();
+    lds_sync();
     acc_to_lds<T, MB, NB, D::LDH>(x, z2s, n0);
-    __syncthreads();
+    lds_sync();
     lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.da1 + (size_t)row0 * H, H, [](int i) { return i; });
     zero_acc(x);
     wave_gemm<T, MB, NB, H, D::LDH>(x, z2s, W1T, H, n0);
     acc_to_ldsf<MB, NB, D::LDF>(x, ft, n0);
-    __syncthreads();
+    lds_sync();
     for (int c = threadIdx.x; c < nr * (H / 4); c += NTHR) {
       const int i = c / (H / 4), q = c - i * (H / 4);
       *(float4*)(o.dh + (size_t)b.inner[row0 + i] * H + 4 * q) = *(const float4*)(ft + i * D::LDF + 4 * q);
     }
-    __syncthreads();
+    lds_sync();
   }
   float* p = o.partial + (size_t)blockIdx.x * (2 * H + 16);
   write_partial<NB>(p, n0, cb1);
@@ -864,7 +911,7 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
         xin[task] = (i < nr && k < in_dim) ? src[(size_t)b.gid[row0 + i] * in_dim + k] : 0.f;
       }
     }
-    __syncthreads();
+    lds_sync();
     f32x4 a1[MB][NB], a2[MB][NB], x[MB][NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
@@ -903,7 +950,7 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
         for (int r = 0; r < 4; ++r) x[mb][nb][r] = act_f<ACT>(a1[mb][nb][r]);
     }
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
-    __syncthreads();
+    lds_sync();
     zero_acc(a2);
     if constexpr (FE) {
       wave_gemm_lds<MB, NB, H, D::LDH>(a2, (const bf16*)zs, [&](int k, int nb) {
@@ -924,7 +971,7 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
         }
       }
     acc_to_lds<T, MB, NB, D::LDH>(x, z2s, n0);
-    __syncthreads();
+    lds_sync();
     zero_acc(x);
     if constexpr (FE) {
       wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)z2s, [&](int k, int nb) {
@@ -948,7 +995,7 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
       lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z1 + (size_t)row0 * H, H, [](int i) { return i; });
       lds_rows_to_global<T, D::LDH>(z2s, nr, H, (T*)o.z2 + (size_t)row0 * H, H, [](int i) { return i; });
     }
-    __syncthreads();
+    lds_sync();
     f32x4 g[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -962,13 +1009,13 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
     if constexpr (FE) {
       wave_wgrad<MB, NB, H, D::LDH>(accW3, g, (const bf16*)z2s);  // dW3 += du3^T z2
       acc_to_lds<T, MB, NB, D::LDH>(g, du3s, n0);
-      __syncthreads();
+      lds_sync();
       wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)du3s, [&](int k, int nb) {
         return lds_bfrag_tr(W3s, LDW, k + 8 * lg, n0 + 16 * nb, 4);
       });
     } else {
       acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
-      __syncthreads();
+      lds_sync();
       lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.du3 + (size_t)row0 * H, H, [](int i) { return i; });
       wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W3T, H, n0);
     }
@@ -980,9 +1027,9 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
         for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a2[mb][nb][r]);
     col_accumulate(x, cb2);
     if constexpr (FE) wave_wgrad<MB, NB, H, D::LDH>(accW2, x, (const bf16*)zs);  // dW2 += da2^T z1
-    __syncthreads();
+    lds_sync();
     acc_to_lds<T, MB, NB, D::LDH>(x, z2s, n0);
-    __syncthreads();
+    lds_sync();
     zero_acc(x);
     if constexpr (FE) {
       wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)z2s, [&](int k, int nb) {
@@ -1022,7 +1069,7 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
             if (row < nr) o.da1[(size_t)(row0 + row) * H + acc_col(n0, nb)] = x[mb][nb][r];
           }
     }
-    __syncthreads();
+    lds_sync();
   }
   float* p = o.partial + (size_t)blockIdx.x * 13 * H;
   write_partial<NB>(p, n0, cb1);
@@ -1095,6 +1142,17 @@ __global__ __launch_bounds__(NTHR) void k_enc_bwd(int rows, BatchView b, MlpW w,
     constexpr int MT = 32;                 \
     __VA_ARGS__                            \
   }
+// Edge tiles (whole receiver segments): 64 or 32 rows at H = 128, and in the
+// BF16 form also at H = 256 (a 64-row BF16 tile of [h_r | h_s | e] fits in
+// LDS there and halves the weight bytes streamed per edge); 32 otherwise.
+#define XMGN_DISPATCH_MT_EDGE(mt, ...)                                 \
+  if (mt == 64 && (H == 128 || (H == 256 && sizeof(T) == 2))) {       \
+    constexpr int MT = (H == 128 || (H == 256 && sizeof(T) == 2)) ? 64 : 32; \
+    __VA_ARGS__                                                        \
+  } else {                                                             \
+    constexpr int MT = 32;                                             \
+    __VA_ARGS__                                                        \
+  }
 
 template <typename T, int H, int MT>
 constexpr bool edge_bwd_fits() {
@@ -1108,13 +1166,19 @@ constexpr bool node_fits() {
 }
 
 bool edge_bwd_fuses_wgrad(const Shape& s) { return s.prec == 1 && s.H == 128; }
+bool edge_bwd_fuses_dw1e(const Shape& s, bool ztape) {
+  return edge_bwd_fuses_wgrad(s) && !(ztape && s.mt_edge == 32);
+}
 
 template <int NW>
 static void edge_bwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
                         const void* zt, const void* at, const float* de_in, const float* dm, const EdgeBwdOut& o,
                         hipStream_t st) {
-  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
-    constexpr int FW = (sizeof(T) == 2 && H == 128) ? 1 : 0;
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT_EDGE(s.mt_edge, {
+    // z from the tape: dW2-only fusion on 32-row tiles (two workgroups per
+    // CU), both blocks fused on 64-row tiles; recompute: both fused
+    constexpr int FW = (sizeof(T) == 2 && H == 128) ? (MT == 32 ? 2 : 1) : 0;
+    constexpr int FWR = (sizeof(T) == 2 && H == 128) ? 1 : 0;
     constexpr int ZT = 1;
     if constexpr (edge_bwd_fits<T, H, MT>()) {
       if (zt && ACT != 0 && !at) {
@@ -1128,10 +1192,10 @@ static void edge_bwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const
               b, w, (const T*)h, (const T*)e, (const T*)zt, (const T*)at, de_in, dm, o, s.eps);
       } else {
         if (s.agg)
-          k_edge_bwd<T, H, MT, ACT, 1, FW, NW, 0><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, nullptr,
+          k_edge_bwd<T, H, MT, ACT, 1, FWR, NW, 0><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, nullptr,
                                                                               nullptr, de_in, dm, o, s.eps);
         else
-          k_edge_bwd<T, H, MT, ACT, 0, FW, NW, 0><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, nullptr,
+          k_edge_bwd<T, H, MT, ACT, 0, FWR, NW, 0><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, nullptr,
                                                                               nullptr, de_in, dm, o, s.eps);
       }
     } else {

@@ -68,13 +68,13 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
       rs[threadIdx.x] = cur.rv;
       ss[threadIdx.x] = cur.cv;
     }
-    __syncthreads();
+    lds_sync();
     gather_tile<T, D::LD3, MT, 3, H, 64 * NW>(
         xs, ne,
         [&](int p, int i) { return p == 0 ? h + (size_t)rs[i] * H : p == 1 ? h + (size_t)ss[i] * H : e + (size_t)(e0 + i) * H; },
         [](int, int, int, const uint4&) {});
     if (t + sch.step < sch.end) nx.load(b, t + sch.step);  // next tile's indices, in flight from here
-    __syncthreads();
+    lds_sync();
 
     f32x4 acc[MB][NB];
     zero_acc(acc);
@@ -94,9 +94,9 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
       }
     if (a_out) {  // uniform: the pre-activation goes out through zs first
       acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
-      __syncthreads();
+      lds_sync();
       lds_rows_to_global<T, D::LDH>(zs, ne, H, a_out + (size_t)e0 * H, H, [](int i) { return i; });
-      __syncthreads();
+      lds_sync();
     }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r]);
     acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
-    __syncthreads();
+    lds_sync();
     if (z_out) lds_rows_to_global<T, D::LDH>(zs, ne, H, z_out + (size_t)e0 * H, H, [](int i) { return i; });
 
     zero_acc(acc);
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
           zs[row * D::LDH + c] = from_f<T>(en);
         }
       }
-    __syncthreads();
+    lds_sync();
 
     // m_r: sequential sum over the receiver's edges (ascending sender id)
     const int nr = r1 - r0;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
       *(float4*)(m + (size_t)(r0 + rl) * H + 4 * q) = s;
     }
     if (e_out) lds_rows_to_global<T, D::LDH>(zs, ne, H, e_out + (size_t)e0 * H, H, [](int i) { return i; });
-    __syncthreads();
+    lds_sync();
   }
 }
 
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_node_fwd(int n, MlpW
     const int row0 = t * MT, nr = min(MT, n - row0);
     global_rows_to_lds<T, D::LD2, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
     global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
-    __syncthreads();
+    lds_sync();
     f32x4 acc[MB][NB];
     zero_acc(acc);
     wave_gemm<T, MB, NB, 2 * H, D::LD2>(acc, xs, W1, 2 * H, n0);
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_node_fwd(int n, MlpW
         }
       }
     acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
-    __syncthreads();
+    lds_sync();
     zero_acc(acc);
     wave_gemm<T, MB, NB, H, D::LDH>(acc, zs, W2, H, n0);
 #pragma unroll
@@ -223,9 +223,9 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_node_fwd(int n, MlpW
         for (int r = 0; r < 4; ++r)
           zs[acc_row(mb, r) * D::LDH + c] = from_f<T>(hv[mb][nb][r] + g * acc[mb][nb][r] + be);
       }
-    __syncthreads();
+    lds_sync();
     lds_rows_to_global<T, D::LDH>(zs, nr, H, h_out + (size_t)row0 * H, H, [](int i) { return i; });
-    __syncthreads();
+    lds_sync();
   }
 }
 
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_enc_fwd(int rows, Ba
         xin[task] = (i < nr && k < in_dim) ? src[(size_t)b.gid[row0 + i] * in_dim + k] : 0.f;
       }
     }
-    __syncthreads();
+    lds_sync();
     f32x4 acc[MB][NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_enc_fwd(int rows, Ba
       }
     }
     acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
-    __syncthreads();
+    lds_sync();
     zero_acc(acc);
     wave_gemm<T, MB, NB, H, D::LDH>(acc, zs, W2, H, n0);
 #pragma unroll
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_enc_fwd(int rows, Ba
         for (int r = 0; r < 4; ++r) acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r] + bb);
       }
     acc_to_lds<T, MB, NB, D::LDH>(acc, z2, n0);
-    __syncthreads();
+    lds_sync();
     zero_acc(acc);
     wave_gemm<T, MB, NB, H, D::LDH>(acc, z2, W3, H, n0);
 #pragma unroll
@@ -372,9 +372,9 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_enc_fwd(int rows, Ba
 #pragma unroll
         for (int r = 0; r < 4; ++r) zs[acc_row(mb, r) * D::LDH + c] = from_f<T>(g * acc[mb][nb][r] + be);
       }
-    __syncthreads();
+    lds_sync();
     lds_rows_to_global<T, D::LDH>(zs, nr, H, out + (size_t)row0 * H, H, [](int i) { return i; });
-    __syncthreads();
+    lds_sync();
   }
 }
 
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_fwd(BatchView b,
   for (int t = sch.begin; t < sch.end; t += sch.step) {
     const int row0 = t * MT, nr = min(MT, b.n_inner - row0);
     global_rows_to_lds<T, D::LDH, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)b.inner[row0 + i] * H; });
-    __syncthreads();
+    lds_sync();
     f32x4 acc[MB][NB];
     zero_acc(acc);
     wave_gemm<T, MB, NB, H, D::LDH>(acc, xs, W1, H, n0);
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_fwd(BatchView b,
         for (int r = 0; r < 4; ++r) acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r] + bb);
       }
     acc_to_lds<T, MB, NB, D::LDH>(acc, zs, n0);
-    __syncthreads();
+    lds_sync();
     zero_acc(acc);
     wave_gemm<T, MB, NB, H, D::LDH>(acc, zs, W2, H, n0);
 #pragma unroll
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_fwd(BatchView b,
         for (int r = 0; r < 4; ++r) acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r] + bb);
       }
     acc_to_lds<T, MB, NB, D::LDH>(acc, xs, n0);
-    __syncthreads();
+    lds_sync();
     for (int task = threadIdx.x; task < nr * out_dim; task += NTHR) {
       const int i = task / out_dim, o = task - i * out_dim;
       const float* wr = w.W1f + (size_t)o * H;  // decoder W3 (FP32)
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_fwd(BatchView b,
       for (int j = 0; j < H; ++j) y += wr[j] * to_f(z[j]);
       out[(size_t)b.gid[b.inner[row0 + i]] * out_dim + o] = y + w.b3[o];
     }
-    __syncthreads();
+    lds_sync();
   }
 }
 
@@ -483,6 +483,17 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_dec_fwd(BatchView b,
     constexpr int MT = 32;                 \
     __VA_ARGS__                            \
   }
+// Edge tiles (whole receiver segments): 64 or 32 rows at H = 128, and in the
+// BF16 form also at H = 256 (a 64-row BF16 tile of [h_r | h_s | e] fits in
+// LDS there and halves the weight bytes streamed per edge); 32 otherwise.
+#define XMGN_DISPATCH_MT_EDGE(mt, ...)                                 \
+  if (mt == 64 && (H == 128 || (H == 256 && sizeof(T) == 2))) {       \
+    constexpr int MT = (H == 128 || (H == 256 && sizeof(T) == 2)) ? 64 : 32; \
+    __VA_ARGS__                                                        \
+  } else {                                                             \
+    constexpr int MT = 32;                                             \
+    __VA_ARGS__                                                        \
+  }
 
 template <typename T, int H, int MT>
 constexpr bool edge_fits() {
@@ -493,7 +504,7 @@ constexpr bool edge_fits() {
 template <int NW>
 static void edge_fwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e, void* e_out,
                         float* m, void* z_out, void* a_out, hipStream_t st) {
-  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT(s.mt_edge, {
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT_EDGE(s.mt_edge, {
     if constexpr (edge_fits<T, H, MT>()) {
       if (s.agg)
         k_edge_fwd<T, H, MT, ACT, 1, NW><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m,

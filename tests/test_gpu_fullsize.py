@@ -13,7 +13,7 @@ benchmark times.
 import numpy as np
 import pytest
 
-from cases import Case, check_step, cone_graph, log, rel_l2
+from cases import Case, check_step, cone_graph, log, per_tensor_errors, rel_l2
 from oracle import graph as og
 from oracle import model as om
 from oracle import partition as opart
@@ -70,8 +70,7 @@ def sampled_outputs(case, G, seeds):
     return y[: len(seeds)], len(c.gid)
 
 
-@pytest.mark.parametrize("cfg,precision,tol,n_seeds", [(2, "fp32", 1e-4, 6), (2, "bf16", 2e-2, 6),
-                                                       (3, "bf16", 2e-2, 2), (3, "fp32", 1e-4, 2)])
+@pytest.mark.parametrize("cfg,precision,tol,n_seeds", [(2, "fp32", 1e-4, 6), (2, "bf16", 2e-2, 6)])
 def test_fullsize_sampled_outputs(api, ctx, cfg, precision, tol, n_seeds):
     case = Case(cfg, precision=precision)
     log(f"full-size cfg={cfg} {precision}: N={case.N}")
@@ -144,19 +143,55 @@ def test_graph_replay_equals_eager(api, ctx):
         assert torch.equal(r.dp, g0)
 
 
-def test_fullsize_car_4m_sampled_outputs(api, ctx):
-    """The 4M-point car recipe at H = 256 (BF16, 15 layers) as one batch:
-    outputs of sampled nodes against the oracle through their 15-hop
-    in-cones, and the kNN rows of every node of those cones bit for bit."""
+def test_graph_replay_multi_wave(api):
+    """A step over several batches (two waves of two partitions, gradients
+    accumulated) captured as one HIP graph: the context keeps one batch plan
+    per wave, so after one eager step the capture needs no plan upload and
+    no allocation, and every replay equals the eager step bit for bit."""
+    case = Case(4, levels=(2000, 8000, 32000), layers=3, precision="bf16")
+    ctx = api.Context(0)
+    g = ctx.build_knn(dev(case.inp.pos), case.levels, case.k_intra, case.k_cross)
+    ps = api.Partset.halo(g, case.inp.pos, [9000, 7000, 10000, 6000], case.L)
+    r = Run(api, ctx, case, ps=ps, g=g)
+    waves = [[0, 1], [2, 3]]
+    acc = torch.zeros_like(r.p)
+
+    def step():
+        acc.zero_()
+        for w in waves:
+            r.part_ids = w
+            r.step()
+            api.grad_accumulate(acc, r.dp)
+
+    step()
+    torch.cuda.synchronize()
+    a0, y0 = acc.clone(), r.out.clone()
+    mem = ctx.memory()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        step()
+    assert ctx.memory() == mem  # nothing was allocated under capture
+    for i in range(3):
+        acc.fill_(float("nan"))
+        r.out.zero_()
+        gr.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(acc, a0), i
+        assert torch.equal(r.out, y0), i
+        step()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(acc, a0), i
+
+
+def test_fullsize_car_4m_knn_cones(api, ctx):
+    """The 4M-point car recipe's multi-scale kNN graph built on the GPU: the
+    kNN rows of every node of two sampled nodes' 15-hop in-cones, bit for
+    bit against the oracle's exact kNN of those nodes."""
     from scipy.spatial import cKDTree
     case = Case(5, precision="bf16")
-    log(f"full-size car: N={case.N}")
-    r = Run(api, ctx, case)
-    r.ctx.forward(r.model, r.p, r.ps, r.part_ids, r.node_in, r.pos, case.inp.edge_norm, r.out, keep_tape=False)
-    torch.cuda.synchronize()
-    y = r.out.cpu().numpy()
-    assert np.isfinite(y).all()
-    rp, col = r.g.export()
+    log(f"full-size car kNN: N={case.N}")
+    g = ctx.build_knn(dev(case.inp.pos), case.levels, case.k_intra, case.k_cross)
+    rp, col = g.export()
     pos64 = case.inp.pos.astype(np.float64)
     trees = {n_l: cKDTree(pos64[:n_l]) for n_l in case.levels}
     rng = np.random.default_rng(99)
@@ -165,25 +200,65 @@ def test_fullsize_car_4m_sampled_outputs(api, ctx):
         rows = np.flatnonzero(np.diff(G.row_ptr) > 0)
         for q in rows:
             assert (col[rp[q]:rp[q + 1]] == G.col[G.row_ptr[q]:G.row_ptr[q + 1]]).all(), q
-        c = opart.in_cone(G, [s], case.L)
-        yo = om.forward(case.desc, case.params.astype(np.float64), c.graph, case.inp.node_in[c.gid],
-                        case.inp.pos[c.gid], case.inp.edge_norm)
-        ya = om.forward(case.desc, om.amp_cast(case.desc, case.params), c.graph, case.inp.node_in[c.gid],
-                        case.inp.pos[c.gid], case.inp.edge_norm)
-        e, ea = rel_l2(y[s], yo[0]), rel_l2(y[s], ya[0])
-        log(f"  seed {s}: in-cone {len(c.gid)} nodes, {len(rows)} kNN rows bit-exact, rel-L2 {e:.2e} "
-            f"(cast weights {ea:.2e})")
-        assert e <= 2e-2 and ea <= 2e-2
+        log(f"  seed {s}: {len(rows)} kNN rows bit-exact")
 
 
-def test_fullsize_partition_gradient(api, ctx):
+# partitions per batch as the benchmark runs each workload
+BENCH_WAVE_PARTS = {"ellipsoid-ms-400k": 1, "car-ms-4m-16p": 2}
+
+
+@pytest.mark.parametrize("workload,precision", [("ellipsoid-ms-400k", "bf16"), ("ellipsoid-ms-400k", "fp32"),
+                                                ("car-ms-4m-16p", "bf16")])
+def test_fullsize_64_seeds(api, workload, precision):
+    """Outputs of 64 seeded nodes of the full-size workload, run as the
+    benchmark runs it (the car in its 16 partitions, two per batch; tiles
+    from the autotuner), against the FP64 oracle's outputs through each
+    node's 15-hop in-cone, precomputed from oracle/ alone by
+    tests/golden/make_fullsize_golden.py: FP32 within 1e-4 of the model;
+    BF16 within 2e-2 of the model and of the bfloat16-cast weights."""
+    import json
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_fullsize_golden as mg
+    rec = json.load(open(mg.fixture_path(workload)))
+    case = Case(rec["config"], precision=precision)
+    assert mg.inputs_digest(case) == rec["inputs_digest"], "stale fixture: rerun make_fullsize_golden.py"
+    seeds = np.asarray(rec["seeds"])
+    assert (mg.seeds_for(case, rec["config"]) == seeds).all()
+    ctx = api.Context(0)
+    g = ctx.build_knn(dev(case.inp.pos), case.levels, case.k_intra, case.k_cross)
+    n_parts = case.cfg.n_parts
+    ps = api.Partset.halo(g, case.inp.pos, case.inp.part_sizes if n_parts > 1 else None, case.L)
+    wp = BENCH_WAVE_PARTS[workload]
+    waves = [list(range(i, min(i + wp, n_parts))) for i in range(0, n_parts, wp)]
+    r = Run(api, ctx, case, part_ids=waves[0], ps=ps, g=g)
+    tiles = ctx.autotune(r.model, r.p, ps, waves[0], r.node_in, r.pos, case.inp.edge_norm, r.out, r.d_out, r.dp)
+    r.out.zero_()
+    for w in waves:
+        ctx.forward(r.model, r.p, ps, w, r.node_in, r.pos, case.inp.edge_norm, r.out, keep_tape=False)
+    torch.cuda.synchronize()
+    y = r.out.cpu().numpy()[seeds]
+    e_model = [rel_l2(y[i], rec["y_model"][i]) for i in range(len(seeds))]
+    e_cast = [rel_l2(y[i], rec["y_cast"][i]) for i in range(len(seeds))]
+    log(f"{workload} {precision}, tiles {tiles[:4]}, {len(waves)} batches: 64 seeds, worst rel-L2 vs model "
+        f"{max(e_model):.2e}, vs cast weights {max(e_cast):.2e}")
+    if precision == "fp32":
+        assert max(e_model) <= 1e-4, e_model
+    else:
+        assert max(e_model) <= 2e-2 and max(e_cast) <= 2e-2, (e_model, e_cast)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_fullsize_partition_gradient(api, ctx, precision):
     """One partition of the 1M-point, 24-part workload (its smallest, with
-    its 15-hop halo; FP32, 15 layers) in the configuration the benchmark
-    runs it: the partition's nodes against the oracle's RCB and halo, and
-    its outputs, loss and every gradient tensor G_p (before accumulation,
-    with the global normaliser) against the oracle's step on it."""
+    its 15-hop halo; 15 layers, both forms) in the configuration the
+    benchmark runs it: the partition's nodes against the oracle's RCB and
+    halo, and its outputs, loss and every gradient tensor G_p (before
+    accumulation, with the global normaliser) against the oracle's step on
+    it (BF16: also at the bfloat16-cast weights, as check_step spells out)."""
     from scipy.spatial import cKDTree
-    case = Case(4, precision="fp32")
+    case = Case(4, precision=precision)
     sizes = case.inp.part_sizes
     p = int(np.argmin(sizes))
     log(f"full-size partition {p} of {len(sizes)}: {sizes[p]} inner nodes of {case.N}")
@@ -199,7 +274,65 @@ def test_fullsize_partition_gradient(api, ctx):
     x = ps.export(p)
     assert (x["gid"] == P.gid).all() and (x["col"] == P.graph.col).all()
     log(f"  {len(P.gid)} local nodes, {P.graph.n_edges} edges: partition bit-exact")
-    refs = (om.step_part(case.desc, case.params.astype(np.float64), P, case.inp.node_in, case.inp.pos,
-                         case.inp.edge_norm, case.inp.targets, case.N), None)
+    args = (P, case.inp.node_in, case.inp.pos, case.inp.edge_norm, case.inp.targets, case.N)
+    refs = (om.step_part(case.desc, case.params.astype(np.float64), *args),
+            om.step_part(case.desc, om.amp_cast(case.desc, case.params), *args) if precision == "bf16" else None)
     y = r.out.cpu().numpy()[P.gid[: P.n_inner]]
     log("  " + check_step(case, y, float(r.loss.item()), r.dp.cpu().numpy(), refs))
+
+
+def test_fullsize_car_partition_gradients(api):
+    """The 4M-point car workload (H = 256, ReLU, 15 layers) split as the
+    benchmark splits it (16 RCB parts, 15-hop halos): for two of the 16
+    partitions, the ones with the fewest and the most local edges (the inner
+    counts are equal), the partition's gradient G_p before accumulation, run
+    over the whole partition at its real size, of a loss sum(w * y) over one
+    seeded inner node s (w seeded, d_out zero on every other row).  Only s's
+    15-hop in-cone reaches that loss (Eq. 4) and the partition's halo holds
+    all of it, so the oracle runs on the cone.  Such a one-node gradient is
+    ill-conditioned (on the oracle alone, perturbing the weights by 1e-4
+    moves it by about a hundred times more than the whole-graph loss's, and
+    the bfloat16 weight cast by 7-20%), so it is held to the FP32 bar: the
+    output at s within 1e-4, the whole gradient within 1e-4 and every tensor
+    within 1e-3 (ReLU kinks, as for the whole-graph FP32 bar)."""
+    from scipy.spatial import cKDTree
+    case = Case(5, precision="fp32")
+    ctx = api.Context(0)
+    g = ctx.build_knn(dev(case.inp.pos), case.levels, case.k_intra, case.k_cross)
+    sizes = case.inp.part_sizes
+    ps = api.Partset.halo(g, case.inp.pos, sizes, case.L)
+    local_edges = [ps.info(p)[2] for p in range(len(sizes))]  # equal inner counts: take the halo's spread
+    parts = [int(np.argmin(local_edges)), int(np.argmax(local_edges))]
+    assert parts[0] != parts[1]
+    pos64 = case.inp.pos.astype(np.float64)
+    trees = {n_l: cKDTree(pos64[:n_l]) for n_l in case.levels}
+    rng = np.random.default_rng(5099)
+    model = case.model(api)
+    p_dev, node_in, pos = dev(case.params), dev(case.inp.node_in), dev(case.inp.pos)
+    for p in parts:
+        x = ps.export(p)
+        s = int(rng.choice(x["gid"][: x["n_inner"]]))
+        w = rng.standard_normal(4).astype(np.float32)
+        log(f"car partition {p}: {x['n_inner']} inner, {len(x['gid'])} local nodes, {len(x['col'])} edges; seed {s}")
+        out = torch.zeros(case.N, 4, device="cuda")
+        ctx.forward(model, p_dev, ps, [p], node_in, pos, case.inp.edge_norm, out, keep_tape=True)
+        d_out = torch.zeros_like(out)
+        d_out[s] = torch.from_numpy(w).cuda()
+        d_params = torch.full_like(p_dev, float("nan"))
+        ctx.backward(model, p_dev, d_out, d_params)
+        torch.cuda.synchronize()
+        y_s, grad = out[s].cpu().numpy(), d_params.cpu().numpy()
+        assert np.isfinite(grad).all()
+        G = cone_graph(case, s, trees)
+        c = opart.in_cone(G, [s], case.L)
+        args = (c.graph, case.inp.node_in[c.gid], case.inp.pos[c.gid], case.inp.edge_norm)
+        dy = np.zeros((len(c.gid), 4))
+        dy[0] = w  # the seed is the cone's only inner node, local row 0
+        log(f"  oracle on the {len(c.gid)}-node cone")
+        y, saved = om.forward(case.desc, case.params.astype(np.float64), *args, keep=True)
+        g_ref = om.backward(case.desc, *args, saved, dy)
+        e_out, total = rel_l2(y_s, y[0]), rel_l2(grad, g_ref)
+        errs = per_tensor_errors(case, grad, g_ref)
+        worst = sorted(errs.items(), key=lambda kv: -kv[1])[:3]
+        log(f"  out {e_out:.2e}, grad {total:.2e}, worst tensor {worst}")
+        assert e_out <= 1e-4 and total <= 1e-4 and worst[0][1] <= 1e-3
