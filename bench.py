@@ -107,12 +107,15 @@ def kernel_flops(name: str, n: int, E: int, H: int, fused: int = 0, ztape: bool 
 
 
 def kernel_source_hash() -> str:
-    """Hash of the kernel sources; HBM counters taken on other sources are stale."""
+    """Hash of the device-code sources (.hip and .hpp; the host-side
+    api.cpp only picks among the kernels, and a traffic record names the
+    instantiation it measured); HBM counters taken on other sources are
+    stale."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2411_17164_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".cpp")):
+        if f.endswith((".hip", ".hpp")):
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -628,9 +628,11 @@ static Shape make_shape(const xmgn_ctx* c, const xmgn_model_desc* d) {
   }
   s.mt_edge = me;
   s.mt_node = mn;
-  // the edge adjoint may tile the same edges differently (BF16, H = 128:
-  // 32 or 64 rows, independent of the forward)
-  s.mt_edge_bwd = (d->hidden == 128 && d->precision == 1 && c->mt_edge_bwd > 0) ? c->mt_edge_bwd : me;
+  // the edge adjoint may tile the same edges differently (BF16, H = 128 and
+  // 256: 32 or 64 rows, independent of the forward)
+  s.mt_edge_bwd = ((d->hidden == 128 || d->hidden == 256) && d->precision == 1 && c->mt_edge_bwd > 0)
+                      ? c->mt_edge_bwd
+                      : me;
   s.grid = c->grid > 0 ? c->grid : 1024;
   s.nw_edge = c->nw_edge > 0 ? c->nw_edge : d->hidden == 512 ? 8 : 4;  // H = 512: fewer spills at 8 waves
   return s;
@@ -1644,10 +1646,14 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
         for (int wpc : {4, 8})
           if (!err) err = trial(er, 32, ((cus * wpc + 7) / 8) * 8, wv, 0);
     if (!err && d->hidden == 128) err = trial(best[0], 64, best[2], best[3], 0);
-    // stage 3 (BF16, H = 128): the edge adjoint on its own tile rows
-    if (!err && d->hidden == 128 && d->precision == 1)
-      for (int br : {32, 64})
-        if (!err && br != best[0]) err = trial(best[0], best[1], best[2], best[3], br);
+    // stage 3 (BF16, H = 128 and 256): the edge adjoint on its own tile rows,
+    // paired with either forward tiling (stage 1 timed equal rows only)
+    if (!err && (d->hidden == 128 || d->hidden == 256) && d->precision == 1) {
+      const int nr = best[1], g = best[2], wv = best[3];
+      for (int er : rows)
+        for (int br : {32, 64})
+          if (!err && br != er) err = trial(er, nr, g, wv, br);
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (err) return err;

@@ -239,6 +239,24 @@ def test_adjoint_tiles_relu_bf16(api, bwd_rows, agg):
     log(f"  adjoint tiles {bwd_rows} relu {agg}: " + check_step(case, out, loss, grad, oracle_refs(case)))
 
 
+@pytest.mark.parametrize("fwd_rows,bwd_rows", [(64, 32), (32, 64)])
+@pytest.mark.parametrize("act", ["relu", "silu"])
+def test_adjoint_tiles_h256_bf16(api, fwd_rows, bwd_rows, act):
+    """H = 256 (the 4M-point car recipe's width, reduced) with the edge
+    adjoint on tile rows other than the forward's: the adjoint's plan tiles
+    the same receiver segments on its own, and reads z (and a) from the tape
+    by edge id whatever tile wrote them."""
+    c = api.Context(0)
+    c.set_tiles(fwd_rows, 32, 512, 4)
+    c.set_bwd_tiles(bwd_rows)
+    case = Case(5, levels=(400, 1600, 5000), layers=3, precision="bf16", activation=act)
+    assert case.H == 256
+    g = gpu_graph(api, c, case)
+    ps = api.Partset.halo(g, case.inp.pos, None, case.L)
+    out, loss, grad = gpu_step(api, c, case, ps, [0])
+    log(f"  H=256 tiles {fwd_rows}/{bwd_rows} {act}: " + check_step(case, out, loss, grad, oracle_refs(case)))
+
+
 def test_fwd_bwd_silu_fp32(api, ctx):
     case = Case(2, levels=(3000,), layers=3, activation="silu")
     log("fwd+bwd silu fp32")
