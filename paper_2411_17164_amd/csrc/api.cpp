@@ -983,9 +983,10 @@ static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32
     std::vector<int32_t> fill(csc_ptr.begin(), csc_ptr.end() - 1);
     for (int64_t k = 0; k < E; ++k) csc_edge[fill[col[k]]++] = (int32_t)k;
   }
-  // edge tiles: whole receiver segments, at most mt edges and receivers
+  // edge tiles: whole receiver segments, at most mt edges and receivers;
+  // each boundary as a (receiver, edge) pair
   auto make_tiles = [&](int mt) {
-    std::vector<int32_t> t{0};
+    std::vector<int32_t> t{0, 0};
     for (int64_t r = 0; r < n;) {
       int64_t cnt = 0, r1 = r;
       while (r1 < n && r1 - r < mt && cnt + (row_ptr[r1 + 1] - row_ptr[r1]) <= mt) {
@@ -993,14 +994,15 @@ static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32
         ++r1;
       }
       t.push_back((int32_t)r1);
+      t.push_back(row_ptr[r1]);
       r = r1;
     }
     return t;
   };
   etiles = make_tiles(mt_edge);
   const std::vector<int32_t> etiles_b = mt_edge_bwd == mt_edge ? std::vector<int32_t>{} : make_tiles(mt_edge_bwd);
-  const int64_t nt = (int64_t)etiles.size() - 1;
-  const int64_t total = n + (n + 1) + E + E + (n + 1) + E + (nt + 1) + ni + (int64_t)etiles_b.size();
+  const int64_t nt = (int64_t)etiles.size() / 2 - 1;
+  const int64_t total = n + (n + 1) + E + E + (n + 1) + E + 2 * (nt + 1) + ni + (int64_t)etiles_b.size() + 2;
   if (xmgn_status s = B.ints.ensure((size_t)total * 4, st)) return s;
   int32_t* d = B.ints.as<int32_t>();
   int64_t o = 0;
@@ -1019,14 +1021,16 @@ static xmgn_status ensure_batch(xmgn_ctx* c, const xmgn_partset* ps, const int32
   V.recv = up(recv);
   V.csc_ptr = up(csc_ptr);
   V.csc_edge = up(csc_edge);
+  o += o & 1;  // the (receiver, edge) pairs are read as 8-byte loads
   V.etiles = up(etiles);
   V.n_etiles = (int)nt;
   V.inner = up(inner);
   V.n_inner = (int)ni;
   B.view_b = V;
   if (!etiles_b.empty()) {
+    o += o & 1;
     B.view_b.etiles = up(etiles_b);
-    B.view_b.n_etiles = (int)etiles_b.size() - 1;
+    B.view_b.n_etiles = (int)etiles_b.size() / 2 - 1;
   }
   HIPCHK(hipGetLastError());
   B.n = (int)n;

@@ -524,24 +524,73 @@ __host__ __device__ constexpr int waves_per_simd(size_t lds_bytes, int nw) {
   return w < 1 ? 1 : (w > 2 ? 2 : w);
 }
 
+// Bounds of one edge tile: receivers [r0, r1), edges [e0, e1).  The plan
+// stores (receiver, edge) pairs per tile boundary, so the four bounds are
+// two independent loads.
+struct EdgeTileBounds {
+  int r0, r1, e0, e1;
+  template <typename BV>
+  __device__ __forceinline__ void load(const BV& b, int t) {
+    const int2 lo = *(const int2*)(b.etiles + 2 * t);
+    const int2 hi = *(const int2*)(b.etiles + 2 * t + 2);
+    r0 = lo.x;
+    e0 = lo.y;
+    r1 = hi.x;
+    e1 = hi.y;
+  }
+};
+
 // Indices of one edge tile: its receiver range [r0, r1), its edge range
 // [e0, e0 + ne), and this thread's edge (receiver rv, sender cv; threads
-// below ne).  Loaded one tile ahead so that the chain of dependent index
-// loads overlaps the previous tile's work.
+// below ne).
 struct EdgeTileIdx {
   int r0, r1, e0, ne, rv, cv;
   template <typename BV>
-  __device__ __forceinline__ void load(const BV& b, int t) {
-    r0 = b.etiles[t];
-    r1 = b.etiles[t + 1];
-    e0 = b.row_ptr[r0];
-    ne = b.row_ptr[r1] - e0;
+  __device__ __forceinline__ void load(const BV& b, const EdgeTileBounds& bd) {
+    r0 = bd.r0;
+    r1 = bd.r1;
+    e0 = bd.e0;
+    ne = bd.e1 - bd.e0;
     rv = 0;
     cv = 0;
     if ((int)threadIdx.x < ne) {
       rv = b.recv[e0 + threadIdx.x];
       cv = b.col[e0 + threadIdx.x];
     }
+  }
+  // bounds and indices of tile t, one dependent step after the other
+  template <typename BV>
+  __device__ __forceinline__ void load(const BV& b, int t) {
+    EdgeTileBounds bd;
+    bd.load(b, t);
+    load(b, bd);
+  }
+};
+
+// Index pipeline of a persistent edge kernel: while a workgroup works on
+// tile t, the per-thread indices of its next tile and the bounds of the tile
+// after that are in flight, so neither link of the dependent chain
+// (bounds -> indices) waits on the critical path of a tile.
+struct EdgeTilePipe {
+  EdgeTileBounds nb;  // bounds of the tile after the next
+  EdgeTileIdx nx;     // indices of the next tile
+  template <typename BV, typename Sched>
+  __device__ __forceinline__ void start(const BV& b, const Sched& sch) {
+    nb = EdgeTileBounds{};
+    nx = EdgeTileIdx{};
+    if (sch.begin < sch.end) {
+      EdgeTileBounds b0;
+      b0.load(b, sch.begin);
+      nx.load(b, b0);
+    }
+    if (sch.begin + sch.step < sch.end) nb.load(b, sch.begin + sch.step);
+  }
+  // After the current tile t has taken nx: issue the next tile's indices and
+  // the bounds of the one after.
+  template <typename BV, typename Sched>
+  __device__ __forceinline__ void advance(const BV& b, const Sched& sch, int t) {
+    if (t + sch.step < sch.end) nx.load(b, nb);
+    if (t + 2 * sch.step < sch.end) nb.load(b, t + 2 * sch.step);
   }
 };
 

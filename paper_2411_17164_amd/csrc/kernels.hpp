@@ -20,7 +20,7 @@ struct BatchView {
   const int* recv;       // [E] receiver (batch index)
   const int* csc_ptr;    // [n+1] sender CSR
   const int* csc_edge;   // [E] CSR edge of each sender slot
-  const int* etiles;     // [n_etiles+1] receiver bounds of edge tiles
+  const int* etiles;     // [n_etiles+1][2] (receiver, edge) bounds of edge tiles
   int n_etiles;
   const int* inner;      // [n_inner] batch rows of inner nodes
   int n_inner;

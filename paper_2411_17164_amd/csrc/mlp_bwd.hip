@@ -212,7 +212,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
   }
 
   TileSched sch(b.n_etiles);
-  EdgeTileIdx nx{};
+  EdgeTileIdx nx{};  // a tile ahead; deeper prefetch costs this kernel registers it spills
   if (sch.begin < sch.end) nx.load(b, sch.begin);
   for (int t = sch.begin; t < sch.end; t += sch.step) {
     const EdgeTileIdx cur = nx;

@@ -59,10 +59,10 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
   const int n0 = wave_id() * D::CPW;
 
   TileSched sch(b.n_etiles);
-  EdgeTileIdx nx{};
-  if (sch.begin < sch.end) nx.load(b, sch.begin);
+  EdgeTilePipe ip;
+  ip.start(b, sch);
   for (int t = sch.begin; t < sch.end; t += sch.step) {
-    const EdgeTileIdx cur = nx;
+    const EdgeTileIdx cur = ip.nx;
     const int r0 = cur.r0, r1 = cur.r1, e0 = cur.e0, ne = cur.ne;
     if (threadIdx.x < MT) {
       rs[threadIdx.x] = cur.rv;
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
         xs, ne,
         [&](int p, int i) { return p == 0 ? h + (size_t)rs[i] * H : p == 1 ? h + (size_t)ss[i] * H : e + (size_t)(e0 + i) * H; },
         [](int, int, int, const uint4&) {});
-    if (t + sch.step < sch.end) nx.load(b, t + sch.step);  // next tile's indices, in flight from here
+    ip.advance(b, sch, t);  // next tile's indices and the bounds after, in flight from here
     lds_sync();
 
     f32x4 acc[MB][NB];
