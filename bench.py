@@ -14,7 +14,10 @@ Two tape policies are timed, for both precisions, each BF16 leg against the
 plain FP32 leg of the same policy: "keep" (the forward also stores every
 edge's hidden activation z, so the edge adjoint skips the first product;
 the headline) and "recompute" (per-layer checkpoints only, every edge MLP
-recomputed in the backward).
+recomputed in the backward).  A second form of the edge forward is timed
+beside them as a variant (keep policy): "split", the first layer
+re-associated over its input blocks with per-node projections of W1 (the
+headline is the gathered form, which applies the 3H x H layer per edge).
 
 edge-updates/s = E_useful * L / t_step.
 
@@ -56,7 +59,7 @@ def log(msg):
 
 
 def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: int = 0, de_in: float = 1.0,
-                 ztape: bool = False, atape: bool = False) -> float | None:
+                 ztape: bool = False, atape: bool = False, split: bool = False) -> float | None:
     """Algorithmic HBM bytes of one launch of a processor kernel: each input
     read once, each output written once (s = bytes per stored latent; FP32
     adjoints are 4 bytes).  `fused`: the edge adjoint accumulates dW2 (1), or
@@ -65,7 +68,15 @@ def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: int = 0, de_i
     `de_in`: fraction of launches that read an incoming edge adjoint de' (all
     but the last layer).  `atape`: the forward also writes the
     pre-activation a (SiLU), which the adjoint reads too.  `ztape`: the
-    forward writes z for the adjoint, which reads it instead of h_s and h_r."""
+    forward writes z for the adjoint, which reads it instead of h_s and h_r.
+    `split`: the edge forward's split form, which reads the FP32 node
+    projections of W1 instead of h."""
+    if name == "edge_fwd" and split:
+        # per edge: e read, e' (and z, a) written; per node: the projections
+        # W1_r h + b1 and W1_s h (FP32) read; per receiver: m (FP32) written
+        return E * (2 + (1 if ztape else 0) + (1 if atape else 0)) * H * s + n * (8 * H + 4 * H)
+    if name == "node_proj":
+        return n * (H * s + 8 * H)
     if name == "edge_fwd":
         # per edge: e and the gathered h_s read, e' (and z) written; per
         # receiver: h_r read, m (FP32) written
@@ -91,10 +102,13 @@ def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: int = 0, de_i
     return None
 
 
-def kernel_flops(name: str, n: int, E: int, H: int, fused: int = 0, ztape: bool = False) -> float | None:
+def kernel_flops(name: str, n: int, E: int, H: int, fused: int = 0, ztape: bool = False,
+                 split: bool = False) -> float | None:
     """Dense multiply-add flops of one launch (2 per MAC)."""
     if name == "edge_fwd":
-        return E * 8.0 * H * H
+        return E * (4.0 if split else 8.0) * H * H
+    if name == "node_proj":
+        return n * 4.0 * H * H
     if name == "edge_bwd":
         # recompute (3H x H unless z is on the tape, H x H), W2^T du, W1e^T da;
         # fused: du^T z (1), and da^T e (2)
@@ -303,6 +317,9 @@ def main():
     ap.add_argument("--tape", choices=["keep", "recompute", "both"], default="both",
                     help="tape policy: keep the edge MLPs' hidden activations, recompute them from the "
                          "per-layer checkpoints, or time both (the first listed is the headline)")
+    ap.add_argument("--edge-form", choices=["gather", "split", "both"], default="both",
+                    help="edge forward: the gathered 3H first layer (the headline), the split form with "
+                         "per-node projections of W1 (a variant, keep policy only), or both")
     ap.add_argument("--graph", action="store_true", help="replay each step from a captured HIP graph")
     ap.add_argument("--edge-rows", type=int, default=0)
     ap.add_argument("--node-rows", type=int, default=0)
@@ -370,13 +387,18 @@ def main():
         log("[bench] H = 512 runs in the BF16 form only: no FP32 leg")
     precs = ["bf16"] if args.no_fp32 or H == 512 else ["bf16", "fp32"]
     policies = {"keep": [True], "recompute": [False], "both": [True, False]}[args.tape]
-    # legs: (name, precision, keep_hidden); the first is the headline
-    legs = [(p + ("" if keep else "_recompute"), p, keep) for keep in policies for p in precs]
-    for leg, prec, keep in legs:
+    forms = {"gather": [False], "split": [True], "both": [False, True]}[args.edge_form]
+    # legs: (name, precision, keep_hidden, split form); the first is the headline
+    legs = [(p + ("_split" if split else "") + ("" if keep else "_recompute"), p, keep, split)
+            for split in forms for keep in policies if keep or not split for p in precs]
+    if not legs:
+        sys.exit("the split edge form runs with the keep tape policy only")
+    for leg, prec, keep, split in legs:
         ctx = api.Context(0)  # a context per leg, so that its workspace is the leg's own
         ctx.set_tiles(args.edge_rows, args.node_rows, args.grid, args.edge_waves)
         ctx.set_bwd_tiles(args.adjoint_edge_rows)
         ctx.set_tape(keep)
+        ctx.set_edge_split(split)
         model = api.Model(H, L, node_in=cfg.node_in, activation=cfg.activation, precision=prec)
         entries = [(kind, shape) for (_, _, _, kind, shape, _) in model.param_tensors()]
         params = to(init_params(entries, cfg.seed("weights")))
@@ -438,7 +460,7 @@ def main():
         torch.cuda.synchronize()
         tk = ctx.timings()
         ctx.set_timing(False)
-        results[leg] = dict(wall=wall, ev=ev, kernels=tk, mem=ctx.memory(), tiles=tuned, keep=keep)
+        results[leg] = dict(wall=wall, ev=ev, kernels=tk, mem=ctx.memory(), tiles=tuned, keep=keep, split=split)
         log(f"[bench] {leg} kernels: " + ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in
                                                      sorted(tk.items(), key=lambda kv: -kv[1][0])))
         del params, out, d_out, d_params, ctx
@@ -456,13 +478,14 @@ def main():
     fused = 0 if H != 128 else (1 if (ztape and adj_rows == 32) else 2)
     atape = ztape and cfg.activation != "relu"  # ... and, under SiLU, a
     de_in = (L - 1) / L
-    kb = lambda k, n_w, e_w: kernel_bytes(k, n_w, e_w, H, 2, fused, de_in, ztape, atape)  # noqa: E731
+    kb = lambda k, n_w, e_w: kernel_bytes(k, n_w, e_w, H, 2, fused, de_in, ztape, atape, bf["split"])  # noqa: E731
     dom = max((k for k in kern if kb(k, N, E) is not None), key=lambda k: kern[k][0])
     avg_ms = kern[dom][0] / kern[dom][1]
     # launches of a processor kernel per step: L per wave (edge/node kernels)
     per_step = kern[dom][1]
     tot_bytes = sum(kb(dom, n_w, e_w) for n_w, e_w in wave_sizes) * per_step / len(waves)
-    tot_flops = sum(kernel_flops(dom, n_w, e_w, H, fused, ztape) for n_w, e_w in wave_sizes) * per_step / len(waves)
+    tot_flops = sum(kernel_flops(dom, n_w, e_w, H, fused, ztape, bf["split"])
+                    for n_w, e_w in wave_sizes) * per_step / len(waves)
     by = tot_bytes / per_step
     fl = tot_flops / per_step
     achieved = by / (avg_ms * 1e-3) / 1e9
@@ -504,6 +527,7 @@ def main():
         "partition_plan_ms": round(t_part * 1e3, 2),
     }
     line["tape"] = "keep hidden activations" if bf["keep"] else "checkpoints only (recompute)"
+    line["edge_form"] = "split (per-node W1 projections)" if bf["split"] else "gathered 3H first layer"
     line["end_to_end_ms"] = round((t_knn + t_part) * 1e3 + bf["wall"] * 1e3, 3)
     for leg, r in results.items():
         if leg == head:
@@ -511,7 +535,7 @@ def main():
         line[f"{leg}_value"] = E * L / r["wall"]
         line[f"{leg}_ms_per_step"] = round(r["wall"] * 1e3, 3)
     # BF16 against plain FP32 under the same tape policy
-    for sfx in ("", "_recompute"):
+    for sfx in ("", "_recompute", "_split"):
         if "bf16" + sfx in results and "fp32" + sfx in results:
             line["bf16_over_fp32" + sfx] = round(results["fp32" + sfx]["wall"] / results["bf16" + sfx]["wall"], 3)
     line["tiles"] = {p: (dict(zip(["edge_rows", "node_rows", "grid", "edge_waves", "adjoint_edge_rows"],

@@ -377,6 +377,22 @@ xmgn_status xmgn_ctx_set_offload(xmgn_ctx* ctx, int32_t enable);
  */
 xmgn_status xmgn_ctx_set_tape(xmgn_ctx* ctx, int32_t keep_hidden);
 xmgn_status xmgn_ctx_get_tape(const xmgn_ctx* ctx, int32_t* keep_hidden);
+/*
+ * Form of the edge forward (Eq. 1).  split = 0 (the default): every edge
+ * gathers [h_r ; h_s ; e] into LDS and applies the 3H -> H first layer.
+ * split = 1: the first layer is re-associated over its input blocks,
+ * W1 x + b1 = W1_e e + (W1_r h_r + b1) + W1_s h_s; a per-node kernel first
+ * computes W1_r h + b1 and W1_s h for every node of the batch (FP32,
+ * 8 n H bytes of context memory), and each edge then adds the rows of its
+ * receiver and sender to W1_e e.  The value is the same up to the rounding
+ * order of the sum; the product's flops per edge fall from 6 H^2 to 2 H^2.
+ * The split form runs in forwards without a tape and in forwards whose tape
+ * keeps z (keep_hidden = 1, resident); elsewhere the gathered form runs, so
+ * that an adjoint that recomputes the first product sees the forward's own
+ * rounding.  Invalidates the last forward.
+ */
+xmgn_status xmgn_ctx_set_edge_split(xmgn_ctx* ctx, int32_t split);
+xmgn_status xmgn_ctx_get_edge_split(const xmgn_ctx* ctx, int32_t* split);
 /* Page-locked host bytes currently held by the context (the offloaded tape). */
 xmgn_status xmgn_ctx_host_memory(const xmgn_ctx* ctx, int64_t* bytes);
 

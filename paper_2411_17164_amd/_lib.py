@@ -52,6 +52,8 @@ _SIGS = {
     "xmgn_ctx_tape_serial": (_i32, [_p, _pi64]),
     "xmgn_ctx_set_tape": (_i32, [_p, _i32]),
     "xmgn_ctx_get_tape": (_i32, [_p, _pi32]),
+    "xmgn_ctx_set_edge_split": (_i32, [_p, _i32]),
+    "xmgn_ctx_get_edge_split": (_i32, [_p, _pi32]),
     "xmgn_ctx_host_memory": (_i32, [_p, _pi64]),
     "xmgn_ctx_set_offload": (_i32, [_p, _i32]),
     "xmgn_ctx_set_timing": (_i32, [_p, _i32]),

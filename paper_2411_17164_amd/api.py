@@ -231,6 +231,17 @@ class Context:
         check(lib.xmgn_ctx_get_tape(self._h, C.byref(v)))
         return bool(v.value)
 
+    def set_edge_split(self, split: bool):
+        """Edge forward form: the first layer re-associated over its input
+        blocks (node projections of W1, Eq. 1) instead of the gathered 3H
+        product; used where no adjoint recomputes that product."""
+        check(lib.xmgn_ctx_set_edge_split(self._h, 1 if split else 0))
+
+    def get_edge_split(self) -> bool:
+        v = C.c_int32()
+        check(lib.xmgn_ctx_get_edge_split(self._h, C.byref(v)))
+        return bool(v.value)
+
     def set_offload(self, enable: bool):
         """Keep the training tape's checkpoints in host memory (synchronises the device)."""
         check(lib.xmgn_ctx_set_offload(self._h, 1 if enable else 0))

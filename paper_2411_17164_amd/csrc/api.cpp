@@ -553,6 +553,8 @@ struct xmgn_ctx {
   DBuf at;  // their pre-activations [L][E][H] (BF16 SiLU forms, device-resident tape)
   bool tape_z = false, tape_a = false;
   bool tape_hidden = true;  // tape policy: BF16 forms keep z (and a) of every edge
+  bool edge_split = false;  // edge forward form: node projections of W1 (see xmgn_ctx_set_edge_split)
+  DBuf proj;                // [2][n][H] FP32 node projections of the current layer
   // per-kernel timing
   bool timing = false;
   std::vector<std::string> tnames;
@@ -794,6 +796,20 @@ extern "C" xmgn_status xmgn_ctx_set_tape(xmgn_ctx* c, int32_t keep_hidden) {
 extern "C" xmgn_status xmgn_ctx_get_tape(const xmgn_ctx* c, int32_t* keep_hidden) {
   if (!c || !keep_hidden) return fail(XMGN_ERR_INVALID, "NULL argument");
   *keep_hidden = c->tape_hidden ? 1 : 0;
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_ctx_set_edge_split(xmgn_ctx* c, int32_t split) {
+  if (!c) return fail(XMGN_ERR_INVALID, "ctx is NULL");
+  if (split != 0 && split != 1) return fail(XMGN_ERR_INVALID, "split must be 0 or 1");
+  c->edge_split = split != 0;
+  c->fwd_valid = false;
+  return XMGN_OK;
+}
+
+extern "C" xmgn_status xmgn_ctx_get_edge_split(const xmgn_ctx* c, int32_t* split) {
+  if (!c || !split) return fail(XMGN_ERR_INVALID, "NULL argument");
+  *split = c->edge_split ? 1 : 0;
   return XMGN_OK;
 }
 
@@ -1186,10 +1202,24 @@ extern "C" xmgn_status xmgn_forward(xmgn_ctx* c, const xmgn_model_desc* d, const
     if (xmgn_status r = tape_out(c, d, st, tape_h_offloaded(0, L) ? 0 : -1, tape_em_offloaded(0, L) ? 0 : -1, -1,
                                  &copies[0]))
       return r;
+  // the split form (node projections of W1) runs where no adjoint will
+  // recompute the first product in the gathered order: forwards without a
+  // tape, and forwards whose tape keeps z (and a)
+  const bool split = c->edge_split && (keep_tape == 0 || c->tape_z);
+  float* pr = nullptr;
+  float* pq = nullptr;
+  if (split) {
+    if (xmgn_status r = c->proj.ensure((size_t)2 * b.n * d->hidden * 4, st)) return r;
+    pr = c->proj.as<float>();
+    pq = pr + (size_t)b.n * d->hidden;
+  }
   for (int l = 0; l < L; ++l) {
     if (off && l >= 1) HIPCHK(hipStreamWaitEvent(st, copies[l - 1], 0));
-    { KT("edge_fwd"); launch_edge_fwd(s, b, weights(c, d, params, 2 + 2 * l, 2, l), hslot(c, d, l), eslot(c, d, l),
-                    l + 1 < L ? eslot(c, d, l + 1) : nullptr, mslot(c, d, l), zslot(c, d, l), aslot(c, d, l), st); }
+    const MlpW we = weights(c, d, params, 2 + 2 * l, 2, l);
+    if (split) { KT("node_proj"); launch_node_proj(s, b, we, hslot(c, d, l), pr, pq, st); }
+    { KT("edge_fwd"); launch_edge_fwd(s, b, we, hslot(c, d, l), eslot(c, d, l),
+                    l + 1 < L ? eslot(c, d, l + 1) : nullptr, mslot(c, d, l), zslot(c, d, l), aslot(c, d, l),
+                    pr, pq, st); }
     { KT("node_fwd"); launch_node_fwd(s, b, weights(c, d, params, 3 + 2 * l, 3, l), hslot(c, d, l), mslot(c, d, l), hslot(c, d, l + 1),
                     st); }
     if (off)
@@ -1565,7 +1595,8 @@ static std::string tune_key(const xmgn_ctx* c, const xmgn_model_desc* d) {
   if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
   std::ostringstream k;
   k << arch.substr(0, arch.find(':')) << ":H" << d->hidden << ":L" << d->n_layers << ":p" << d->precision << ":a"
-    << d->activation << ":g" << d->aggregate << ":t" << (c->tape_hidden ? 1 : 0) << ":n" << c->cur->n << ":E"
+    << d->activation << ":g" << d->aggregate << ":t" << (c->tape_hidden ? 1 : 0) << ":s" << (c->edge_split ? 1 : 0)
+    << ":n" << c->cur->n << ":E"
     << c->cur->E;
   return k.str();
 }

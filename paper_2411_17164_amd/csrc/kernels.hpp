@@ -72,8 +72,14 @@ void launch_enc_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, cons
                          hipStream_t st);
 // z_out (or NULL): the hidden activation of every edge, for edge_z_tape forms;
 // a_out (or NULL): its pre-activation, for edge_a_tape forms.
+// pr, ps (or NULL for the gathered form): the node projections of
+// launch_node_proj for this layer's edge MLP.
 void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h,
-                     const void* e, void* e_out, float* m, void* z_out, void* a_out, hipStream_t st);
+                     const void* e, void* e_out, float* m, void* z_out, void* a_out, const float* pr,
+                     const float* ps, hipStream_t st);
+// pr = W1_r h + b1, ps = W1_s h for every node (FP32 [n][H] each).
+void launch_node_proj(const Shape& s, const BatchView& b, const MlpW& w, const void* h, float* pr, float* ps,
+                      hipStream_t st);
 void launch_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h,
                      const float* m, void* h_out, hipStream_t st);
 void launch_dec_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, float* out,

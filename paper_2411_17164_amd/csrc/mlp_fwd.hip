@@ -3,6 +3,8 @@
 // (see TileSched); each tile is staged in LDS, multiplied on MFMA with FP32
 // accumulation, and post-processed (bias, activation, LayerNorm, residual)
 // in registers before a coalesced write.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -27,10 +29,15 @@ struct Dims {
 // ascending sender order (the CSR order) -- deterministic, no atomics.
 // ---------------------------------------------------------------------------
 // NW waves per workgroup; each wave owns H / NW output columns of every GEMM.
-template <typename T, int H, int MT, int NW>
+// SPLIT: the first layer's node blocks come precomputed per node (see
+// k_node_proj), so only the e rows are gathered; the staging tile must still
+// hold the FP32 tile of the segment sums.
+template <typename T, int H, int MT, int NW, int SPLIT = 0>
 struct EdgeFwdLds {
   using D = Dims<T, H, NW>;
-  static constexpr size_t XS = (size_t)MT * D::LD3 * sizeof(T);
+  static constexpr size_t GS = (size_t)MT * (SPLIT ? D::LDH : D::LD3) * sizeof(T);
+  static constexpr size_t FS = (size_t)MT * D::LDF * 4;
+  static constexpr size_t XS = SPLIT && FS > GS ? FS : GS;
   static constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
   static constexpr size_t bytes = XS + ZS + 2 * NW * MT * 4 + 2 * MT * 4;
 };
@@ -38,12 +45,18 @@ struct EdgeFwdLds {
 // z_out (or NULL): the hidden activation z = act(W1 x + b1) of every edge,
 // kept for the adjoint; a_out (or NULL): its pre-activation a = W1 x + b1
 // (SiLU's derivative needs a).
-template <typename T, int H, int MT, int ACT, int AGG, int NW>
-__global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::bytes, NW)) void k_edge_fwd(
+// SPLIT = 1: W1 x + b1 = W1_e e + (W1_r h_r + b1) + W1_s h_s, the last two
+// read per edge from the FP32 node projections pr and ps (same value as the
+// gathered form up to the rounding order of the sum).
+template <typename T, int H, int MT, int ACT, int AGG, int NW, int SPLIT>
+__global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW, SPLIT>::bytes, NW)) void k_edge_fwd(
     BatchView b, MlpW w, const T* __restrict__ h, const T* __restrict__ e, T* __restrict__ e_out,
-    float* __restrict__ m, T* __restrict__ z_out, T* __restrict__ a_out, float eps) {
+    float* __restrict__ m, T* __restrict__ z_out, T* __restrict__ a_out, const float* __restrict__ pr,
+    const float* __restrict__ ps, float eps) {
   using D = Dims<T, H, NW>;
-  using L = EdgeFwdLds<T, H, MT, NW>;
+  using L = EdgeFwdLds<T, H, MT, NW, SPLIT>;
+  constexpr int LDX = SPLIT ? D::LDH : D::LD3;  // staging row stride
+  constexpr int EC = SPLIT ? 0 : 2 * H;          // column of e in a staged row
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t XS = L::XS, ZS = L::ZS;
   static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
@@ -69,27 +82,56 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
       ss[threadIdx.x] = cur.cv;
     }
     lds_sync();
-    gather_tile<T, D::LD3, MT, 3, H, 64 * NW>(
-        xs, ne,
-        [&](int p, int i) { return p == 0 ? h + (size_t)rs[i] * H : p == 1 ? h + (size_t)ss[i] * H : e + (size_t)(e0 + i) * H; },
-        [](int, int, int, const uint4&) {});
-    ip.advance(b, sch, t);  // next tile's indices and the bounds after, in flight from here
-    lds_sync();
-
     f32x4 acc[MB][NB];
-    zero_acc(acc);
-    wave_gemm<T, MB, NB, 3 * H, D::LD3>(acc, xs, W1, 3 * H, n0);
+    if constexpr (SPLIT) {
+      gather_tile<T, D::LDH, MT, 1, H, 64 * NW>(
+          xs, ne, [&](int, int i) { return e + (size_t)(e0 + i) * H; }, [](int, int, int, const uint4&) {});
+      // the node blocks of the first product, in the accumulator layout:
+      // acc = P_r[receiver] + P_s[sender], in flight during the barrier
+      f32x4 sv[MB][NB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = acc_row(mb, r);
+          const float* prow = pr + (size_t)rs[row] * H + n0 + (lane_id() & 15);
+          const float* srow = ps + (size_t)ss[row] * H + n0 + (lane_id() & 15);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            acc[mb][nb][r] = prow[16 * nb];
+            sv[mb][nb][r] = srow[16 * nb];
+          }
+        }
+      ip.advance(b, sch, t);  // next tile's indices and the bounds after, in flight from here
+      lds_sync();
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[mb][nb][r] += sv[mb][nb][r];
+      wave_gemm<T, MB, NB, H, D::LDH>(acc, xs, W1 + 2 * H, 3 * H, n0);  // + W1_e e
+    } else {
+      gather_tile<T, D::LD3, MT, 3, H, 64 * NW>(
+          xs, ne,
+          [&](int p, int i) { return p == 0 ? h + (size_t)rs[i] * H : p == 1 ? h + (size_t)ss[i] * H : e + (size_t)(e0 + i) * H; },
+          [](int, int, int, const uint4&) {});
+      ip.advance(b, sch, t);  // next tile's indices and the bounds after, in flight from here
+      lds_sync();
+      zero_acc(acc);
+      wave_gemm<T, MB, NB, 3 * H, D::LD3>(acc, xs, W1, 3 * H, n0);
+    }
     f32x4 ev[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const int c = acc_col(n0, nb);
-        const float bb = w.b1[c];
+        const float bb = SPLIT ? 0.f : w.b1[c];  // SPLIT: b1 is in P_r
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           acc[mb][nb][r] += bb;
-          ev[mb][nb][r] = to_f(xs[acc_row(mb, r) * D::LD3 + 2 * H + c]);
+          ev[mb][nb][r] = to_f(xs[acc_row(mb, r) * LDX + EC + c]);
         }
       }
     if (a_out) {  // uniform: the pre-activation goes out through zs first
@@ -154,6 +196,55 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW>::b
     }
     if (e_out) lds_rows_to_global<T, D::LDH>(zs, ne, H, e_out + (size_t)e0 * H, H, [](int i) { return i; });
     lds_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Node projections of the edge MLP's first layer (Eq. 1 re-associated): the
+// blocks of W1 that act on the receiver's and the sender's latent give
+//   pr = W1_r h + b1,  ps = W1_s h   (FP32, [n][H] each)
+// once per node instead of once per edge; the edge forward's split form
+// then needs only W1_e e per edge.
+// ---------------------------------------------------------------------------
+template <typename T, int H, int MT>
+__global__ __launch_bounds__(NTHR, 2) void k_node_proj(int n, MlpW w, const T* __restrict__ h, float* __restrict__ pr,
+                                                      float* __restrict__ ps) {
+  using D = Dims<T, H>;
+  constexpr int MB = MT / 16, NB = D::NB;
+  constexpr size_t XS = (size_t)MT * D::LDH * sizeof(T);
+  __shared__ __align__(16) unsigned char smem[XS + (size_t)MT * D::LDF * 4];
+  T* xs = (T*)smem;
+  float* ft = (float*)(smem + XS);
+  const T* W1 = (const T*)w.W1;
+  const int n0 = wave_id() * D::CPW;
+  const int n_tiles = (n + MT - 1) / MT;
+  TileSched sch(n_tiles);
+  for (int t = sch.begin; t < sch.end; t += sch.step) {
+    const int row0 = t * MT, nr = min(MT, n - row0);
+    global_rows_to_lds<T, D::LDH, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
+    lds_sync();
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      f32x4 acc[MB][NB];
+      zero_acc(acc);
+      wave_gemm<T, MB, NB, H, D::LDH>(acc, xs, W1 + blk * H, 3 * H, n0);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int c = acc_col(n0, nb);
+          const float bb = blk == 0 ? w.b1[c] : 0.f;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) ft[acc_row(mb, r) * D::LDF + c] = acc[mb][nb][r] + bb;
+        }
+      lds_sync();
+      float* dst = blk == 0 ? pr : ps;
+      for (int c = threadIdx.x; c < nr * (H / 4); c += NTHR) {
+        const int i = c / (H / 4), q = c - i * (H / 4);
+        *(float4*)(dst + (size_t)(row0 + i) * H + 4 * q) = *(const float4*)(ft + i * D::LDF + 4 * q);
+      }
+      lds_sync();
+    }
   }
 }
 
@@ -503,15 +594,20 @@ constexpr bool edge_fits() {
 
 template <int NW>
 static void edge_fwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e, void* e_out,
-                        float* m, void* z_out, void* a_out, hipStream_t st) {
+                        float* m, void* z_out, void* a_out, const float* pr, const float* ps, hipStream_t st) {
   XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, XMGN_DISPATCH_ACT(s.act, XMGN_DISPATCH_MT_EDGE(s.mt_edge, {
     if constexpr (edge_fits<T, H, MT>()) {
-      if (s.agg)
-        k_edge_fwd<T, H, MT, ACT, 1, NW><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m,
-                                                                     (T*)z_out, (T*)a_out, s.eps);
-      else
-        k_edge_fwd<T, H, MT, ACT, 0, NW><<<s.grid, 64 * NW, 0, st>>>(b, w, (const T*)h, (const T*)e, (T*)e_out, m,
-                                                                     (T*)z_out, (T*)a_out, s.eps);
+      auto go = [&](auto agg, auto split) {
+        k_edge_fwd<T, H, MT, ACT, decltype(agg)::value, NW, decltype(split)::value><<<s.grid, 64 * NW, 0, st>>>(
+            b, w, (const T*)h, (const T*)e, (T*)e_out, m, (T*)z_out, (T*)a_out, pr, ps, s.eps);
+      };
+      using I0 = std::integral_constant<int, 0>;
+      using I1 = std::integral_constant<int, 1>;
+      if (pr) {
+        if (s.agg) go(I1{}, I1{}); else go(I0{}, I1{});
+      } else {
+        if (s.agg) go(I1{}, I0{}); else go(I0{}, I0{});
+      }
     } else {
       g_config_error = 1;
     }
@@ -519,12 +615,22 @@ static void edge_fwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const
 }
 
 void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
-                     void* e_out, float* m, void* z_out, void* a_out, hipStream_t st) {
+                     void* e_out, float* m, void* z_out, void* a_out, const float* pr, const float* ps,
+                     hipStream_t st) {
   if (b.n_etiles == 0) return;
   if (s.nw_edge == 8)
-    edge_fwd_nw<8>(s, b, w, h, e, e_out, m, z_out, a_out, st);
+    edge_fwd_nw<8>(s, b, w, h, e, e_out, m, z_out, a_out, pr, ps, st);
   else
-    edge_fwd_nw<4>(s, b, w, h, e, e_out, m, z_out, a_out, st);
+    edge_fwd_nw<4>(s, b, w, h, e, e_out, m, z_out, a_out, pr, ps, st);
+}
+
+void launch_node_proj(const Shape& s, const BatchView& b, const MlpW& w, const void* h, float* pr, float* ps,
+                      hipStream_t st) {
+  if (b.n == 0) return;
+  XMGN_DISPATCH_T(s.prec, XMGN_DISPATCH_H(s.H, {
+    constexpr int MT = H == 512 ? 16 : 32;
+    k_node_proj<T, H, MT><<<s.grid, NTHR, 0, st>>>(b.n, w, (const T*)h, pr, ps);
+  }));
 }
 
 void launch_node_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const float* m,

@@ -398,3 +398,69 @@ def test_wide_node_input(api, ctx, precision):
     torch.cuda.synchronize()
     errs = per_tensor_errors(case, acc.cpu().numpy(), grad)
     assert max(errs.values()) <= (1e-5 if precision == "fp32" else 5e-3), sorted(errs.items(), key=lambda kv: -kv[1])[:3]
+
+
+# --------------------------------------------------------------------------
+# split form of the edge forward (first layer re-associated over its blocks)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("act", ["relu", "silu"])
+@pytest.mark.parametrize("cfg,levels,layers", [(3, (500, 2000, 6000), 4), (5, (400, 1600, 5000), 3)])
+def test_edge_split_form(api, precision, act, cfg, levels, layers):
+    """W1 x + b1 = W1_e e + (W1_r h_r + b1) + W1_s h_s (Eq. 1, re-associated)
+    with per-node projections, at H = 128 and 256, against the FP64 oracle;
+    the adjoint reads z (and a) from the tape the split forward wrote."""
+    c = api.Context(0)
+    c.set_edge_split(True)
+    assert c.get_edge_split() and c.get_tape()
+    case = Case(cfg, levels=levels, layers=layers, precision=precision, activation=act)
+    g = gpu_graph(api, c, case)
+    ps = api.Partset.halo(g, case.inp.pos, None, case.L)
+    out, loss, grad = gpu_step(api, c, case, ps, [0])
+    log(f"  split form H={case.H} {precision} {act}: " + check_step(case, out, loss, grad, oracle_refs(case)))
+
+
+@pytest.mark.parametrize("act", ["silu", "relu"])
+def test_edge_split_form_h512(api, act):
+    """The split form at the production width (H = 512, 24 inputs, BF16)."""
+    c = api.Context(0)
+    c.set_edge_split(True)
+    case = Case(6, levels=(200, 800, 2500), layers=3, precision="bf16", activation=act)
+    g = gpu_graph(api, c, case)
+    ps = api.Partset.halo(g, case.inp.pos, None, case.L)
+    out, loss, grad = gpu_step(api, c, case, ps, [0])
+    log(f"  split form H=512 {act}: " + check_step(case, out, loss, grad, oracle_refs(case)))
+
+
+def test_edge_split_partitions_and_fallback(api):
+    """Split form: partitioned outputs equal the full graph's bitwise (the
+    projections are per node, independent of the batch); a training forward
+    under the recompute policy runs the gathered form instead (bitwise equal
+    to a context without the split); an inference forward keeps the split."""
+    case = Case(4, levels=(500, 2000, 8000), layers=3, precision="bf16")
+    c = api.Context(0)
+    c.set_edge_split(True)
+    g = gpu_graph(api, c, case)
+    full = api.Partset.halo(g, case.inp.pos, None, case.L)
+    y_full, _, _ = gpu_step(api, c, case, full, [0])
+    sizes = np.array([1500, 2500, 1000, 3000])
+    ps = api.Partset.halo(g, case.inp.pos, sizes, case.L)
+    y_b, _, _ = gpu_step(api, c, case, ps, list(range(len(sizes))))
+    assert (y_b == y_full).all()
+    # recompute policy: the gathered form runs
+    c.set_tape(False)
+    y_rc, _, g_rc = gpu_step(api, c, case, full, [0])
+    ref = api.Context(0)
+    ref.set_tape(False)
+    y_ref, _, g_ref = gpu_step(api, ref, case, api.Partset.halo(gpu_graph(api, ref, case), case.inp.pos, None, case.L), [0])
+    assert (y_rc == y_ref).all() and (g_rc == g_ref).all()
+    # inference (no tape): the split form, equal to the split training forward
+    c.set_tape(True)
+    model = case.model(api)
+    p = dev(case.params)
+    out = torch.zeros(case.N, 4, device="cuda")
+    c.forward(model, p, full, [0], dev(case.inp.node_in), dev(case.inp.pos), case.inp.edge_norm, out, keep_tape=False)
+    torch.cuda.synchronize()
+    assert (out.cpu().numpy() == y_full).all()
+    assert not (y_full == y_ref).all()  # the split form did run: another rounding order
