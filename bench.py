@@ -326,6 +326,7 @@ def main():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--edge-waves", type=int, default=0)
     ap.add_argument("--adjoint-edge-rows", type=int, default=0, help="edge tile rows of the edge adjoint")
+    ap.add_argument("--adjoint-edge-waves", type=int, default=0, help="waves per workgroup of the edge adjoint")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tiles")
     ap.add_argument("--wave-parts", type=int, default=0,
                     help="partitions per batch (wave) for partitioned workloads (0 = the workload's default: "
@@ -396,7 +397,7 @@ def main():
     for leg, prec, keep, split in legs:
         ctx = api.Context(0)  # a context per leg, so that its workspace is the leg's own
         ctx.set_tiles(args.edge_rows, args.node_rows, args.grid, args.edge_waves)
-        ctx.set_bwd_tiles(args.adjoint_edge_rows)
+        ctx.set_bwd_tiles(args.adjoint_edge_rows, args.adjoint_edge_waves)
         ctx.set_tape(keep)
         ctx.set_edge_split(split)
         model = api.Model(H, L, node_in=cfg.node_in, activation=cfg.activation, precision=prec)
@@ -425,12 +426,13 @@ def main():
         if H == 512 and not args.no_autotune:
             log("[bench] H = 512: fixed tiles (32-row edge, 16-row node), no autotuning")
         elif not args.no_autotune and not (args.edge_rows or args.node_rows or args.grid or args.edge_waves
-                                           or args.adjoint_edge_rows):
+                                           or args.adjoint_edge_rows or args.adjoint_edge_waves):
             ctx.set_tiles(0, 0, 0, 0)
             tuned = ctx.autotune(model, params, ps, waves[0], node_in, pos, inp.edge_norm, out, d_out, d_params)
-            tuned = tuned[:4] + (ctx.get_bwd_tiles(),) + tuned[4:]
+            tuned = tuned[:4] + ctx.get_bwd_tiles() + tuned[4:]
             log(f"[bench] {leg}: autotuned edge_rows={tuned[0]} node_rows={tuned[1]} grid={tuned[2]} "
-                f"edge_waves={tuned[3]} adjoint_edge_rows={tuned[4]} ({tuned[5]:.2f} ms)")
+                f"edge_waves={tuned[3]} adjoint_edge_rows={tuned[4]} adjoint_edge_waves={tuned[5]} "
+                f"({tuned[6]:.2f} ms)")
         log(f"[bench] {leg}: warmup {args.warmup}")
         for _ in range(max(1, args.warmup)):
             step()
@@ -538,8 +540,8 @@ def main():
     for sfx in ("", "_recompute", "_split"):
         if "bf16" + sfx in results and "fp32" + sfx in results:
             line["bf16_over_fp32" + sfx] = round(results["fp32" + sfx]["wall"] / results["bf16" + sfx]["wall"], 3)
-    line["tiles"] = {p: (dict(zip(["edge_rows", "node_rows", "grid", "edge_waves", "adjoint_edge_rows"],
-                                  r["tiles"][:5]))
+    line["tiles"] = {p: (dict(zip(["edge_rows", "node_rows", "grid", "edge_waves", "adjoint_edge_rows",
+                                   "adjoint_edge_waves"], r["tiles"][:6]))
                          if r["tiles"] else None) for p, r in results.items()}
     line["kernels_ms"] = {p: {k: round(v[0], 3) for k, v in r["kernels"].items()} for p, r in results.items()}
     line["device_workspace_gb"] = {p: round(r["mem"] / 1e9, 2) for p, r in results.items()}

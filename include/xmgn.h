@@ -114,14 +114,15 @@ void xmgn_ctx_destroy(xmgn_ctx* ctx);
 xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int32_t node_rows,
                                int32_t grid, int32_t edge_waves);
 
-/* Rows per edge tile of the edge adjoint, which tiles the same edges on its
- * own (whole receiver segments per tile): 32 or 64 in the BF16 form at
+/* Tiles of the edge adjoint, which tiles the same edges on its own (whole
+ * receiver segments per tile).  edge_rows: 32 or 64 in the BF16 form at
  * H = 128 and 256 (at H = 128, 32-row tiles with the z tape run a variant
  * that keeps half the weight-gradient accumulators and two workgroups per
- * compute unit), else the forward's; 0 = the forward's.  Invalidates the
- * last forward. */
-xmgn_status xmgn_ctx_set_bwd_tiles(xmgn_ctx* ctx, int32_t edge_rows);
-xmgn_status xmgn_ctx_get_bwd_tiles(const xmgn_ctx* ctx, int32_t* edge_rows);
+ * compute unit), else the forward's; 0 = the forward's.  edge_waves: 4 or 8
+ * waves per workgroup, any form; 0 = the forward's.  Invalidates the last
+ * forward. */
+xmgn_status xmgn_ctx_set_bwd_tiles(xmgn_ctx* ctx, int32_t edge_rows, int32_t edge_waves);
+xmgn_status xmgn_ctx_get_bwd_tiles(const xmgn_ctx* ctx, int32_t* edge_rows, int32_t* edge_waves);
 
 /*
  * 1. Multi-scale kNN graph (Sec. III.B, III.C).
@@ -242,15 +243,16 @@ xmgn_status xmgn_backward(xmgn_ctx* ctx, const xmgn_model_desc* desc, const floa
  * candidate configurations -- edge-tile rows {32, 64} x edge waves {4, 8} x
  * persistent grid {4, 8} workgroups per compute unit, then node-tile rows
  * {32, 64} for the best of those (64-row edge tiles at H = 128 and, BF16,
- * H = 256; 64-row node tiles at H = 128), then (BF16, H = 128 and 256) each
- * edge-tile height of the forward paired with the other height for the edge
- * adjoint -- and keeps the fastest in ctx (as xmgn_ctx_set_tiles and
- * xmgn_ctx_set_bwd_tiles would).
+ * H = 256; 64-row node tiles at H = 128), then the edge adjoint's own
+ * waves {4, 8} and (BF16, H = 128 and 256) its own tile rows {32, 64}
+ * against each edge-tile height and wave count of the forward -- and keeps
+ * the fastest in ctx (as xmgn_ctx_set_tiles and xmgn_ctx_set_bwd_tiles
+ * would).
  * Arguments as for xmgn_forward / xmgn_backward; out and d_params are
  * overwritten, d_out is only read.  cache_path (host string or NULL): a text
  * file of configuration lines; a hit skips the timing,
  * a miss appends a line ("key edge_rows node_rows grid edge_waves
- * adjoint_edge_rows ms").  The key holds the device name, the model
+ * adjoint_edge_rows adjoint_edge_waves ms").  The key holds the device name, the model
  * description, the tape policy and the batch's node and edge counts.  The chosen
  * configuration and its step time are returned (any output pointer may be
  * NULL).  Synchronises the stream.

@@ -46,8 +46,8 @@ _SIGS = {
     "xmgn_ctx_create": (_i32, [_i32, C.POINTER(_p)]),
     "xmgn_ctx_destroy": (None, [_p]),
     "xmgn_ctx_set_tiles": (_i32, [_p, _i32, _i32, _i32, _i32]),
-    "xmgn_ctx_set_bwd_tiles": (_i32, [_p, _i32]),
-    "xmgn_ctx_get_bwd_tiles": (_i32, [_p, _pi32]),
+    "xmgn_ctx_set_bwd_tiles": (_i32, [_p, _i32, _i32]),
+    "xmgn_ctx_get_bwd_tiles": (_i32, [_p, _pi32, _pi32]),
     "xmgn_ctx_memory": (_i32, [_p, _pi64]),
     "xmgn_ctx_tape_serial": (_i32, [_p, _pi64]),
     "xmgn_ctx_set_tape": (_i32, [_p, _i32]),

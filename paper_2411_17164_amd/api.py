@@ -179,14 +179,16 @@ class Context:
     def set_tiles(self, edge_rows: int = 0, node_rows: int = 0, grid: int = 0, edge_waves: int = 0):
         check(lib.xmgn_ctx_set_tiles(self._h, edge_rows, node_rows, grid, edge_waves))
 
-    def set_bwd_tiles(self, edge_rows: int = 0):
-        """Rows per edge tile of the edge adjoint (0 = the forward's)."""
-        check(lib.xmgn_ctx_set_bwd_tiles(self._h, edge_rows))
+    def set_bwd_tiles(self, edge_rows: int = 0, edge_waves: int = 0):
+        """Rows per edge tile and waves per workgroup of the edge adjoint
+        (0 = the forward's)."""
+        check(lib.xmgn_ctx_set_bwd_tiles(self._h, edge_rows, edge_waves))
 
-    def get_bwd_tiles(self) -> int:
-        v = C.c_int32()
-        check(lib.xmgn_ctx_get_bwd_tiles(self._h, C.byref(v)))
-        return v.value
+    def get_bwd_tiles(self) -> tuple[int, int]:
+        """(edge rows, edge waves) of the edge adjoint; 0 = the forward's."""
+        r, w = C.c_int32(), C.c_int32()
+        check(lib.xmgn_ctx_get_bwd_tiles(self._h, C.byref(r), C.byref(w)))
+        return r.value, w.value
 
     def set_timing(self, enable: bool):
         check(lib.xmgn_ctx_set_timing(self._h, 1 if enable else 0))

@@ -520,6 +520,7 @@ struct xmgn_ctx {
   int device = 0;
   int mt_edge = 0, mt_node = 0, grid = 0, nw_edge = 0;  // 0 = default
   int mt_edge_bwd = 0;                                  // 0 = the forward's edge tile
+  int nw_edge_bwd = 0;                                  // 0 = the forward's waves per edge workgroup
   // Batch plans, one per (partition set, part list, edge-tile rows), kept
   // while the context lives (at most kMaxPlans, least recently used evicted),
   // so a step over several batches (waves of partitions) builds each plan
@@ -637,6 +638,7 @@ static Shape make_shape(const xmgn_ctx* c, const xmgn_model_desc* d) {
                       : me;
   s.grid = c->grid > 0 ? c->grid : 1024;
   s.nw_edge = c->nw_edge > 0 ? c->nw_edge : d->hidden == 512 ? 8 : 4;  // H = 512: fewer spills at 8 waves
+  s.nw_edge_bwd = c->nw_edge_bwd > 0 ? c->nw_edge_bwd : s.nw_edge;
   return s;
 }
 
@@ -721,17 +723,20 @@ extern "C" xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int3
   return XMGN_OK;
 }
 
-extern "C" xmgn_status xmgn_ctx_set_bwd_tiles(xmgn_ctx* ctx, int32_t edge_rows) {
+extern "C" xmgn_status xmgn_ctx_set_bwd_tiles(xmgn_ctx* ctx, int32_t edge_rows, int32_t edge_waves) {
   if (!ctx) return fail(XMGN_ERR_INVALID, "ctx is NULL");
   if (edge_rows != 0 && edge_rows != 32 && edge_rows != 64) return fail(XMGN_ERR_INVALID, "edge_rows must be 0, 32 or 64");
+  if (edge_waves != 0 && edge_waves != 4 && edge_waves != 8) return fail(XMGN_ERR_INVALID, "edge_waves must be 0, 4 or 8");
   ctx->mt_edge_bwd = edge_rows;
+  ctx->nw_edge_bwd = edge_waves;
   ctx->fwd_valid = false;
   return XMGN_OK;
 }
 
-extern "C" xmgn_status xmgn_ctx_get_bwd_tiles(const xmgn_ctx* ctx, int32_t* edge_rows) {
-  if (!ctx || !edge_rows) return fail(XMGN_ERR_INVALID, "NULL argument");
+extern "C" xmgn_status xmgn_ctx_get_bwd_tiles(const xmgn_ctx* ctx, int32_t* edge_rows, int32_t* edge_waves) {
+  if (!ctx || !edge_rows || !edge_waves) return fail(XMGN_ERR_INVALID, "NULL argument");
   *edge_rows = ctx->mt_edge_bwd;
+  *edge_waves = ctx->nw_edge_bwd;
   return XMGN_OK;
 }
 
@@ -1326,6 +1331,7 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   // the edge adjoint runs on its own tiling of the batch's edges
   Shape se = s;
   se.mt_edge = s.mt_edge_bwd;
+  se.nw_edge = s.nw_edge_bwd;
   const bool fw = edge_bwd_fuses_wgrad(se);
   const bool fw1e = edge_bwd_fuses_dw1e(se, c->tape_z);  // else the e-block of dW1 is a separate product
   if (fw) se.grid = std::min(s.grid, 512);
@@ -1620,7 +1626,7 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
   if (xmgn_status r = xmgn_forward(c, d, params, ps, part_ids, n_batch, node_in, pos, edge_norm, out, 1, stream))
     return r;
   const std::string key = tune_key(c, d);
-  int best[5] = {0, 0, 0, 0, 0};  // edge rows, node rows, grid, edge waves, adjoint edge rows
+  int best[6] = {0, 0, 0, 0, 0, 0};  // edge rows, node rows, grid, edge waves, adjoint edge rows, adjoint waves
   float best_ms = -1.f;
   if (cache_path) {
     std::ifstream f(cache_path);
@@ -1628,14 +1634,15 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
     while (std::getline(f, line)) {
       std::istringstream is(line);
       std::string k;
-      int e, n, g, wv, br;
+      int e, n, g, wv, br, bw;
       float ms;
-      if (is >> k >> e >> n >> g >> wv >> br >> ms && k == key) {
+      if (is >> k >> e >> n >> g >> wv >> br >> bw >> ms && k == key) {
         best[0] = e;
         best[1] = n;
         best[2] = g;
         best[3] = wv;
         best[4] = br;
+        best[5] = bw;
         best_ms = ms;
       }
     }
@@ -1645,9 +1652,9 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     xmgn_status err = XMGN_OK;
-    auto trial = [&](int er, int nr, int g, int wv, int br) -> xmgn_status {
+    auto trial = [&](int er, int nr, int g, int wv, int br, int bw) -> xmgn_status {
       if (xmgn_status r = xmgn_ctx_set_tiles(c, er, nr, g, wv)) return r;
-      if (xmgn_status r = xmgn_ctx_set_bwd_tiles(c, br)) return r;
+      if (xmgn_status r = xmgn_ctx_set_bwd_tiles(c, br, bw)) return r;
       auto step = [&]() -> xmgn_status {
         if (xmgn_status r = xmgn_forward(c, d, params, ps, part_ids, n_batch, node_in, pos, edge_norm, out, 1, stream))
           return r;
@@ -1669,6 +1676,7 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
         best[2] = g;
         best[3] = wv;
         best[4] = br;
+        best[5] = bw;
       }
       return XMGN_OK;
     };
@@ -1679,15 +1687,22 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
     for (int er : rows)
       for (int wv : {4, 8})
         for (int wpc : {4, 8})
-          if (!err) err = trial(er, 32, ((cus * wpc + 7) / 8) * 8, wv, 0);
-    if (!err && d->hidden == 128) err = trial(best[0], 64, best[2], best[3], 0);
-    // stage 3 (BF16, H = 128 and 256): the edge adjoint on its own tile rows,
-    // paired with either forward tiling (stage 1 timed equal rows only)
-    if (!err && (d->hidden == 128 || d->hidden == 256) && d->precision == 1) {
-      const int nr = best[1], g = best[2], wv = best[3];
-      for (int er : rows)
-        for (int br : {32, 64})
-          if (!err && br != er) err = trial(er, nr, g, wv, br);
+          if (!err) err = trial(er, 32, ((cus * wpc + 7) / 8) * 8, wv, 0, 0);
+    if (!err && d->hidden == 128) err = trial(best[0], 64, best[2], best[3], 0, 0);
+    // stage 3: the edge adjoint on its own waves per workgroup and (BF16,
+    // H = 128 and 256) its own tile rows, against each forward tiling and
+    // wave count (stage 1 timed the adjoint on the forward's rows and waves
+    // only)
+    if (!err) {
+      const bool own_rows = (d->hidden == 128 || d->hidden == 256) && d->precision == 1;
+      const int nr = best[1], g = best[2];
+      const std::vector<int> ers = own_rows ? rows : std::vector<int>{best[0]};
+      const std::vector<int> brs = own_rows ? std::vector<int>{32, 64} : std::vector<int>{0};
+      for (int er : ers)
+        for (int wv : {4, 8})
+          for (int br : brs)
+            for (int bw : {4, 8})
+              if (!err && !((br == 0 || br == er) && bw == wv)) err = trial(er, nr, g, wv, br, bw);
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -1695,11 +1710,11 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
     if (cache_path) {
       std::ofstream f(cache_path, std::ios::app);
       f << key << " " << best[0] << " " << best[1] << " " << best[2] << " " << best[3] << " " << best[4] << " "
-        << best_ms << "\n";
+        << best[5] << " " << best_ms << "\n";
     }
   }
   if (xmgn_status r = xmgn_ctx_set_tiles(c, best[0], best[1], best[2], best[3])) return r;
-  if (xmgn_status r = xmgn_ctx_set_bwd_tiles(c, best[4])) return r;
+  if (xmgn_status r = xmgn_ctx_set_bwd_tiles(c, best[4], best[5])) return r;
   if (edge_rows) *edge_rows = best[0];
   if (node_rows) *node_rows = best[1];
   if (grid) *grid = best[2];

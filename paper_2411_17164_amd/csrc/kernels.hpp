@@ -55,6 +55,7 @@ struct Shape {
   int mt_node;  // rows per node tile
   int grid;     // persistent grid (workgroups)
   int nw_edge;  // waves per workgroup of the edge kernels (4 or 8)
+  int nw_edge_bwd;  // waves per workgroup of the edge adjoint
   float eps;
 };
 

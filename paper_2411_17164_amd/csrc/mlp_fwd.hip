@@ -30,14 +30,17 @@ struct Dims {
 // ---------------------------------------------------------------------------
 // NW waves per workgroup; each wave owns H / NW output columns of every GEMM.
 // SPLIT: the first layer's node blocks come precomputed per node (see
-// k_node_proj), so only the e rows are gathered; the staging tile must still
-// hold the FP32 tile of the segment sums.
+// k_node_proj), so only the e rows are gathered.  The FP32 tile of the
+// segment sums aliases the staging tile; where it would be the larger (the
+// split form), it holds one half of the columns at a time (NH = 2).
 template <typename T, int H, int MT, int NW, int SPLIT = 0>
 struct EdgeFwdLds {
   using D = Dims<T, H, NW>;
   static constexpr size_t GS = (size_t)MT * (SPLIT ? D::LDH : D::LD3) * sizeof(T);
-  static constexpr size_t FS = (size_t)MT * D::LDF * 4;
-  static constexpr size_t XS = SPLIT && FS > GS ? FS : GS;
+  static constexpr int NH = (size_t)MT * D::LDF * 4 > GS ? 2 : 1;
+  static constexpr int LDFH = H / NH + 4;
+  static constexpr size_t FS = (size_t)MT * LDFH * 4;
+  static constexpr size_t XS = FS > GS ? FS : GS;
   static constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
   static constexpr size_t bytes = XS + ZS + 2 * NW * MT * 4 + 2 * MT * 4;
 };
@@ -59,7 +62,9 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW, SP
   constexpr int EC = SPLIT ? 0 : 2 * H;          // column of e in a staged row
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t XS = L::XS, ZS = L::ZS;
-  static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
+  constexpr int NH = L::NH, HH = H / NH, LDFH = L::LDFH;
+  static_assert(NH == 1 || !SPLIT || D::CPW <= HH, "a wave's columns lie in one half");
+  static_assert(SPLIT || NH == 1, "the gathered tile holds the whole FP32 tile");
   __shared__ __align__(16) unsigned char smem[L::bytes];
   T* xs = (T*)smem;
   float* ft = (float*)smem;  // aliases xs once the gathered tile is dead
@@ -173,26 +178,38 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW, SP
           const int row = acc_row(mb, r);
           const float v = g * acc[mb][nb][r] + be;
           const float en = ev[mb][nb][r] + v;
-          ft[row * D::LDF + c] = AGG ? en : v;
+          acc[mb][nb][r] = AGG ? en : v;  // the summand of m
           zs[row * D::LDH + c] = from_f<T>(en);
         }
       }
-    lds_sync();
 
-    // m_r: sequential sum over the receiver's edges (ascending sender id)
+    // m_r: sequential sum over the receiver's edges (ascending sender id),
+    // NH column blocks of HH columns each
     const int nr = r1 - r0;
-    for (int task = threadIdx.x; task < nr * (H / 4); task += 64 * NW) {
-      const int rl = task / (H / 4), q = task - rl * (H / 4);
-      const int lo = b.row_ptr[r0 + rl] - e0, hi = b.row_ptr[r0 + rl + 1] - e0;
-      float4 s = {0.f, 0.f, 0.f, 0.f};
-      for (int i = lo; i < hi; ++i) {
-        const float4 v = *(const float4*)(ft + i * D::LDF + 4 * q);
-        s.x += v.x;
-        s.y += v.y;
-        s.z += v.z;
-        s.w += v.w;
+#pragma unroll
+    for (int hf = 0; hf < NH; ++hf) {
+      if (n0 / HH == hf)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ft[acc_row(mb, r) * LDFH + acc_col(n0, nb) - hf * HH] = acc[mb][nb][r];
+      lds_sync();
+      for (int task = threadIdx.x; task < nr * (HH / 4); task += 64 * NW) {
+        const int rl = task / (HH / 4), q = task - rl * (HH / 4);
+        const int lo = b.row_ptr[r0 + rl] - e0, hi = b.row_ptr[r0 + rl + 1] - e0;
+        float4 s = {0.f, 0.f, 0.f, 0.f};
+        for (int i = lo; i < hi; ++i) {
+          const float4 v = *(const float4*)(ft + i * LDFH + 4 * q);
+          s.x += v.x;
+          s.y += v.y;
+          s.z += v.z;
+          s.w += v.w;
+        }
+        *(float4*)(m + (size_t)(r0 + rl) * H + hf * HH + 4 * q) = s;
       }
-      *(float4*)(m + (size_t)(r0 + rl) * H + 4 * q) = s;
+      if (hf + 1 < NH) lds_sync();  // the next block overwrites the FP32 tile
     }
     if (e_out) lds_rows_to_global<T, D::LDH>(zs, ne, H, e_out + (size_t)e0 * H, H, [](int i) { return i; });
     lds_sync();

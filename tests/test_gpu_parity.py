@@ -204,8 +204,10 @@ def test_fwd_bwd_h256_car_15_layers(api, ctx, loss, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-@pytest.mark.parametrize("edge_rows,edge_waves,bwd_rows", [(32, 8, 0), (64, 8, 0), (32, 4, 0), (64, 4, 32), (32, 4, 64)])
-def test_tile_configs(api, precision, edge_rows, edge_waves, bwd_rows):
+@pytest.mark.parametrize("edge_rows,edge_waves,bwd_rows,bwd_waves",
+                         [(32, 8, 0, 0), (64, 8, 0, 0), (32, 4, 0, 0), (64, 4, 32, 0), (32, 4, 64, 0),
+                          (64, 8, 32, 4), (64, 4, 32, 8)])
+def test_tile_configs(api, precision, edge_rows, edge_waves, bwd_rows, bwd_waves):
     """Every tile / wave configuration the autotuner may pick meets the bound.
     SiLU keeps the comparison well conditioned: with ReLU, FP32-sized
     perturbations of the FP64 oracle itself move single gradient tensors by
@@ -213,12 +215,12 @@ def test_tile_configs(api, precision, edge_rows, edge_waves, bwd_rows):
     the rounding order could not be told apart from errors."""
     c = api.Context(0)
     c.set_tiles(edge_rows, 32, 256, edge_waves)
-    c.set_bwd_tiles(bwd_rows)  # the edge adjoint's own tiling (BF16 at H = 128; else the forward's)
+    c.set_bwd_tiles(bwd_rows, bwd_waves)  # the edge adjoint's own tiles (rows: BF16 only; waves: any form)
     case = Case(3, levels=(500, 2000, 6000), layers=3, precision=precision, activation="silu")
     g = gpu_graph(api, c, case)
     ps = api.Partset.halo(g, case.inp.pos, None, case.L)
     out, loss, grad = gpu_step(api, c, case, ps, [0])
-    log(f"  tiles {edge_rows}x{edge_waves} (adjoint {bwd_rows or edge_rows}) {precision}: "
+    log(f"  tiles {edge_rows}x{edge_waves} (adjoint {bwd_rows or edge_rows}x{bwd_waves or edge_waves}) {precision}: "
         + check_step(case, out, loss, grad, oracle_refs(case)))
 
 
@@ -231,7 +233,7 @@ def test_adjoint_tiles_relu_bf16(api, bwd_rows, agg):
     c = api.Context(0)
     c.set_tiles(64, 32, 512, 4)
     c.set_bwd_tiles(bwd_rows)
-    assert c.get_bwd_tiles() == bwd_rows
+    assert c.get_bwd_tiles() == (bwd_rows, 0)
     case = Case(3, levels=(500, 2000, 6000), layers=4, precision="bf16", activation="relu", aggregate=agg)
     g = gpu_graph(api, c, case)
     ps = api.Partset.halo(g, case.inp.pos, None, case.L)
@@ -247,8 +249,8 @@ def test_adjoint_tiles_h256_bf16(api, fwd_rows, bwd_rows, act):
     the same receiver segments on its own, and reads z (and a) from the tape
     by edge id whatever tile wrote them."""
     c = api.Context(0)
-    c.set_tiles(fwd_rows, 32, 512, 4)
-    c.set_bwd_tiles(bwd_rows)
+    c.set_tiles(fwd_rows, 32, 512, 8 if fwd_rows == 64 else 4)
+    c.set_bwd_tiles(bwd_rows, 4)
     case = Case(5, levels=(400, 1600, 5000), layers=3, precision="bf16", activation=act)
     assert case.H == 256
     g = gpu_graph(api, c, case)

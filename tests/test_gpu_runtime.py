@@ -67,6 +67,8 @@ def test_autotune_and_cache(api, tmp_path):
     assert len(lines) == 1
     key, *vals = lines[0].split()
     assert [int(v) for v in vals[:4]] == [er, nr, gr, wv]
+    br, bw = ctx.get_bwd_tiles()
+    assert [int(v) for v in vals[4:6]] == [br, bw] and br in (0, 32, 64) and bw in (0, 4, 8)
     assert ":H128:L2:p1:a1:g0:" in key
     # the cached configuration comes back as is
     ctx2 = api.Context(0)
