@@ -12,6 +12,7 @@
 #include <numeric>
 #include <string>
 #include <thread>
+#include <stdexcept>
 #include <vector>
 
 #include "../../include/xmgn.h"
@@ -548,6 +549,7 @@ struct xmgn_ctx {
   size_t sev_used = 0;
   // backward workspace
   DBuf dhA, dhMid, dm, Sr, Ss, deA, deB, fa, fb, fc, fd, dy, part, wpart, wfused, redtmp, lossp;
+  DBuf part_e, wfused_e;  // the edge adjoint's partials, reduced with the node adjoint's at the end of a layer
   DBuf xe;    // edge features of the forward [E][4]
   DBuf optp;  // optimizer: per-workgroup squared-norm partials (FP64)
   DBuf zt;  // hidden activations of the edge MLPs [L][E][H] (BF16 forms, device-resident tape)
@@ -753,6 +755,7 @@ extern "C" xmgn_status xmgn_ctx_memory(const xmgn_ctx* c, int64_t* bytes) {
   const DBuf* bufs[] = {&c->jobs_dev, &c->blob, &c->h, &c->e, &c->m, &c->dhA, &c->dhMid,
                         &c->dm, &c->Sr, &c->Ss, &c->deA, &c->deB, &c->fa, &c->fb, &c->fc, &c->fd,
                         &c->dy, &c->part, &c->wpart, &c->wfused, &c->redtmp, &c->lossp, &c->xe, &c->zt,
+                        &c->part_e, &c->wfused_e, &c->proj,
                         &c->at, &c->optp};
   for (const DBuf* b : bufs) t += (int64_t)b->bytes;
   *bytes = t;
@@ -1311,6 +1314,8 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   const size_t H = d->hidden, n = c->cur->n, E = c->cur->E, ts = tsize(d);
   const int L = d->n_layers, G = s.grid;
   const size_t rows = std::max(n, E);
+  constexpr int kLayerWgrads = 7;
+  size_t wpart_stride = 0;
   for (DBuf* p : {&c->dhA, &c->dhMid, &c->dm, &c->Sr, &c->Ss})
     if (xmgn_status r = p->ensure(n * H * 4, st)) return r;
   for (DBuf* p : {&c->deA, &c->deB})
@@ -1325,7 +1330,10 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     for (int R : Rs)
       need = std::max(need, wgrad_partial_floats(s, wop(nullptr, 0, 0, 0, nullptr, nullptr, 0, 0, 0, nullptr, R,
                                                         (int)H, (int)H, nullptr, 0)));
-    if (xmgn_status r = c->wpart.ensure(need * 4, st)) return r;
+    // a layer's separate weight-gradient products (at most 3 node-side, 4
+    // edge-side) each keep their partials until the layer's reductions run
+    wpart_stride = need;
+    if (xmgn_status r = c->wpart.ensure(kLayerWgrads * need * 4, st)) return r;
   }
   // the edge adjoint may accumulate its dense weight gradients itself
   // the edge adjoint runs on its own tiling of the batch's edges
@@ -1335,12 +1343,16 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   const bool fw = edge_bwd_fuses_wgrad(se);
   const bool fw1e = edge_bwd_fuses_dw1e(se, c->tape_z);  // else the e-block of dW1 is a separate product
   if (fw) se.grid = std::min(s.grid, 512);
-  if (fw || enc_bwd_fuses_wgrad(s) || node_bwd_fuses_wgrad(s)) {
-    // edge adjoint: [se.grid][2][H][H]; encoders: [<=256][2][H][H]; node adjoint: [<=256][3][H][H]
-    const size_t mats = std::max((size_t)se.grid * 2, (size_t)std::min(s.grid, 256) * 3);
-    if (xmgn_status r = c->wfused.ensure(mats * H * H * 4, st)) return r;
+  if (enc_bwd_fuses_wgrad(s) || node_bwd_fuses_wgrad(s)) {
+    // encoders: [<=256][2][H][H]; node adjoint: [<=256][3][H][H]
+    if (xmgn_status r = c->wfused.ensure((size_t)std::min(s.grid, 256) * 3 * H * H * 4, st)) return r;
   }
-  if (xmgn_status r = c->redtmp.ensure(reduce_tmp_floats((int)std::max<size_t>(H * H, 16 * H)) * 4, st)) return r;
+  if (fw)  // edge adjoint: [se.grid][2][H][H]
+    if (xmgn_status r = c->wfused_e.ensure((size_t)se.grid * 2 * H * H * 4, st)) return r;
+  if (xmgn_status r = c->part_e.ensure((size_t)se.grid * 4 * H * 4, st)) return r;
+  // one layer's batch of reductions: at most 9 H x H matrices and 8 H-vectors
+  const size_t red_cols = std::max<size_t>(std::max<size_t>(H * H, 16 * H), 9 * H * H + 8 * H);
+  if (xmgn_status r = c->redtmp.ensure(reduce_tmp_floats((int)red_cols) * 4, st)) return r;
   float* rt = c->redtmp.as<float>();
   float* part = c->part.as<float>();
   auto P = [&](int block, int layer, int t) { return d_params + poff(d, block, layer, t); };
@@ -1384,53 +1396,62 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     NodeBwdOut no{c->dhMid.as<float>(), c->dm.as<float>(), c->fa.p, c->fb.p, c->fc.p, part,
                   fnode ? c->wfused.as<float>() : nullptr};
     { KT("node_bwd"); launch_node_bwd(snode, b, wn, hl(l), mslot(c, d, l), c->dhA.as<float>(), no, st); }
+    // the layer's reductions of partial sums run as one batch at its end
+    RedBatch rb;
+    int n_wg = 0;
+    auto wg = [&](const WgradOp& op) {
+      if (n_wg >= kLayerWgrads) throw std::logic_error("more weight-gradient products in a layer than partials");
+      KT("wgrad");
+      launch_wgrad_partials(s, op, c->wpart.as<float>() + (size_t)(n_wg++) * wpart_stride, rb, st);
+    };
     VecSeg ns[4] = {{0, (int)H, P(3, l, 1)}, {(int)H, (int)H, P(3, l, 3)}, {2 * (int)H, (int)H, P(3, l, 4)},
                     {3 * (int)H, (int)H, P(3, l, 5)}};
-    launch_vec_reduce(part, snode.grid, 4 * (int)H, ns, 4, rt, st);
+    rb.add_vec(part, snode.grid, 4 * (int)H, ns, 4);
     if (fnode) {
-      KT("wgrad");
       const int MN3 = 3 * (int)(H * H);
       float* wf = c->wfused.as<float>();
-      launch_wgrad_reduce(wf, snode.grid, (int)H, (int)H, P(3, l, 2), (int)H, MN3, rt, st);
-      launch_wgrad_reduce(wf + H * H, snode.grid, (int)H, (int)H, P(3, l, 0), 2 * (int)H, MN3, rt, st);
-      launch_wgrad_reduce(wf + 2 * H * H, snode.grid, (int)H, (int)H, P(3, l, 0) + H, 2 * (int)H, MN3, rt, st);
+      rb.add(wf, snode.grid, MN3, (int)H, (int)H, P(3, l, 2), (int)H);
+      rb.add(wf + H * H, snode.grid, MN3, (int)H, (int)H, P(3, l, 0), 2 * (int)H);
+      rb.add(wf + 2 * H * H, snode.grid, MN3, (int)H, (int)H, P(3, l, 0) + H, 2 * (int)H);
     } else {
-      wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 0),
-                   2 * (int)H), c->wpart, st);
-      wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, mslot(c, d, l), 1, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
-                   P(3, l, 0) + H, 2 * (int)H), c->wpart, st);
-      wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, c->fc.p, 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
-                   P(3, l, 2), (int)H), c->wpart, st);
+      wg(wop(c->fa.p, 0, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 0),
+             2 * (int)H));
+      wg(wop(c->fa.p, 0, (int)H, 0, nullptr, mslot(c, d, l), 1, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
+             P(3, l, 0) + H, 2 * (int)H));
+      wg(wop(c->fb.p, 0, (int)H, 0, nullptr, c->fc.p, 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 2),
+             (int)H));
     }
 
     const MlpW we = weights(c, d, params, 2 + 2 * l, 2, l);
-    EdgeBwdOut eo{de_out->as<float>(), c->Sr.as<float>(), c->fa.p, c->fb.p, c->fc.p, part,
-                  fw ? c->wfused.as<float>() : nullptr};
+    EdgeBwdOut eo{de_out->as<float>(), c->Sr.as<float>(), c->fa.p, c->fb.p, c->fc.p, c->part_e.as<float>(),
+                  fw ? c->wfused_e.as<float>() : nullptr};
     const void* zt = edge_z_tape(se) ? zslot(c, d, l) : nullptr;  // the forward's z, when it kept it
     const void* at = edge_a_tape(se) ? aslot(c, d, l) : nullptr;  // ... and a (SiLU)
     { KT("edge_bwd"); launch_edge_bwd(se, c->cur->view_b, we, hl(l), eslot(c, d, l), zt, at, de_in, c->dm.as<float>(), eo, st); }
     VecSeg es[4] = {{0, (int)H, P(2, l, 1)}, {(int)H, (int)H, P(2, l, 3)}, {2 * (int)H, (int)H, P(2, l, 4)},
                     {3 * (int)H, (int)H, P(2, l, 5)}};
-    launch_vec_reduce(part, se.grid, 4 * (int)H, es, 4, rt, st);
+    rb.add_vec(c->part_e.as<float>(), se.grid, 4 * (int)H, es, 4);
     if (fw) {
-      KT("wgrad");
-      launch_wgrad_reduce(c->wfused.as<float>(), se.grid, (int)H, (int)H, P(2, l, 2), (int)H, 2 * (int)(H * H), rt, st);
+      rb.add(c->wfused_e.as<float>(), se.grid, 2 * (int)(H * H), (int)H, (int)H, P(2, l, 2), (int)H);
       if (fw1e)
-        launch_wgrad_reduce(c->wfused.as<float>() + H * H, se.grid, (int)H, (int)H, P(2, l, 0) + 2 * H, 3 * (int)H,
-                            2 * (int)(H * H), rt, st);
+        rb.add(c->wfused_e.as<float>() + H * H, se.grid, 2 * (int)(H * H), (int)H, (int)H, P(2, l, 0) + 2 * H,
+               3 * (int)H);
     }
     { KT("sender_sum"); launch_sender_sum(s, b, c->fa.p, c->Ss.as<float>(), st); }
     { KT("node_dh"); launch_node_dh(s, b, we, c->dhMid.as<float>(), c->Sr.as<float>(), c->Ss.as<float>(), c->dhA.as<float>(), st); }
-    wgrad(s, wop(c->Sr.p, 1, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(2, l, 0),
-                 3 * (int)H), c->wpart, st);
-    wgrad(s, wop(c->Ss.p, 1, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
-                 P(2, l, 0) + H, 3 * (int)H), c->wpart, st);
+    wg(wop(c->Sr.p, 1, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(2, l, 0),
+           3 * (int)H));
+    wg(wop(c->Ss.p, 1, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(2, l, 0) + H,
+           3 * (int)H));
     if (!fw1e)
-      wgrad(s, wop(c->fa.p, 0, (int)H, 0, nullptr, eslot(c, d, l), 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H,
-                   P(2, l, 0) + 2 * H, 3 * (int)H), c->wpart, st);
+      wg(wop(c->fa.p, 0, (int)H, 0, nullptr, eslot(c, d, l), 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H,
+             P(2, l, 0) + 2 * H, 3 * (int)H));
     if (!fw)
-      wgrad(s, wop(c->fb.p, 0, (int)H, 0, nullptr, zt ? zt : c->fc.p, 0, (int)H, 0, nullptr, (int)E, (int)H,
-                   (int)H, P(2, l, 2), (int)H), c->wpart, st);
+      wg(wop(c->fb.p, 0, (int)H, 0, nullptr, zt ? zt : c->fc.p, 0, (int)H, 0, nullptr, (int)E, (int)H, (int)H,
+             P(2, l, 2), (int)H));
+    if ((size_t)rb.tmp_floats > reduce_tmp_floats((int)red_cols))
+      throw std::logic_error("a layer's reduction batch exceeds its scratch");
+    { KT("wgrad"); launch_reduce_batch(rb, rt, st); }
     de_in = de_out->as<float>();
     std::swap(de_out, de_other);
   }

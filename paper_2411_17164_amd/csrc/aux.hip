@@ -3,6 +3,7 @@
 // of per-workgroup partial vectors, weight preparation (cast / transpose into
 // the compute type), the masked MSE and gradient accumulation.
 #include <mutex>
+#include <stdexcept>
 #include <type_traits>
 
 #include "common.hpp"
@@ -215,6 +216,81 @@ void launch_wgrad(const Shape& s, const WgradOp& op, float* partial, float* tmp,
     }
   }
   colsum_to(partial, nc, op.M * op.N, op.M_valid, op.N, op.dst, op.ldd, tmp, st);
+}
+
+void launch_wgrad_partials(const Shape& s, const WgradOp& op, float* partial, RedBatch& b, hipStream_t st) {
+  int rpc;
+  const int nc = wgrad_chunks(op, &rpc);
+  const int nbm = (op.M + WG_B - 1) / WG_B, nbn = (op.N + WG_B - 1) / WG_B;
+  if (nc > 0) {
+    dim3 grid(nc, nbm * nbn);
+    if (s.prec == 1) {
+      if (op.a_f32 && op.b_f32) k_wgrad<bf16, float, float><<<grid, NTHR, 0, st>>>(op, rpc, nbm, partial);
+      else if (op.a_f32) k_wgrad<bf16, float, bf16><<<grid, NTHR, 0, st>>>(op, rpc, nbm, partial);
+      else if (op.b_f32) k_wgrad<bf16, bf16, float><<<grid, NTHR, 0, st>>>(op, rpc, nbm, partial);
+      else k_wgrad<bf16, bf16, bf16><<<grid, NTHR, 0, st>>>(op, rpc, nbm, partial);
+    } else {
+      k_wgrad<float, float, float><<<grid, NTHR, 0, st>>>(op, rpc, nbm, partial);
+    }
+  }
+  b.add(partial, nc, op.M * op.N, op.M_valid, op.N, op.dst, op.ldd);
+}
+
+// Batched form: blockIdx.z selects the job; the per-job work is exactly
+// k_colsum_stage1's and k_wgrad_reduce's.
+__global__ void k_colsum_batch1(RedBatch b, float* __restrict__ tmp) {
+  const RedJob& jb = b.job[blockIdx.z];
+  const int ncol = jb.M_valid * jb.N;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (j >= ncol || s >= jb.splits) return;
+  const int r0 = s * jb.per, r1 = min(jb.rows, r0 + jb.per);
+  float a0 = 0.f, a1 = 0.f;
+  int r = r0;
+  for (; r + 1 < r1; r += 2) {
+    a0 += jb.src[(size_t)r * jb.stride + j];
+    a1 += jb.src[(size_t)(r + 1) * jb.stride + j];
+  }
+  if (r < r1) a0 += jb.src[(size_t)r * jb.stride + j];
+  tmp[jb.tmp_off + (size_t)s * ncol + j] = a0 + a1;
+}
+
+__global__ void k_colsum_batch2(RedBatch b, const float* __restrict__ tmp) {
+  const RedJob& jb = b.job[blockIdx.y];
+  const int ncol = jb.M_valid * jb.N;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ncol) return;
+  const int m = idx / jb.N, n = idx - m * jb.N;
+  float s = 0.f;
+  for (int k = 0; k < jb.splits; ++k) s += tmp[jb.tmp_off + (size_t)k * ncol + idx];
+  jb.dst[(size_t)m * jb.ldd + n] = s;
+}
+
+void RedBatch::add(const float* src, int rows, int stride, int M_valid, int N, float* dst, int ldd) {
+  if (n >= kMaxRedJobs) throw std::runtime_error("reduction batch is full");
+  RedJob& j = job[n++];
+  j.src = src;
+  j.dst = dst;
+  j.rows = rows;
+  j.stride = stride;
+  j.M_valid = M_valid;
+  j.N = N;
+  j.ldd = ldd;
+  j.splits = rows < RED_SPLITS ? (rows > 0 ? rows : 1) : RED_SPLITS;
+  j.per = rows > 0 ? (rows + j.splits - 1) / j.splits : 0;
+  j.tmp_off = tmp_floats;
+  tmp_floats += (long long)j.splits * M_valid * N;
+  if (M_valid * N > max_cols) max_cols = M_valid * N;
+}
+
+void RedBatch::add_vec(const float* partial, int G, int row, const VecSeg* segs, int n_seg) {
+  for (int i = 0; i < n_seg; ++i) add(partial + segs[i].src, G, row, 1, segs[i].len, segs[i].dst, 0);
+}
+
+void launch_reduce_batch(const RedBatch& b, float* tmp, hipStream_t st) {
+  if (b.n == 0) return;
+  k_colsum_batch1<<<dim3((b.max_cols + 255) / 256, RED_SPLITS, b.n), 256, 0, st>>>(b, tmp);
+  k_colsum_batch2<<<dim3((b.max_cols + 255) / 256, b.n), 256, 0, st>>>(b, tmp);
 }
 
 // ---------------------------------------------------------------------------

@@ -199,6 +199,32 @@ void launch_vec_reduce(const float* partial, int G, int row, const VecSeg* segs,
 void launch_vec_reduce_strided(const float* partial, int G, int row, int src, int runs, int inner, int src_stride,
                                float* dst, int dst_stride, float* tmp, hipStream_t st);
 
+// A batch of the same fixed-order two-stage reductions, run as two launches
+// in all: job j sets dst[m * ldd + n] = sum over r < rows of
+// src[r * stride + m * N + n] (m < M_valid, n < N), with the split points
+// and summation order of the single reductions above, so each result is
+// bitwise the one a single reduction gives.
+struct RedJob {
+  const float* src;
+  float* dst;
+  int rows, stride, M_valid, N, ldd, splits, per;
+  long long tmp_off;  // this job's stage-1 scratch, in floats
+};
+constexpr int kMaxRedJobs = 24;
+struct RedBatch {
+  int n = 0;
+  int max_cols = 0;
+  long long tmp_floats = 0;  // scratch the batch needs
+  RedJob job[kMaxRedJobs];
+  void add(const float* src, int rows, int stride, int M_valid, int N, float* dst, int ldd);
+  // the segments of a per-workgroup partial row [G][row] (launch_vec_reduce)
+  void add_vec(const float* partial, int G, int row, const VecSeg* segs, int n_seg);
+};
+void launch_reduce_batch(const RedBatch& b, float* tmp, hipStream_t st);
+// The products of launch_wgrad without their reduction: adds that
+// reduction to b.
+void launch_wgrad_partials(const Shape& s, const WgradOp& op, float* partial, RedBatch& b, hipStream_t st);
+
 struct PrepJob {
   int64_t src_off;   // element offset in the FP32 params
   int src_ld;        // row stride of the source matrix
