@@ -1343,9 +1343,11 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
   const bool fw = edge_bwd_fuses_wgrad(se);
   const bool fw1e = edge_bwd_fuses_dw1e(se, c->tape_z);  // else the e-block of dW1 is a separate product
   if (fw) se.grid = std::min(s.grid, 512);
-  if (enc_bwd_fuses_wgrad(s) || node_bwd_fuses_wgrad(s)) {
-    // encoders: [<=256][2][H][H]; node adjoint: [<=256][3][H][H]
-    if (xmgn_status r = c->wfused.ensure((size_t)std::min(s.grid, 256) * 3 * H * H * 4, st)) return r;
+  const bool fnode = node_bwd_fuses_wgrad(s);
+  if (enc_bwd_fuses_wgrad(s) || fnode) {
+    // encoders: [<=256][2][H][H]; node adjoint: [<=512][H][H]
+    const size_t mats = std::max((size_t)std::min(s.grid, 256) * 2, (size_t)std::min(s.grid, 512));
+    if (xmgn_status r = c->wfused.ensure(mats * H * H * 4, st)) return r;
   }
   if (fw)  // edge adjoint: [se.grid][2][H][H]
     if (xmgn_status r = c->wfused_e.ensure((size_t)se.grid * 2 * H * H * 4, st)) return r;
@@ -1375,9 +1377,8 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
           c->wpart, st);
   }
   // processor layers, last to first
-  const bool fnode = node_bwd_fuses_wgrad(s);
-  Shape snode = s;  // node adjoint: with LDS-resident weights, one workgroup per CU
-  if (fnode) snode.grid = std::min(s.grid, 256);
+  Shape snode = s;  // node adjoint with W2 resident in LDS: two workgroups per CU
+  if (fnode) snode.grid = std::min(s.grid, 512);
   const float* de_in = nullptr;
   DBuf* de_out = &c->deA;
   DBuf* de_other = &c->deB;
@@ -1407,20 +1408,16 @@ extern "C" xmgn_status xmgn_backward(xmgn_ctx* c, const xmgn_model_desc* d, cons
     VecSeg ns[4] = {{0, (int)H, P(3, l, 1)}, {(int)H, (int)H, P(3, l, 3)}, {2 * (int)H, (int)H, P(3, l, 4)},
                     {3 * (int)H, (int)H, P(3, l, 5)}};
     rb.add_vec(part, snode.grid, 4 * (int)H, ns, 4);
-    if (fnode) {
-      const int MN3 = 3 * (int)(H * H);
-      float* wf = c->wfused.as<float>();
-      rb.add(wf, snode.grid, MN3, (int)H, (int)H, P(3, l, 2), (int)H);
-      rb.add(wf + H * H, snode.grid, MN3, (int)H, (int)H, P(3, l, 0), 2 * (int)H);
-      rb.add(wf + 2 * H * H, snode.grid, MN3, (int)H, (int)H, P(3, l, 0) + H, 2 * (int)H);
-    } else {
-      wg(wop(c->fa.p, 0, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 0),
-             2 * (int)H));
-      wg(wop(c->fa.p, 0, (int)H, 0, nullptr, mslot(c, d, l), 1, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
-             P(3, l, 0) + H, 2 * (int)H));
+    // dW1 = sum da [h ; m]^T (two products); dW2 = sum du z^T, fused or a product
+    wg(wop(c->fa.p, 0, (int)H, 0, nullptr, hl(l), 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 0),
+           2 * (int)H));
+    wg(wop(c->fa.p, 0, (int)H, 0, nullptr, mslot(c, d, l), 1, (int)H, 0, nullptr, (int)n, (int)H, (int)H,
+           P(3, l, 0) + H, 2 * (int)H));
+    if (fnode)
+      rb.add(c->wfused.as<float>(), snode.grid, (int)(H * H), (int)H, (int)H, P(3, l, 2), (int)H);
+    else
       wg(wop(c->fb.p, 0, (int)H, 0, nullptr, c->fc.p, 0, (int)H, 0, nullptr, (int)n, (int)H, (int)H, P(3, l, 2),
              (int)H));
-    }
 
     const MlpW we = weights(c, d, params, 2 + 2 * l, 2, l);
     EdgeBwdOut eo{de_out->as<float>(), c->Sr.as<float>(), c->fa.p, c->fb.p, c->fc.p, c->part_e.as<float>(),

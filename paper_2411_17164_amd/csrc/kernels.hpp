@@ -125,10 +125,10 @@ struct NodeBwdOut {
   void* du;        // [n][H] T
   void* z;         // [n][H] T
   float* partial;  // [grid][4H]
-  float* wpart;    // fused [grid][3][H][H]: dW2, dW1[:, 0:H], dW1[:, H:2H] (or NULL)
+  float* wpart;    // fused dW2 partials [grid][H][H] (or NULL)
 };
-// True when the node adjoint accumulates dW2 and dW1 itself (then z, du and
-// da are not written and wpart must be given).
+// True when the node adjoint accumulates dW2 itself (then z and du are not
+// written and wpart must be given); da is always written.
 bool node_bwd_fuses_wgrad(const Shape& s);
 void launch_node_bwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h,
                      const float* m, const float* dh_in, const NodeBwdOut& o, hipStream_t st);

@@ -451,36 +451,36 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
 
 // ---------------------------------------------------------------------------
 // Node adjoint (with recompute).  dh_mid = dh' + (W1^T da)[0:H], dm = (W1^T da)[H:2H].
-// FN (BF16, H = 128, 32-row tiles): W1 and W2 live in LDS for the whole kernel and serve
-// both their products and, read transposed, the adjoint products; dW2 and
-// both blocks of dW1 are accumulated per workgroup on MFMA (du and da from
-// the accumulators; z, h and m read transposed from their tiles, the FP32
-// staging tile having its own LDS so that [h ; m] stays intact; partials to
-// o.wpart as [dW2 | dW1_h | dW1_m]), so z, du and da are not written.
+// FM (BF16, H = 128, 32-row tiles): W2 lives in LDS for the whole kernel
+// and serves both its product and, read transposed, dz = du W2; dW2 is
+// accumulated per workgroup on MFMA (du from the accumulators, z read
+// transposed from its tile; partials to o.wpart [grid][H][H]), so z and du
+// are not written.  78 KB of LDS: two workgroups per CU.  W1 and W1^T come
+// from L2, and da is written for the two dW1 blocks, which are separate
+// products over da, h and m.  (Keeping W1 in LDS too and fusing both dW1
+// blocks takes 146 KB, one workgroup per CU, and measured slower.)
 // ---------------------------------------------------------------------------
 bool node_bwd_fuses_wgrad(const Shape& s) { return s.prec == 1 && s.H == 128 && s.mt_node == 32; }
 
 template <typename T, int H, int MT, int ACT>
-__global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 && H == 128 ? 2 : 1)) void k_node_bwd(
+__global__ __launch_bounds__(NTHR, (MT == 32 && H == 128 ? 2 : 1)) void k_node_bwd(
     int n, MlpW w, const T* __restrict__ h, const float* __restrict__ m, const float* __restrict__ dh_in,
     NodeBwdOut o, float eps) {
   using D = BD<T, H>;
-  constexpr bool FN = sizeof(T) == 2 && H == 128 && MT == 32;  // LDS: 146 KB at 32 rows
+  constexpr bool FM = sizeof(T) == 2 && H == 128 && MT == 32;
   constexpr int MB = MT / 16, NB = D::NB;
-  constexpr int LDW1 = 2 * H + 8, LDW2 = H + 8;
+  constexpr int LDW2 = H + 8;
   constexpr size_t XS = (size_t)MT * D::LD2 * sizeof(T);
   constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
-  constexpr size_t W1S = FN ? (size_t)H * LDW1 * 2 : 0, W2S = FN ? (size_t)H * LDW2 * 2 : 0;
-  constexpr size_t FS = FN ? (size_t)MT * D::LDF * 4 : 0;  // FN: own FP32 tile
+  constexpr size_t W2S = FM ? (size_t)H * LDW2 * 2 : 0;
   static_assert((size_t)MT * D::LDF * 4 <= XS, "FP32 tile must fit in the staging tile");
-  static_assert(!FN || MB % 2 == 0, "fused weight gradients: k chunks of 32 rows");
-  __shared__ __align__(16) unsigned char smem[XS + ZS + 2 * NWAVE * MT * 4 + W1S + W2S + FS];
+  static_assert(!FM || MB % 2 == 0, "fused weight gradients: k chunks of 32 rows");
+  __shared__ __align__(16) unsigned char smem[XS + ZS + 2 * NWAVE * MT * 4 + W2S];
   T* xs = (T*)smem;
   T* zs = (T*)(smem + XS);
   float* red = (float*)(smem + XS + ZS);
-  bf16* W1s = (bf16*)(red + 2 * NWAVE * MT);  // FN: W1 [out][2H in]
-  bf16* W2s = W1s + (FN ? H * LDW1 : 0);      // FN: W2 [out][in]
-  float* ft = FN ? (float*)(W2s + H * LDW2) : (float*)smem;
+  bf16* W2s = (bf16*)(red + 2 * NWAVE * MT);  // FM: W2 [out][in]
+  float* ft = (float*)smem;                   // aliases [h ; m] once the first product is done
   const T* W1 = (const T*)w.W1;
   const T* W2 = (const T*)w.W2;
   const T* W2T = (const T*)w.W2T;
@@ -488,15 +488,9 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
   const int n0 = wave_id() * D::CPW;
   const int li = lane_id() & 15, lg = lane_id() >> 4;
   double cb1[NB] = {}, cb2[NB] = {}, cg[NB] = {}, cbt[NB] = {};
-  f32x4 accW2[NB][H / 16], accW1h[NB][H / 16], accW1m[NB][H / 16];
-  if constexpr (FN) {
+  f32x4 accW2[NB][H / 16];
+  if constexpr (FM) {
     zero_acc(accW2);
-    zero_acc(accW1h);
-    zero_acc(accW1m);
-    for (int c = threadIdx.x; c < H * (2 * H / 8); c += NTHR) {
-      const int r = c / (2 * H / 8), q = c - r * (2 * H / 8);
-      *(uint4*)(W1s + r * LDW1 + 8 * q) = *(const uint4*)(W1 + (size_t)r * 2 * H + 8 * q);
-    }
     for (int c = threadIdx.x; c < H * (H / 8); c += NTHR) {
       const int r = c / (H / 8), q = c - r * (H / 8);
       *(uint4*)(W2s + r * LDW2 + 8 * q) = *(const uint4*)(W2 + (size_t)r * H + 8 * q);
@@ -512,13 +506,7 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
     lds_sync();
     f32x4 a[MB][NB], x[MB][NB];
     zero_acc(a);
-    if constexpr (FN) {
-      wave_gemm_lds<MB, NB, 2 * H, D::LD2>(a, (const bf16*)xs, [&](int k, int nb) {
-        return *(const bf16x8*)(W1s + (n0 + 16 * nb + li) * LDW1 + k + 8 * lg);
-      });
-    } else {
-      wave_gemm<T, MB, NB, 2 * H, D::LD2>(a, xs, W1, 2 * H, n0);
-    }
+    wave_gemm<T, MB, NB, 2 * H, D::LD2>(a, xs, W1, 2 * H, n0);
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -533,7 +521,7 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
     lds_sync();
     zero_acc(x);
-    if constexpr (FN) {
+    if constexpr (FM) {
       wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)zs, [&](int k, int nb) {
         return *(const bf16x8*)(W2s + (n0 + 16 * nb + li) * LDW2 + k + 8 * lg);
       });
@@ -551,7 +539,7 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
     float inv[MB][4];
     ln_normalize<MB, NB, MT, H>(x, red, eps, inv);
     f32_rows_to_lds<H, D::LDF, MT>(ft, nr, [&](int i, int q) { return *(const float4*)(dh_in + (size_t)(row0 + i) * H + 4 * q); });
-    if constexpr (!FN) lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z + (size_t)row0 * H, H, [](int i) { return i; });
+    if constexpr (!FM) lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z + (size_t)row0 * H, H, [](int i) { return i; });
     lds_sync();
     f32x4 g[MB][NB];
 #pragma unroll
@@ -562,14 +550,14 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
         for (int r = 0; r < 4; ++r) g[mb][nb][r] = ft[acc_row(mb, r) * D::LDF + acc_col(n0, nb)];
     ln_backward<MB, NB, MT, H>(x, g, inv, w.gamma, n0, red, cg, cbt);
     col_accumulate(g, cb2);
-    if constexpr (FN) {
+    if constexpr (FM) {
       wave_wgrad<MB, NB, H, D::LDH>(accW2, g, (const bf16*)zs);  // dW2 += du^T z
       lds_sync();  // every wave is done reading z before du replaces it
     }
     acc_to_lds<T, MB, NB, D::LDH>(g, zs, n0);
     lds_sync();
     zero_acc(x);
-    if constexpr (FN) {
+    if constexpr (FM) {
       wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)zs, [&](int k, int nb) {
         return lds_bfrag_tr(W2s, LDW2, k + 8 * lg, n0 + 16 * nb, 4);
       });
@@ -584,28 +572,15 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
 #pragma unroll
         for (int r = 0; r < 4; ++r) x[mb][nb][r] *= act_d<ACT>(a[mb][nb][r]);
     col_accumulate(x, cb1);
-    if constexpr (FN) {
-      wave_wgrad<MB, NB, H, D::LD2>(accW1h, x, (const bf16*)xs);      // dW1[:, 0:H] += da^T h
-      wave_wgrad<MB, NB, H, D::LD2>(accW1m, x, (const bf16*)xs + H);  // dW1[:, H:2H] += da^T m
-    }
     lds_sync();
     acc_to_lds<T, MB, NB, D::LDH>(x, zs, n0);
     lds_sync();
-    if constexpr (!FN)
-      lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.da + (size_t)row0 * H, H, [](int i) { return i; });
+    // da for the dW1 products
+    lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.da + (size_t)row0 * H, H, [](int i) { return i; });
     zero_acc(g);
     zero_acc(x);
-    if constexpr (FN) {
-      wave_gemm_lds<MB, NB, H, D::LDH>(g, (const bf16*)zs, [&](int k, int nb) {  // -> dh part
-        return lds_bfrag_tr(W1s, LDW1, k + 8 * lg, n0 + 16 * nb, 4);
-      });
-      wave_gemm_lds<MB, NB, H, D::LDH>(x, (const bf16*)zs, [&](int k, int nb) {  // -> dm
-        return lds_bfrag_tr(W1s, LDW1, k + 8 * lg, H + n0 + 16 * nb, 4);
-      });
-    } else {
-      wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1T, H, n0);                  // -> dh part
-      wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W1T + (size_t)H * H, H, n0);  // -> dm
-    }
+    wave_gemm<T, MB, NB, H, D::LDH>(g, zs, W1T, H, n0);                  // -> dh part
+    wave_gemm<T, MB, NB, H, D::LDH>(x, zs, W1T + (size_t)H * H, H, n0);  // -> dm
     acc_to_ldsf<MB, NB, D::LDF>(g, ft, n0);
     lds_sync();
     f32_tile<MT, H, NTHR>(
@@ -631,19 +606,14 @@ __global__ __launch_bounds__(NTHR, (sizeof(T) == 2 && H == 128) ? 1 : (MT == 32 
   write_partial<NB>(p + H, n0, cb2);
   write_partial<NB>(p + 2 * H, n0, cg);
   write_partial<NB>(p + 3 * H, n0, cbt);
-  if constexpr (FN) {
-    float* q2 = o.wpart + (size_t)blockIdx.x * 3 * H * H;
+  if constexpr (FM) {
+    float* q2 = o.wpart + (size_t)blockIdx.x * H * H;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int jb = 0; jb < H / 16; ++jb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int at = (n0 + nb * 16 + lg * 4 + r) * H + jb * 16 + li;
-          q2[at] = accW2[nb][jb][r];
-          q2[H * H + at] = accW1h[nb][jb][r];
-          q2[2 * H * H + at] = accW1m[nb][jb][r];
-        }
+        for (int r = 0; r < 4; ++r) q2[(n0 + nb * 16 + lg * 4 + r) * H + jb * 16 + li] = accW2[nb][jb][r];
   }
 }
 
