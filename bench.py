@@ -98,7 +98,9 @@ def kernel_bytes(name: str, n: int, E: int, H: int, s: int, fused: int = 0, de_i
     if name == "node_fwd":
         return n * (2 * H * s + 4 * H)
     if name == "node_bwd":
-        return n * (H * s + 4 * H + 4 * H + 3 * H * s + 12 * H)
+        # h, m (FP32), dh' (FP32) read; dh_mid, dm (FP32) and da written (z and
+        # du too where dW2 is not fused: BF16 at H = 128 fuses it)
+        return n * (2 * H * s + 16 * H + (0 if (s == 2 and H == 128) else 2 * H * s))
     return None
 
 
@@ -116,7 +118,7 @@ def kernel_flops(name: str, n: int, E: int, H: int, fused: int = 0, ztape: bool 
     if name == "node_fwd":
         return n * 6.0 * H * H
     if name == "node_bwd":
-        return n * 12.0 * H * H
+        return n * (14.0 if H == 128 else 12.0) * H * H
     return None
 
 
