@@ -170,6 +170,45 @@ __device__ __forceinline__ void wave_gemm(f32x4 (&acc)[MB][NB], const T* A,
   wave_gemm<T, MB, NB, K, LDA>(acc, A, f);
 }
 
+// The same product with A's rows taken through an indirection: this lane's
+// row of 16-row block mb starts at A + roff[mb] (an LDS offset in elements,
+// the lane's own row, lane % 16, of that block).
+template <typename T, int MB, int NB, int K>
+__device__ __forceinline__ void wave_gemm_rows(f32x4 (&acc)[MB][NB], const T* A, const int (&roff)[MB],
+                                               const WFrag<T, NB, K>& f) {
+  using V = typename TT<T>::V;
+  constexpr int KC = WFrag<T, NB, K>::KC, E = WFrag<T, NB, K>::E;
+  const int lg = lane_id() >> 4;
+  if constexpr (WFrag<T, NB, K>::PRE) {
+#pragma unroll
+    for (int kk = 0; kk < K / KC; kk += 2) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k2 = kk; k2 < kk + 2 && k2 < K / KC; ++k2)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          V a = *(const V*)(A + roff[mb] + lg * E + k2 * KC);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mma(a, f.b[k2][nb], acc[mb][nb]);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  } else {
+#pragma unroll 4
+    for (int k = 0; k < K; k += KC) {
+      V b[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) b[nb] = *(const V*)(f.wrow[nb] + k);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        V a = *(const V*)(A + roff[mb] + lg * E + k);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mma(a, b[nb], acc[mb][nb]);
+      }
+    }
+  }
+}
+
 // Transposing LDS read (ds_read_b64_tr_b16, gfx950).  In each group of 16
 // lanes, lane L reads four 16-bit values at its own address, and lane 4a + b
 // receives value b of lanes a, a + 4, a + 8 and a + 12.  So if lane L points

@@ -29,6 +29,10 @@ struct Dims {
 // ascending sender order (the CSR order) -- deterministic, no atomics.
 // ---------------------------------------------------------------------------
 // NW waves per workgroup; each wave owns H / NW output columns of every GEMM.
+// Gathered form: [h_s ; e] per edge (stride LD2) and h_r once per receiver
+// of the tile (the tile's receivers are consecutive rows of h; MT rows at
+// most), the first product reading each edge's h_r row through its
+// receiver's tile-local index.
 // SPLIT: the first layer's node blocks come precomputed per node (see
 // k_node_proj), so only the e rows are gathered.  The FP32 tile of the
 // segment sums aliases the staging tile; where it would be the larger (the
@@ -36,7 +40,8 @@ struct Dims {
 template <typename T, int H, int MT, int NW, int SPLIT = 0>
 struct EdgeFwdLds {
   using D = Dims<T, H, NW>;
-  static constexpr size_t GS = (size_t)MT * (SPLIT ? D::LDH : D::LD3) * sizeof(T);
+  static constexpr size_t ES = (size_t)MT * (SPLIT ? D::LDH : D::LD2) * sizeof(T);  // per-edge rows
+  static constexpr size_t GS = ES + (SPLIT ? 0 : (size_t)MT * D::LDH * sizeof(T));  // + receiver rows
   static constexpr int NH = (size_t)MT * D::LDF * 4 > GS ? 2 : 1;
   static constexpr int LDFH = H / NH + 4;
   static constexpr size_t FS = (size_t)MT * LDFH * 4;
@@ -58,8 +63,8 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW, SP
     const float* __restrict__ ps, float eps) {
   using D = Dims<T, H, NW>;
   using L = EdgeFwdLds<T, H, MT, NW, SPLIT>;
-  constexpr int LDX = SPLIT ? D::LDH : D::LD3;  // staging row stride
-  constexpr int EC = SPLIT ? 0 : 2 * H;          // column of e in a staged row
+  constexpr int LDX = SPLIT ? D::LDH : D::LD2;  // staging row stride
+  constexpr int EC = SPLIT ? 0 : H;              // column of e in a staged row
   constexpr int MB = MT / 16, NB = D::NB;
   constexpr size_t XS = L::XS, ZS = L::ZS;
   constexpr int NH = L::NH, HH = H / NH, LDFH = L::LDFH;
@@ -67,6 +72,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW, SP
   static_assert(SPLIT || NH == 1, "the gathered tile holds the whole FP32 tile");
   __shared__ __align__(16) unsigned char smem[L::bytes];
   T* xs = (T*)smem;
+  T* hr = (T*)(smem + L::ES);  // gathered form: h_r of the tile's receivers
   float* ft = (float*)smem;  // aliases xs once the gathered tile is dead
   T* zs = (T*)(smem + XS);
   float* red = (float*)(smem + XS + ZS);
@@ -117,14 +123,40 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW, SP
           for (int r = 0; r < 4; ++r) acc[mb][nb][r] += sv[mb][nb][r];
       wave_gemm<T, MB, NB, H, D::LDH>(acc, xs, W1 + 2 * H, 3 * H, n0);  // + W1_e e
     } else {
-      gather_tile<T, D::LD3, MT, 3, H, 64 * NW>(
-          xs, ne,
-          [&](int p, int i) { return p == 0 ? h + (size_t)rs[i] * H : p == 1 ? h + (size_t)ss[i] * H : e + (size_t)(e0 + i) * H; },
-          [](int, int, int, const uint4&) {});
+      // one batch of loads: h_r of the nr receivers (consecutive rows of h),
+      // then h_s and e of the ne edges
+      const int nr = r1 - r0;
+      constexpr int E8 = 16 / sizeof(T), CPR = H / E8, TOT = 3 * MT * CPR, IT = TOT / (64 * NW);
+      static_assert(TOT % (64 * NW) == 0, "whole steps of the workgroup");
+      uint4 v[IT];
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        const int c = (int)threadIdx.x + k * 64 * NW, p = c / (MT * CPR), rem = c - p * (MT * CPR);
+        const int i = rem / CPR, q = rem - i * CPR;
+        const T* src = p == 0 ? h + (size_t)(r0 + i) * H : p == 1 ? h + (size_t)ss[i] * H : e + (size_t)(e0 + i) * H;
+        v[k] = uint4{0u, 0u, 0u, 0u};
+        if (i < (p == 0 ? nr : ne)) v[k] = *(const uint4*)(src + q * E8);
+      }
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        const int c = (int)threadIdx.x + k * 64 * NW, p = c / (MT * CPR), rem = c - p * (MT * CPR);
+        const int i = rem / CPR, q = rem - i * CPR;
+        *(uint4*)(p == 0 ? hr + i * D::LDH + q * E8 : xs + i * D::LD2 + (p - 1) * H + q * E8) = v[k];
+      }
       ip.advance(b, sch, t);  // next tile's indices and the bounds after, in flight from here
+      // each lane's h_r row (its row of every 16-row block): the receiver's tile-local index
+      int roff[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int row = mb * 16 + (lane_id() & 15);
+        roff[mb] = (row < ne ? rs[row] - r0 : 0) * D::LDH;
+      }
+      WFrag<T, NB, H> fr;
+      fr.load(W1, 3 * H, n0);
       lds_sync();
       zero_acc(acc);
-      wave_gemm<T, MB, NB, 3 * H, D::LD3>(acc, xs, W1, 3 * H, n0);
+      wave_gemm_rows<T, MB, NB, H>(acc, hr, roff, fr);                // W1_r h_r
+      wave_gemm<T, MB, NB, 2 * H, D::LD2>(acc, xs, W1 + H, 3 * H, n0);  // + W1_s h_s + W1_e e
     }
     f32x4 ev[MB][NB];
 #pragma unroll
