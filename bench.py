@@ -426,7 +426,7 @@ def main():
 
         tuned = None
         if H == 512 and not args.no_autotune:
-            log("[bench] H = 512: fixed tiles (32-row edge, 16-row node), no autotuning")
+            log("[bench] H = 512: default tiles (64-row wide edge forward, 32-row edge adjoint, 16-row node), no autotuning")
         elif not args.no_autotune and not (args.edge_rows or args.node_rows or args.grid or args.edge_waves
                                            or args.adjoint_edge_rows or args.adjoint_edge_waves):
             ctx.set_tiles(0, 0, 0, 0)

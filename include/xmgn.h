@@ -103,14 +103,19 @@ xmgn_status xmgn_param_offset(const xmgn_model_desc* desc, int32_t block, int32_
 xmgn_status xmgn_ctx_create(int32_t device, xmgn_ctx** out);
 void xmgn_ctx_destroy(xmgn_ctx* ctx);
 
-/* Tile configuration of the processor kernels: rows per tile of the edge and
- * node kernels (32 or 64), the persistent grid size in workgroups (a
- * multiple of 8) and the waves per workgroup of the edge kernels (4 or 8);
- * 0 selects the library default for any of them (64, 64, 1024, 4; 8 edge
- * waves at H = 512).  LDS fixes the rows at H = 256 (32-row node tiles;
- * 32-row edge tiles unless 64 are asked for in the BF16 form) and at
- * H = 512 (32-row edge tiles, 16-row node tiles) whatever is asked.
- * Changing it invalidates cached batch plans. */
+/* Tile configuration of the processor kernels: rows per tile of the edge
+ * kernels (32, 64 or 128) and node kernels (32 or 64), the persistent grid
+ * size in workgroups (a multiple of 8) and the waves per workgroup of the
+ * edge kernels (4 or 8); 0 selects the library default for any of them (64,
+ * 64, 1024, 4; at H = 512 8 edge waves and, in the BF16 gathered forward,
+ * the wide kernel's 64-row tiles).  LDS fixes the rows at H = 128
+ * (at most 64-row edge tiles), at H = 256 (32-row node tiles; 32-row edge
+ * tiles unless, in the BF16 form, 64 are asked for, or 128 for the gathered
+ * edge forward's wide kernel, 8 waves, whose edge adjoint then runs 64-row
+ * tiles unless set otherwise) and at H = 512 (16-row node tiles; 32-row edge
+ * tiles unless 64 are asked for the BF16 gathered forward's wide kernel,
+ * whose adjoint stays on 32) whatever is asked.  Changing it invalidates
+ * cached batch plans. */
 xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int32_t node_rows,
                                int32_t grid, int32_t edge_waves);
 

@@ -619,16 +619,19 @@ static Shape make_shape(const xmgn_ctx* c, const xmgn_model_desc* d) {
   s.act = d->activation;
   s.agg = d->aggregate;
   s.eps = d->ln_eps;
-  int me = c->mt_edge > 0 ? c->mt_edge : 64, mn = c->mt_node > 0 ? c->mt_node : 64;
-  // LDS budget: H = 256 runs 32-row node tiles and 32-row edge tiles, or
-  // 64-row edge tiles in the BF16 form when asked for; H = 512 32-row edge
-  // tiles (a tile holds whole receiver segments) and 16-row node tiles
+  int me = c->mt_edge > 0 ? std::min(c->mt_edge, 64) : 64, mn = c->mt_node > 0 ? c->mt_node : 64;
+  // LDS budget: H = 256 runs 32-row node tiles and 32-row edge tiles, or in
+  // the BF16 form 64-row edge tiles, or 128-row ones in the wide gathered
+  // forward (not in the split form); H = 512 16-row node tiles and 32-row
+  // edge tiles (a tile holds whole receiver segments), or 64-row ones in the
+  // wide gathered forward.  The edge adjoint stays on 32 or 64 rows.
+  const bool wide = d->precision == 1 && !c->edge_split;
   if (d->hidden == 256) {
-    me = (d->precision == 1 && c->mt_edge == 64) ? 64 : 32;
+    me = (d->precision == 1 && c->mt_edge == 64) || (wide && c->mt_edge == 128) ? c->mt_edge : 32;
     mn = 32;
   }
-  if (d->hidden == 512) {
-    me = 32;
+  if (d->hidden == 512) {  // the wide gathered forward by default (1.8x the 32-row kernel on C6)
+    me = (wide && (c->mt_edge == 64 || c->mt_edge == 0)) ? 64 : 32;
     mn = 16;
   }
   s.mt_edge = me;
@@ -637,7 +640,7 @@ static Shape make_shape(const xmgn_ctx* c, const xmgn_model_desc* d) {
   // 256: 32 or 64 rows, independent of the forward)
   s.mt_edge_bwd = ((d->hidden == 128 || d->hidden == 256) && d->precision == 1 && c->mt_edge_bwd > 0)
                       ? c->mt_edge_bwd
-                      : me;
+                      : d->hidden == 512 ? 32 : std::min(me, 64);
   s.grid = c->grid > 0 ? c->grid : 1024;
   s.nw_edge = c->nw_edge > 0 ? c->nw_edge : d->hidden == 512 ? 8 : 4;  // H = 512: fewer spills at 8 waves
   s.nw_edge_bwd = c->nw_edge_bwd > 0 ? c->nw_edge_bwd : s.nw_edge;
@@ -713,7 +716,8 @@ extern "C" xmgn_status xmgn_ctx_set_tiles(xmgn_ctx* ctx, int32_t edge_rows, int3
                                           int32_t edge_waves) {
   if (!ctx) return fail(XMGN_ERR_INVALID, "ctx is NULL");
   if (edge_waves != 0 && edge_waves != 4 && edge_waves != 8) return fail(XMGN_ERR_INVALID, "edge_waves must be 0, 4 or 8");
-  if (edge_rows != 0 && edge_rows != 32 && edge_rows != 64) return fail(XMGN_ERR_INVALID, "edge_rows must be 0, 32 or 64");
+  if (edge_rows != 0 && edge_rows != 32 && edge_rows != 64 && edge_rows != 128)
+    return fail(XMGN_ERR_INVALID, "edge_rows must be 0, 32, 64 or 128");
   if (node_rows != 0 && node_rows != 32 && node_rows != 64) return fail(XMGN_ERR_INVALID, "node_rows must be 0, 32 or 64");
   if (grid < 0 || (grid > 0 && (grid < 8 || grid % 8 != 0 || grid > 65536)))
     return fail(XMGN_ERR_INVALID, "grid must be 0 or a multiple of 8 in [8, 65536]");
@@ -1698,9 +1702,9 @@ extern "C" xmgn_status xmgn_autotune(xmgn_ctx* c, const xmgn_model_desc* d, cons
       }
       return XMGN_OK;
     };
-    const std::vector<int> rows = d->hidden == 128 || (d->hidden == 256 && d->precision == 1)
-                                      ? std::vector<int>{32, 64}
-                                      : std::vector<int>{32};
+    std::vector<int> rows = d->hidden == 128 || (d->hidden == 256 && d->precision == 1) ? std::vector<int>{32, 64}
+                                                                                         : std::vector<int>{32};
+    if (d->hidden == 256 && d->precision == 1 && !c->edge_split) rows.push_back(128);  // the wide forward
     // stage 1: edge kernels (the bulk of the step), stage 2: node tiles
     for (int er : rows)
       for (int wv : {4, 8})

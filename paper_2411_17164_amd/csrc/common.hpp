@@ -130,13 +130,15 @@ __device__ __forceinline__ void wave_gemm(f32x4 (&acc)[MB][NB], const T* A, cons
   const int l = lane_id(), li = l & 15, lg = l >> 4;
   const T* arow = A + li * LDA + lg * E;
   if constexpr (WFrag<T, NB, K>::PRE) {
-    // A fragments (LDS) are read at most two k steps ahead of their MFMAs:
-    // hoisting all of them would cost K / KC x MB x 4 registers
+    // A fragments (LDS) are read at most two k steps ahead of their MFMAs
+    // (one for tall tiles): hoisting all of them would cost K / KC x MB x 4
+    // registers
+    constexpr int G = MB >= 8 ? 1 : 2;
 #pragma unroll
-    for (int kk = 0; kk < K / KC; kk += 2) {
+    for (int kk = 0; kk < K / KC; kk += G) {
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int k2 = kk; k2 < kk + 2 && k2 < K / KC; ++k2)
+      for (int k2 = kk; k2 < kk + G && k2 < K / KC; ++k2)
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
           V a = *(const V*)(arow + mb * 16 * LDA + k2 * KC);

@@ -249,6 +249,197 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW, SP
 }
 
 // ---------------------------------------------------------------------------
+// Wide edge forward (BF16; H = 256 on 128-row tiles, H = 512 on 64-row
+// tiles): the gathered form's MLP on tiles twice as tall as a whole
+// [h_r ; h_s ; e] tile could be at these widths.  The first product runs
+// over K slices of 64 columns of the gathered rows, double-buffered in LDS:
+// the next slice's rows and weight fragments are in flight while the current
+// slice's MFMAs run, and each weight element streamed from L2 serves twice
+// as many edges as on the shorter tiles.  After the second product e is
+// staged in the z tile's place; the FP32 segment-sum tile then takes that
+// place, one half of the columns at a time.
+// ---------------------------------------------------------------------------
+template <int H, int MT>
+struct EdgeFwdWide {
+  static constexpr int NW = 8, NT = 64 * NW;
+  static constexpr int KS = 64, LDK = KS + 8;         // slice width, slice row stride
+  static constexpr int NS = 3 * H / KS;               // slices of [h_r ; h_s ; e]
+  static constexpr int LDH = H + 8;
+  static constexpr size_t SL = (size_t)MT * LDK * 2;  // one slice buffer
+  static constexpr size_t ZS = (size_t)MT * LDH * 2;  // z, then e and e', then the FP32 tile
+  static constexpr int FC = H / 2, LDF = FC + 4;      // FP32 tile: half of the columns
+  static_assert((size_t)MT * LDF * 4 <= ZS, "FP32 half tile fits in the z tile");
+  static constexpr size_t bytes = 2 * SL + ZS + 2 * NW * MT * 4 + 2 * MT * 4;
+};
+
+template <int H, int MT, int ACT, int AGG>
+__global__ __launch_bounds__(512, 2) void k_edge_fwd_wide(BatchView b, MlpW w, const bf16* __restrict__ h,
+                                                         const bf16* __restrict__ e, bf16* __restrict__ e_out,
+                                                         float* __restrict__ m, bf16* __restrict__ z_out,
+                                                         bf16* __restrict__ a_out, float eps) {
+  using L = EdgeFwdWide<H, MT>;
+  constexpr int NW = L::NW, NT = L::NT, KS = L::KS, LDK = L::LDK, NS = L::NS, LDH = L::LDH;
+  constexpr int FC = L::FC, LDF = L::LDF;
+  constexpr int CPW = H / NW, NB = CPW / 16, MB = MT / 16;
+  static_assert(NS % 2 == 0, "slices go in pairs");
+  static_assert(CPW <= FC, "a wave's columns lie in one half");
+  constexpr int CPRS = KS / 8, SLT = MT * CPRS, SIT = SLT / NT;  // 16-byte chunks of a slice
+  static_assert(SLT % NT == 0, "whole steps of the workgroup");
+  __shared__ __align__(16) unsigned char smem[L::bytes];
+  bf16* sl0 = (bf16*)smem;
+  bf16* sl1 = (bf16*)(smem + L::SL);
+  bf16* zs = (bf16*)(smem + 2 * L::SL);
+  float* ft = (float*)zs;
+  float* red = (float*)(smem + 2 * L::SL + L::ZS);
+  int* rs = (int*)(red + 2 * NW * MT);
+  int* ss = rs + MT;
+  const bf16* W1 = (const bf16*)w.W1;
+  const bf16* W2 = (const bf16*)w.W2;
+  const int n0 = wave_id() * CPW;
+
+  TileSched sch(b.n_etiles);
+  EdgeTilePipe ip;
+  ip.start(b, sch);
+  for (int t = sch.begin; t < sch.end; t += sch.step) {
+    const EdgeTileIdx cur = ip.nx;
+    const int r0 = cur.r0, r1 = cur.r1, e0 = cur.e0, ne = cur.ne;
+    if (threadIdx.x < MT) {
+      rs[threadIdx.x] = cur.rv;
+      ss[threadIdx.x] = cur.cv;
+    }
+    lds_sync();
+    uint4 v[SIT];
+    auto load_slice = [&](int sl) {
+      const int p = sl / (H / KS), c0 = (sl % (H / KS)) * KS;
+#pragma unroll
+      for (int k = 0; k < SIT; ++k) {
+        const int c = (int)threadIdx.x + k * NT, i = c / CPRS, q = c - i * CPRS;
+        v[k] = uint4{0u, 0u, 0u, 0u};
+        if (i < ne) {
+          const bf16* row = p == 0 ? h + (size_t)rs[i] * H : p == 1 ? h + (size_t)ss[i] * H : e + (size_t)(e0 + i) * H;
+          v[k] = *(const uint4*)(row + c0 + q * 8);
+        }
+      }
+    };
+    auto store_slice = [&](bf16* buf) {
+#pragma unroll
+      for (int k = 0; k < SIT; ++k) {
+        const int c = (int)threadIdx.x + k * NT, i = c / CPRS, q = c - i * CPRS;
+        *(uint4*)(buf + i * LDK + q * 8) = v[k];
+      }
+    };
+    f32x4 acc[MB][NB];
+    zero_acc(acc);
+    WFrag<bf16, NB, KS> fa, fb;
+    load_slice(0);
+    fa.load(W1, 3 * H, n0);
+    store_slice(sl0);
+    ip.advance(b, sch, t);  // next tile's indices and the bounds after, in flight from here
+#pragma unroll 1
+    for (int sl = 0; sl < NS; sl += 2) {
+      // slice sl from sl0 with fa; slice sl + 1 and its weights in flight
+      load_slice(sl + 1);
+      fb.load(W1 + (sl + 1) * KS, 3 * H, n0);
+      lds_sync();  // slice sl stored by every wave; slice sl - 1's products done with sl1
+      wave_gemm<bf16, MB, NB, KS, LDK>(acc, sl0, fa);
+      store_slice(sl1);
+      // slice sl + 1 from sl1 with fb
+      if (sl + 2 < NS) {
+        load_slice(sl + 2);
+        fa.load(W1 + (sl + 2) * KS, 3 * H, n0);
+      }
+      lds_sync();
+      wave_gemm<bf16, MB, NB, KS, LDK>(acc, sl1, fb);
+      if (sl + 2 < NS) store_slice(sl0);
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b1[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mb][nb][r] += bb;
+      }
+    if (a_out) {  // uniform: the pre-activation goes out through zs first
+      acc_to_lds<bf16, MB, NB, LDH>(acc, zs, n0);
+      lds_sync();
+      lds_rows_to_global<bf16, LDH>(zs, ne, H, a_out + (size_t)e0 * H, H, [](int i) { return i; });
+      lds_sync();
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mb][nb][r] = act_f<ACT>(acc[mb][nb][r]);
+    acc_to_lds<bf16, MB, NB, LDH>(acc, zs, n0);
+    lds_sync();
+    if (z_out) lds_rows_to_global<bf16, LDH>(zs, ne, H, z_out + (size_t)e0 * H, H, [](int i) { return i; });
+    zero_acc(acc);
+    wave_gemm<bf16, MB, NB, H, LDH>(acc, zs, W2, H, n0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bb = w.b2[acc_col(n0, nb)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mb][nb][r] += bb;
+      }
+    float inv[MB][4];
+    ln_normalize<MB, NB, MT, H, NW>(acc, red, eps, inv);  // barriers: every wave is done with z
+    // e of the tile's edges, in the z tile's place
+    gather_tile<bf16, LDH, MT, 1, H, NT>(
+        zs, ne, [&](int, int i) { return e + (size_t)(e0 + i) * H; }, [](int, int, int, const uint4&) {});
+    lds_sync();
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int c = acc_col(n0, nb);
+        const float g = w.gamma[c], be = w.beta[c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = acc_row(mb, r);
+          const float vv = g * acc[mb][nb][r] + be;
+          const float en = to_f(zs[row * LDH + c]) + vv;
+          acc[mb][nb][r] = AGG ? en : vv;  // the summand of m
+          zs[row * LDH + c] = from_f<bf16>(en);
+        }
+      }
+    lds_sync();
+    if (e_out) lds_rows_to_global<bf16, LDH>(zs, ne, H, e_out + (size_t)e0 * H, H, [](int i) { return i; });
+    lds_sync();  // e' is out: the FP32 tile takes its place
+    // m_r: sequential sum over the receiver's edges (ascending sender id), one column half at a time
+    const int nr = r1 - r0;
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+      if (n0 / FC == hf)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ft[acc_row(mb, r) * LDF + acc_col(n0, nb) - hf * FC] = acc[mb][nb][r];
+      lds_sync();
+      for (int task = threadIdx.x; task < nr * (FC / 4); task += NT) {
+        const int rl = task / (FC / 4), q = task - rl * (FC / 4);
+        const int lo = b.row_ptr[r0 + rl] - e0, hi = b.row_ptr[r0 + rl + 1] - e0;
+        float4 sm = {0.f, 0.f, 0.f, 0.f};
+        for (int i = lo; i < hi; ++i) {
+          const float4 x = *(const float4*)(ft + i * LDF + 4 * q);
+          sm.x += x.x;
+          sm.y += x.y;
+          sm.z += x.z;
+          sm.w += x.w;
+        }
+        *(float4*)(m + (size_t)(r0 + rl) * H + hf * FC + 4 * q) = sm;
+      }
+      lds_sync();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Node projections of the edge MLP's first layer (Eq. 1 re-associated): the
 // blocks of W1 that act on the receiver's and the sender's latent give
 //   pr = W1_r h + b1,  ps = W1_s h   (FP32, [n][H] each)
@@ -663,10 +854,39 @@ static void edge_fwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const
   }))));
 }
 
+bool edge_fwd_wide(const Shape& s) {
+  return s.prec == 1 && ((s.H == 256 && s.mt_edge == 128) || (s.H == 512 && s.mt_edge == 64));
+}
+
 void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
                      void* e_out, float* m, void* z_out, void* a_out, const float* pr, const float* ps,
                      hipStream_t st) {
   if (b.n_etiles == 0) return;
+  if (edge_fwd_wide(s)) {
+    if (pr) {  // the split form has no wide tiles
+      g_config_error = 1;
+      return;
+    }
+    auto go = [&](auto hh, auto mt, auto act, auto agg) {
+      k_edge_fwd_wide<decltype(hh)::value, decltype(mt)::value, decltype(act)::value, decltype(agg)::value>
+          <<<s.grid, 512, 0, st>>>(b, w, (const bf16*)h, (const bf16*)e, (bf16*)e_out, m, (bf16*)z_out,
+                                   (bf16*)a_out, s.eps);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    auto by_h = [&](auto act, auto agg) {
+      if (s.H == 256)
+        go(std::integral_constant<int, 256>{}, std::integral_constant<int, 128>{}, act, agg);
+      else
+        go(std::integral_constant<int, 512>{}, std::integral_constant<int, 64>{}, act, agg);
+    };
+    if (s.act) {
+      if (s.agg) by_h(I1{}, I1{}); else by_h(I1{}, I0{});
+    } else {
+      if (s.agg) by_h(I0{}, I1{}); else by_h(I0{}, I0{});
+    }
+    return;
+  }
   if (s.nw_edge == 8)
     edge_fwd_nw<8>(s, b, w, h, e, e_out, m, z_out, a_out, pr, ps, st);
   else

@@ -466,3 +466,24 @@ def test_edge_split_partitions_and_fallback(api):
     torch.cuda.synchronize()
     assert (out.cpu().numpy() == y_full).all()
     assert not (y_full == y_ref).all()  # the split form did run: another rounding order
+
+
+@pytest.mark.parametrize("cfg,rows,act,agg", [(5, 128, "relu", "message"), (5, 128, "silu", "edge"),
+                                              (6, 64, "silu", "message"), (6, 64, "relu", "edge")])
+def test_edge_wide_forward(api, cfg, rows, act, agg):
+    """The wide gathered edge forward (BF16: 128-row tiles at H = 256, 64-row
+    tiles at H = 512, the first product over K slices of the gathered rows)
+    against the FP64 oracle; the adjoint runs its own 64- or 32-row tiles."""
+    c = api.Context(0)
+    c.set_tiles(rows, 0, 512, 8)
+    levels = (400, 1600, 5000) if cfg == 5 else (200, 800, 2500)
+    case = Case(cfg, levels=levels, layers=3, precision="bf16", activation=act, aggregate=agg)
+    assert case.H == (256 if cfg == 5 else 512)
+    g = gpu_graph(api, c, case)
+    ps = api.Partset.halo(g, case.inp.pos, None, case.L)
+    out, loss, grad = gpu_step(api, c, case, ps, [0])
+    log(f"  wide forward H={case.H} rows {rows} {act} {agg}: " + check_step(case, out, loss, grad, oracle_refs(case)))
+    # the same step on the default tiles: outputs agree to BF16 rounding
+    d = api.Context(0)
+    out_d, _, _ = gpu_step(api, d, case, api.Partset.halo(gpu_graph(api, d, case), case.inp.pos, None, case.L), [0])
+    assert rel_l2(out, out_d) <= 2e-2
