@@ -249,19 +249,21 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW, SP
 }
 
 // ---------------------------------------------------------------------------
-// Wide edge forward (BF16; H = 256 on 128-row tiles, H = 512 on 64-row
-// tiles): the gathered form's MLP on tiles twice as tall as a whole
-// [h_r ; h_s ; e] tile could be at these widths.  The first product runs
-// over K slices of 64 columns of the gathered rows, double-buffered in LDS:
-// the next slice's rows and weight fragments are in flight while the current
-// slice's MFMAs run, and each weight element streamed from L2 serves twice
-// as many edges as on the shorter tiles.  After the second product e is
-// staged in the z tile's place; the FP32 segment-sum tile then takes that
-// place, one half of the columns at a time.
+// Wide edge forward (BF16 gathered form at H = 256 and 512): the same MLP as
+// k_edge_fwd's gathered form, with the first product over K slices of 64
+// columns of the gathered [h_r ; h_s ; e] rows, double-buffered in LDS: the
+// next slice's rows and weight fragments are in flight while the current
+// slice's MFMAs run.  Only a slice of the gathered tile is ever in LDS, so
+// tiles can be taller than a whole gathered tile allows (64 rows at
+// H = 512, where each weight element streamed from L2 then serves twice as
+// many edges; 128 at H = 256), or, at the same height (64 rows, 4 waves, at
+// H = 256), small enough for two workgroups per CU.  After the second
+// product e is staged in the z tile's place; the FP32 segment-sum tile then
+// takes that place, one half of the columns at a time.
 // ---------------------------------------------------------------------------
-template <int H, int MT>
+template <int H, int MT, int NW_ = 8>
 struct EdgeFwdWide {
-  static constexpr int NW = 8, NT = 64 * NW;
+  static constexpr int NW = NW_, NT = 64 * NW;
   static constexpr int KS = 64, LDK = KS + 8;         // slice width, slice row stride
   static constexpr int NS = 3 * H / KS;               // slices of [h_r ; h_s ; e]
   static constexpr int LDH = H + 8;
@@ -272,12 +274,13 @@ struct EdgeFwdWide {
   static constexpr size_t bytes = 2 * SL + ZS + 2 * NW * MT * 4 + 2 * MT * 4;
 };
 
-template <int H, int MT, int ACT, int AGG>
-__global__ __launch_bounds__(512, 2) void k_edge_fwd_wide(BatchView b, MlpW w, const bf16* __restrict__ h,
+template <int H, int MT, int ACT, int AGG, int NWW>
+__global__ __launch_bounds__(64 * NWW, (waves_per_simd(EdgeFwdWide<H, MT, NWW>::bytes, NWW))) void k_edge_fwd_wide(
+    BatchView b, MlpW w, const bf16* __restrict__ h,
                                                          const bf16* __restrict__ e, bf16* __restrict__ e_out,
                                                          float* __restrict__ m, bf16* __restrict__ z_out,
                                                          bf16* __restrict__ a_out, float eps) {
-  using L = EdgeFwdWide<H, MT>;
+  using L = EdgeFwdWide<H, MT, NWW>;
   constexpr int NW = L::NW, NT = L::NT, KS = L::KS, LDK = L::LDK, NS = L::NS, LDH = L::LDH;
   constexpr int FC = L::FC, LDF = L::LDF;
   constexpr int CPW = H / NW, NB = CPW / 16, MB = MT / 16;
@@ -854,8 +857,10 @@ static void edge_fwd_nw(const Shape& s, const BatchView& b, const MlpW& w, const
   }))));
 }
 
+// The BF16 gathered form at H = 256 (64- and 128-row tiles) and at H = 512
+// (64-row tiles) runs the wide kernel.
 bool edge_fwd_wide(const Shape& s) {
-  return s.prec == 1 && ((s.H == 256 && s.mt_edge == 128) || (s.H == 512 && s.mt_edge == 64));
+  return s.prec == 1 && ((s.H == 256 && (s.mt_edge == 128 || s.mt_edge == 64)) || (s.H == 512 && s.mt_edge == 64));
 }
 
 void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const void* h, const void* e,
@@ -868,15 +873,18 @@ void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const vo
       return;
     }
     auto go = [&](auto hh, auto mt, auto act, auto agg) {
-      k_edge_fwd_wide<decltype(hh)::value, decltype(mt)::value, decltype(act)::value, decltype(agg)::value>
-          <<<s.grid, 512, 0, st>>>(b, w, (const bf16*)h, (const bf16*)e, (bf16*)e_out, m, (bf16*)z_out,
-                                   (bf16*)a_out, s.eps);
+      constexpr int NWW = decltype(hh)::value == 256 && decltype(mt)::value == 64 ? 4 : 8;
+      k_edge_fwd_wide<decltype(hh)::value, decltype(mt)::value, decltype(act)::value, decltype(agg)::value, NWW>
+          <<<s.grid, 64 * NWW, 0, st>>>(b, w, (const bf16*)h, (const bf16*)e, (bf16*)e_out, m, (bf16*)z_out,
+                                        (bf16*)a_out, s.eps);
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
     auto by_h = [&](auto act, auto agg) {
-      if (s.H == 256)
+      if (s.H == 256 && s.mt_edge == 128)
         go(std::integral_constant<int, 256>{}, std::integral_constant<int, 128>{}, act, agg);
+      else if (s.H == 256)
+        go(std::integral_constant<int, 256>{}, std::integral_constant<int, 64>{}, act, agg);
       else
         go(std::integral_constant<int, 512>{}, std::integral_constant<int, 64>{}, act, agg);
     };

@@ -469,6 +469,7 @@ def test_edge_split_partitions_and_fallback(api):
 
 
 @pytest.mark.parametrize("cfg,rows,act,agg", [(5, 128, "relu", "message"), (5, 128, "silu", "edge"),
+                                              (5, 64, "relu", "edge"), (5, 64, "silu", "message"),
                                               (6, 64, "silu", "message"), (6, 64, "relu", "edge")])
 def test_edge_wide_forward(api, cfg, rows, act, agg):
     """The wide gathered edge forward (BF16: 128-row tiles at H = 256, 64-row
