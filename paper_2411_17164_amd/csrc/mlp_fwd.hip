@@ -867,11 +867,7 @@ void launch_edge_fwd(const Shape& s, const BatchView& b, const MlpW& w, const vo
                      void* e_out, float* m, void* z_out, void* a_out, const float* pr, const float* ps,
                      hipStream_t st) {
   if (b.n_etiles == 0) return;
-  if (edge_fwd_wide(s)) {
-    if (pr) {  // the split form has no wide tiles
-      g_config_error = 1;
-      return;
-    }
+  if (edge_fwd_wide(s) && !pr) {  // the split form runs k_edge_fwd (128-row tiles never reach it)
     auto go = [&](auto hh, auto mt, auto act, auto agg) {
       constexpr int NWW = decltype(hh)::value == 256 && decltype(mt)::value == 64 ? 4 : 8;
       k_edge_fwd_wide<decltype(hh)::value, decltype(mt)::value, decltype(act)::value, decltype(agg)::value, NWW>
