@@ -635,6 +635,23 @@ struct EdgeTilePipe {
   }
 };
 
+// Segment starts of an edge tile, in LDS: seg[rl] is the first tile-local
+// edge of receiver r0 + rl and seg[r1 - r0] = ne, so a receiver's edges are
+// [seg[rl], seg[rl + 1]) (empty for a receiver without edges).  Derived from
+// the receivers rs[0, ne) of the tile's edges (ascending, all in [r0, r1)),
+// which must be visible in LDS, so the segment sums read no CSR row
+// pointers from memory; each entry is written by exactly one thread (the
+// edge at a receiver change, or the tile's last edge for the tail).
+__device__ __forceinline__ void tile_segments(int* seg, const int* rs, int r0, int r1, int ne) {
+  const int i = threadIdx.x;
+  if (i < ne) {
+    const int c = rs[i];
+    for (int r = (i ? rs[i - 1] : r0 - 1) + 1; r <= c; ++r) seg[r - r0] = i;
+  }
+  if (i == (ne ? ne - 1 : 0))
+    for (int r = (ne ? rs[ne - 1] : r0 - 1) + 1; r <= r1; ++r) seg[r - r0] = ne;
+}
+
 // Persistent-grid tile schedule.  The workgroups of the grid are dealt
 // round-robin to the 8 XCDs (workgroup b runs on XCD b % 8); each XCD takes a
 // contiguous eighth of the tiles so that neighbouring tiles, which share

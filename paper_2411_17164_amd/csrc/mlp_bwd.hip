@@ -158,7 +158,8 @@ struct EdgeBwdLds {
   static constexpr size_t WS = FW ? (size_t)H * LDW * 2 : 0;
   static constexpr int NWS = FW == 1 ? 2 : FW == 2 ? 1 : 0;  // LDS-resident weight matrices
   static constexpr int LDF = FW ? D::LD3 * (int)sizeof(T) / 4 : D::LDF;  // FP32 staging row stride
-  static constexpr size_t bytes = XS + ZS + NWS * WS + 2 * NW * MT * 4 + 2 * MT * 4;
+  // receivers, senders, segment starts (MT + 1, padded)
+  static constexpr size_t bytes = XS + ZS + NWS * WS + 2 * NW * MT * 4 + (3 * MT + 4) * 4;
 };
 
 // ZT (BF16): z of every edge comes from the forward's tape (zt) instead of
@@ -218,11 +219,13 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
     const EdgeTileIdx cur = nx;
     const int r0 = cur.r0, r1 = cur.r1, e0 = cur.e0, ne = cur.ne;
     int* ss = rs + MT;
+    int* sg = rs + 2 * MT;
     if (threadIdx.x < MT) {
       rs[threadIdx.x] = cur.rv;
       ss[threadIdx.x] = cur.cv;
     }
     lds_sync();
+    tile_segments(sg, rs, r0, r1, ne);  // read after the next barrier
     if constexpr (ZT) {
       // z rows into zs, (fused: for dW1's e-block) e rows into the e columns
       // of xs and (SiLU) a rows into its first H columns, one batch of loads
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeBwdLds<T, H, MT, FW, NW
     const int nr = r1 - r0;
     for (int task = threadIdx.x; task < nr * (H / 4); task += 64 * NW) {
       const int rl = task / (H / 4), q = task - rl * (H / 4);
-      const int lo = b.row_ptr[r0 + rl] - e0, hi = b.row_ptr[r0 + rl + 1] - e0;
+      const int lo = sg[rl], hi = sg[rl + 1];
       float4 s = {0.f, 0.f, 0.f, 0.f};
       for (int i = lo; i < hi; ++i) {
         const float4 v = *(const float4*)(ft + i * LDF + 4 * q);

@@ -47,7 +47,8 @@ struct EdgeFwdLds {
   static constexpr size_t FS = (size_t)MT * LDFH * 4;
   static constexpr size_t XS = FS > GS ? FS : GS;
   static constexpr size_t ZS = (size_t)MT * D::LDH * sizeof(T);
-  static constexpr size_t bytes = XS + ZS + 2 * NW * MT * 4 + 2 * MT * 4;
+  // receivers, senders, segment starts (MT + 1, padded)
+  static constexpr size_t bytes = XS + ZS + 2 * NW * MT * 4 + (3 * MT + 4) * 4;
 };
 
 // z_out (or NULL): the hidden activation z = act(W1 x + b1) of every edge,
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW, SP
   float* red = (float*)(smem + XS + ZS);
   int* rs = (int*)(red + 2 * NW * MT);
   int* ss = rs + MT;
+  int* sg = rs + 2 * MT;
   const T* W1 = (const T*)w.W1;
   const T* W2 = (const T*)w.W2;
   const int n0 = wave_id() * D::CPW;
@@ -93,6 +95,7 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW, SP
       ss[threadIdx.x] = cur.cv;
     }
     lds_sync();
+    if constexpr (!SPLIT) tile_segments(sg, rs, r0, r1, ne);  // read after the next barrier
     f32x4 acc[MB][NB];
     if constexpr (SPLIT) {
       gather_tile<T, D::LDH, MT, 1, H, 64 * NW>(
@@ -230,7 +233,9 @@ __global__ __launch_bounds__(64 * NW, waves_per_simd(EdgeFwdLds<T, H, MT, NW, SP
       lds_sync();
       for (int task = threadIdx.x; task < nr * (HH / 4); task += 64 * NW) {
         const int rl = task / (HH / 4), q = task - rl * (HH / 4);
-        const int lo = b.row_ptr[r0 + rl] - e0, hi = b.row_ptr[r0 + rl + 1] - e0;
+        // (the split form reads the row pointers: the LDS starts cost it registers)
+        const int lo = SPLIT ? b.row_ptr[r0 + rl] - e0 : sg[rl];
+        const int hi = SPLIT ? b.row_ptr[r0 + rl + 1] - e0 : sg[rl + 1];
         float4 s = {0.f, 0.f, 0.f, 0.f};
         for (int i = lo; i < hi; ++i) {
           const float4 v = *(const float4*)(ft + i * LDFH + 4 * q);
