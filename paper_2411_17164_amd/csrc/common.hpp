@@ -531,6 +531,51 @@ __device__ __forceinline__ void f32_tile(int rows, bool with_b, AFn a, BFn b, Pu
   }
 }
 
+// The [h ; m] rows of a node tile (h in T, m in FP32) held in registers
+// between their loads and their stores into an LDS tile of row stride LD
+// (h at columns [0, H), m converted to T at [H, 2H), zero rows from `rows`
+// on), so that a persistent node kernel can issue the next tile's loads
+// while it computes the current one.  Same thread-to-chunk mapping as
+// global_rows_to_lds and global_f32_rows_to_lds.
+template <typename T, int H, int MT, int LD>
+struct NodeRowsPre {
+  static constexpr int EH = 16 / sizeof(T), CPH = H / EH, CPF = H / 4;
+  static constexpr int IH = MT * CPH / NTHR, IF = MT * CPF / NTHR;
+  static_assert(MT * CPH % NTHR == 0 && MT * CPF % NTHR == 0, "whole steps of the workgroup");
+  uint4 vh[IH];
+  float4 vm[IF];
+  __device__ __forceinline__ void load(const T* __restrict__ h, const float* __restrict__ m, int row0, int rows) {
+#pragma unroll
+    for (int k = 0; k < IH; ++k) {
+      const int c = (int)threadIdx.x + k * NTHR, i = c / CPH, q = c - i * CPH;
+      vh[k] = uint4{0u, 0u, 0u, 0u};
+      if (i < rows) vh[k] = *(const uint4*)(h + (size_t)(row0 + i) * H + q * EH);
+    }
+#pragma unroll
+    for (int k = 0; k < IF; ++k) {
+      const int c = (int)threadIdx.x + k * NTHR, i = c / CPF, q = c - i * CPF;
+      vm[k] = float4{0.f, 0.f, 0.f, 0.f};
+      if (i < rows) vm[k] = *(const float4*)(m + (size_t)(row0 + i) * H + 4 * q);
+    }
+  }
+  __device__ __forceinline__ void store(T* xs) const {
+#pragma unroll
+    for (int k = 0; k < IH; ++k) {
+      const int c = (int)threadIdx.x + k * NTHR, i = c / CPH, q = c - i * CPH;
+      *(uint4*)(xs + i * LD + q * EH) = vh[k];
+    }
+#pragma unroll
+    for (int k = 0; k < IF; ++k) {
+      const int c = (int)threadIdx.x + k * NTHR, i = c / CPF, q = c - i * CPF;
+      T* d = xs + i * LD + H + 4 * q;
+      d[0] = from_f<T>(vm[k].x);
+      d[1] = from_f<T>(vm[k].y);
+      d[2] = from_f<T>(vm[k].z);
+      d[3] = from_f<T>(vm[k].w);
+    }
+  }
+};
+
 // FP32 global rows of W floats converted into a T tile in LDS, zero-filling
 // rows >= rows up to MT; NTHR threads, all loads issued before the stores.
 template <typename T, int LD, int MT, int W, typename SrcFn>

@@ -500,12 +500,33 @@ __global__ __launch_bounds__(NTHR, (MT == 32 && H == 128 ? 2 : 1)) void k_node_b
     }
   }
   const int n_tiles = (n + MT - 1) / MT;
+  // fused form: the next tile's h and m rows travel in registers while this
+  // tile computes, and this tile's dh_in rows are issued at its start, so no
+  // HBM round trip waits on a tile's critical path (the unfused forms have
+  // no registers to spare)
+  constexpr bool PF = FM;
+  constexpr int CPF = H / 4, IF = PF ? MT * CPF / NTHR : 1;
+  NodeRowsPre<T, H, MT, D::LD2> pre;  // (unused by the unfused forms)
+  float4 pd[IF];
 
   TileSched sch(n_tiles);
+  if constexpr (PF)
+    if (sch.begin < sch.end) pre.load(h, m, sch.begin * MT, min(MT, n - sch.begin * MT));
   for (int t = sch.begin; t < sch.end; t += sch.step) {
     const int row0 = t * MT, nr = min(MT, n - row0);
-    global_rows_to_lds<T, D::LD2, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
-    global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
+    if constexpr (PF) {
+#pragma unroll
+      for (int k = 0; k < IF; ++k) {
+        const int c = (int)threadIdx.x + k * NTHR, i = c / CPF, q = c - i * CPF;
+        pd[k] = float4{0.f, 0.f, 0.f, 0.f};
+        if (i < nr) pd[k] = *(const float4*)(dh_in + (size_t)(row0 + i) * H + 4 * q);
+      }
+      pre.store(xs);
+      if (t + sch.step < sch.end) pre.load(h, m, (t + sch.step) * MT, min(MT, n - (t + sch.step) * MT));
+    } else {
+      global_rows_to_lds<T, D::LD2, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
+      global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
+    }
     lds_sync();
     f32x4 a[MB][NB], x[MB][NB];
     zero_acc(a);
@@ -541,7 +562,15 @@ __global__ __launch_bounds__(NTHR, (MT == 32 && H == 128 ? 2 : 1)) void k_node_b
       }
     float inv[MB][4];
     ln_normalize<MB, NB, MT, H>(x, red, eps, inv);
-    f32_rows_to_lds<H, D::LDF, MT>(ft, nr, [&](int i, int q) { return *(const float4*)(dh_in + (size_t)(row0 + i) * H + 4 * q); });
+    if constexpr (PF) {
+#pragma unroll
+      for (int k = 0; k < IF; ++k) {
+        const int c = (int)threadIdx.x + k * NTHR, i = c / CPF, q = c - i * CPF;
+        *(float4*)(ft + i * D::LDF + 4 * q) = pd[k];
+      }
+    } else {
+      f32_rows_to_lds<H, D::LDF, MT>(ft, nr, [&](int i, int q) { return *(const float4*)(dh_in + (size_t)(row0 + i) * H + 4 * q); });
+    }
     if constexpr (!FM) lds_rows_to_global<T, D::LDH>(zs, nr, H, (T*)o.z + (size_t)row0 * H, H, [](int i) { return i; });
     lds_sync();
     f32x4 g[MB][NB];

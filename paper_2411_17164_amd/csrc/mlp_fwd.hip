@@ -516,11 +516,23 @@ __global__ __launch_bounds__(NTHR, H == 128 ? 2 : 1) void k_node_fwd(int n, MlpW
   const int n0 = wave_id() * D::CPW;
   const int n_tiles = (n + MT - 1) / MT;
 
+  // H = 128: the next tile's h and m rows travel in registers while this
+  // tile computes, so their HBM round trip is off the tile's critical path
+  // (wider forms have no registers to spare)
+  constexpr bool PF = H == 128;
   TileSched sch(n_tiles);
+  NodeRowsPre<T, H, MT, D::LD2> pre;
+  if constexpr (PF)
+    if (sch.begin < sch.end) pre.load(h, m, sch.begin * MT, min(MT, n - sch.begin * MT));
   for (int t = sch.begin; t < sch.end; t += sch.step) {
     const int row0 = t * MT, nr = min(MT, n - row0);
-    global_rows_to_lds<T, D::LD2, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
-    global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
+    if constexpr (PF) {
+      pre.store(xs);
+      if (t + sch.step < sch.end) pre.load(h, m, (t + sch.step) * MT, min(MT, n - (t + sch.step) * MT));
+    } else {
+      global_rows_to_lds<T, D::LD2, MT, H>(xs, nr, 0, [&](int i) { return h + (size_t)(row0 + i) * H; });
+      global_f32_rows_to_lds<T, D::LD2, MT, H>(xs, nr, H, [&](int i) { return m + (size_t)(row0 + i) * H; });
+    }
     lds_sync();
     f32x4 acc[MB][NB];
     zero_acc(acc);
