@@ -500,11 +500,11 @@ __global__ __launch_bounds__(NTHR, (MT == 32 && H == 128 ? 2 : 1)) void k_node_b
     }
   }
   const int n_tiles = (n + MT - 1) / MT;
-  // fused form: the next tile's h and m rows travel in registers while this
-  // tile computes, and this tile's dh_in rows are issued at its start, so no
-  // HBM round trip waits on a tile's critical path (the unfused forms have
-  // no registers to spare)
-  constexpr bool PF = FM;
+  // fused form, ReLU: the next tile's h and m rows travel in registers while
+  // this tile computes, and this tile's dh_in rows are issued at its start,
+  // so no HBM round trip waits on a tile's critical path (SiLU and the
+  // unfused forms have no registers to spare: they would spill)
+  constexpr bool PF = FM && ACT == 0;
   constexpr int CPF = H / 4, IF = PF ? MT * CPF / NTHR : 1;
   NodeRowsPre<T, H, MT, D::LD2> pre;  // (unused by the unfused forms)
   float4 pd[IF];
